@@ -1,0 +1,457 @@
+/*
+ * squaresort_oracle.c -- plain CPU oracle of SquareSort (arXiv 2407.14801).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the product path.  Written for
+ * readability, not speed: every step follows the paper's order and notation
+ * (Alg. 1 SquareSort, Alg. 2 SkewTranspose, Alg. 3 NaiveSkewTranspose) with
+ * the conventions stated in squaresort_oracle.h.  No blocking, no fusion.
+ */
+#include "squaresort_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Counter-based generator.  SplitMix64 (Steele, Lea, Flood, OOPSLA 2014):
+ * the state advances by the golden gamma and the output is the variant-13
+ * finaliser.  orc_sm64(x) is the first output of a generator whose state
+ * is x.  The paper draws pivots with the C library's rand() (appendix);
+ * a counter-based draw keyed by the node gives the same distribution and
+ * does not depend on the order in which nodes run.                       */
+uint64_t orc_sm64(uint64_t state)
+{
+    uint64_t z = state + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_root_key(uint64_t seed) { return orc_sm64(seed); }
+
+uint64_t orc_child_key(uint64_t K, uint32_t phase, uint64_t i)
+{
+    return orc_sm64(K ^ orc_sm64(2 * i + phase));
+}
+
+uint64_t orc_draw_pos(uint64_t K, uint64_t t, uint64_t n)
+{
+    uint64_t u = orc_sm64(K ^ orc_sm64((1ull << 63) | t));
+    return (uint64_t)(((unsigned __int128)u * n) >> 64);
+}
+
+/* m = ceil(sqrt(n)) exactly (Alg. 1, "m = ceil(sqrt n)").  Bit-by-bit
+ * integer square root: no floating point decides m. */
+uint64_t orc_ceil_isqrt(uint64_t n)
+{
+    uint64_t r = 0;
+    for (int b = 31; b >= 0; --b) {
+        uint64_t c = r | (1ull << b);
+        if (c * c <= n) r = c;           /* c < 2^32, so c*c fits in 64 bits */
+    }
+    return r + (r * r < n ? 1 : 0);
+}
+
+/* ------------------------------------------------------------------ */
+/* simple_sort: a stable top-down merge sort by key (the paper's base case
+ * sorts small arrays directly; MergeSort is the sort it names for pivots). */
+static void merge_rec(uint64_t *k, uint32_t *v, uint64_t *tk, uint32_t *tv,
+                      uint64_t lo, uint64_t hi)
+{
+    if (hi - lo < 2) return;
+    uint64_t mid = lo + (hi - lo) / 2;
+    merge_rec(k, v, tk, tv, lo, mid);
+    merge_rec(k, v, tk, tv, mid, hi);
+    uint64_t a = lo, b = mid, o = lo;
+    while (a < mid && b < hi) {
+        if (k[b] < k[a]) { tk[o] = k[b]; if (v) tv[o] = v[b]; ++b; }
+        else             { tk[o] = k[a]; if (v) tv[o] = v[a]; ++a; }   /* ties: left first */
+        ++o;
+    }
+    while (a < mid) { tk[o] = k[a]; if (v) tv[o] = v[a]; ++a; ++o; }
+    while (b < hi)  { tk[o] = k[b]; if (v) tv[o] = v[b]; ++b; ++o; }
+    memcpy(k + lo, tk + lo, (hi - lo) * sizeof *k);
+    if (v) memcpy(v + lo, tv + lo, (hi - lo) * sizeof *v);
+}
+
+int orc_stable_sort(uint64_t n, uint64_t *keys, uint32_t *vals)
+{
+    if (n < 2) return 0;
+    uint64_t *tk = malloc(n * sizeof *tk);
+    uint32_t *tv = vals ? malloc(n * sizeof *tv) : NULL;
+    if (!tk || (vals && !tv)) { free(tk); free(tv); return -2; }
+    merge_rec(keys, vals, tk, tv, 0, n);
+    free(tk);
+    free(tv);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Bucket rule.  "x goes to bucket t or earlier" is x <= s_t for a plain
+ * pivot and x < s_t for a strict one (a pivot followed by an equal pivot).
+ * bucket(x) counts the pivots x is NOT at-or-below. */
+static int le_pivot(uint64_t x, uint64_t s, uint8_t strict)
+{
+    return strict ? (x < s) : (x <= s);
+}
+
+uint64_t orc_bucket_of(uint64_t x, const uint64_t *s, const uint8_t *strict, uint64_t npiv)
+{
+    uint64_t b = 0;
+    for (uint64_t t = 0; t < npiv; ++t)          /* plain count, no search */
+        if (!le_pivot(x, s[t], strict[t])) ++b;
+    return b;
+}
+
+/* ------------------------------------------------------------------ */
+/* Alg. 3 NaiveSkewTranspose: for each bucket i, for each column j, move
+ * elements while the column is not exhausted and its head is <= pivot i.
+ * Cursors col[], buc[] advance (passed by reference in the paper).
+ * Pivot index k_hi-1 == npiv means +infinity (the sentinel pivots[m]).   */
+typedef struct {
+    const uint64_t *sk; const uint32_t *sv;   /* source */
+    uint64_t *dk; uint32_t *dv;               /* destination */
+    const uint64_t *piv; const uint8_t *strict; uint64_t npiv;
+    uint64_t *col, *col_end, *buc;            /* cursors, indexed globally */
+    uint32_t threshold;
+} skew_ctx;
+
+static void naive_skew(skew_ctx *c, uint64_t c_lo, uint64_t c_hi, uint64_t b_lo, uint64_t b_hi)
+{
+    for (uint64_t i = b_lo; i < b_hi; ++i)
+        for (uint64_t j = c_lo; j < c_hi; ++j)
+            while (c->col[j] < c->col_end[j] &&
+                   (i == c->npiv || le_pivot(c->sk[c->col[j]], c->piv[i], c->strict[i]))) {
+                c->dk[c->buc[i]] = c->sk[c->col[j]];
+                if (c->dv) c->dv[c->buc[i]] = c->sv[c->col[j]];
+                c->buc[i]++;
+                c->col[j]++;
+            }
+}
+
+/* Alg. 2 SkewTranspose: four recursive calls on halves of the columns and
+ * of the pivots, in the order (cols 1st, piv 1st), (cols 2nd, piv 1st),
+ * (cols 1st, piv 2nd), (cols 2nd, piv 2nd); naive below the threshold
+ * (the paper's Alg. 2 uses 4, its experiments 10), returning after it.  */
+static void rec_skew(skew_ctx *c, uint64_t c_lo, uint64_t c_hi, uint64_t b_lo, uint64_t b_hi)
+{
+    uint64_t l = c_hi - c_lo, k = b_hi - b_lo;
+    if (l < c->threshold || k < c->threshold) { naive_skew(c, c_lo, c_hi, b_lo, b_hi); return; }
+    uint64_t l2 = l / 2, k2 = k / 2;
+    rec_skew(c, c_lo,      c_lo + l2, b_lo,      b_lo + k2);
+    rec_skew(c, c_lo + l2, c_hi,      b_lo,      b_lo + k2);
+    rec_skew(c, c_lo,      c_lo + l2, b_lo + k2, b_hi);
+    rec_skew(c, c_lo + l2, c_hi,      b_lo + k2, b_hi);
+}
+
+/* Bucket sizes and bucket positions (Section 2.2): scan every element,
+ * count its bucket, then an exclusive prefix sum gives the first slot of
+ * every bucket.  bs has m+1 entries; bs[m] = n.                           */
+static void bucket_positions(uint64_t n, const uint64_t *keys, const uint64_t *piv,
+                             const uint8_t *strict, uint64_t m, uint64_t *bs)
+{
+    memset(bs, 0, (m + 1) * sizeof *bs);
+    for (uint64_t r = 0; r < n; ++r) {
+        /* binary search for the number of pivots x is not at-or-below;
+         * the predicate is monotone in t for sorted pivots with strict runs */
+        uint64_t lo = 0, hi = m - 1;
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo) / 2;
+            if (le_pivot(keys[r], piv[mid], strict[mid])) hi = mid; else lo = mid + 1;
+        }
+        bs[lo + 1]++;
+    }
+    for (uint64_t j = 1; j <= m; ++j) bs[j] += bs[j - 1];
+}
+
+static int skew_transpose_node(uint64_t n, uint64_t m,
+                               const uint64_t *sk, const uint32_t *sv,
+                               uint64_t *dk, uint32_t *dv,
+                               const uint64_t *piv, const uint8_t *strict,
+                               uint64_t *bs, uint32_t threshold)
+{
+    uint64_t *col = malloc(m * sizeof *col), *col_end = malloc(m * sizeof *col_end);
+    uint64_t *buc = malloc(m * sizeof *buc);
+    if (!col || !col_end || !buc) { free(col); free(col_end); free(buc); return -2; }
+    for (uint64_t i = 0; i < m; ++i) {            /* column spans, Alg. 1 */
+        col[i] = (i * m < n) ? i * m : n;
+        col_end[i] = ((i + 1) * m < n) ? (i + 1) * m : n;
+    }
+    bucket_positions(n, sk, piv, strict, m, bs);
+    for (uint64_t j = 0; j < m; ++j) buc[j] = bs[j];
+    skew_ctx c = { sk, sv, dk, dv, piv, strict, m - 1, col, col_end, buc, threshold };
+    if (threshold == 0) naive_skew(&c, 0, m, 0, m);
+    else rec_skew(&c, 0, m, 0, m);
+    /* after the transpose, buc[j] is the end of bucket j (the shift by one
+     * Alg. 1 notes); it must equal the start of bucket j+1 */
+    int ok = 1;
+    for (uint64_t j = 0; j < m; ++j) ok &= (buc[j] == bs[j + 1]);
+    for (uint64_t i = 0; i < m; ++i) ok &= (col[i] == col_end[i]);
+    free(col); free(col_end); free(buc);
+    return ok ? 0 : -3;
+}
+
+int orc_skew_transpose_explicit(uint64_t n,
+                                const uint64_t *src_keys, const uint32_t *src_vals,
+                                uint64_t *dst_keys, uint32_t *dst_vals,
+                                const uint64_t *pivots, const uint8_t *strict,
+                                uint64_t *bucket_start, uint32_t threshold)
+{
+    if (n < 2 || !src_keys || !dst_keys || !pivots || !strict || !bucket_start) return -1;
+    if (threshold == 1) return -1;   /* halving a single column never ends */
+    uint64_t m = orc_ceil_isqrt(n);
+    return skew_transpose_node(n, m, src_keys, src_vals, dst_keys, dst_vals,
+                               pivots, strict, bucket_start, threshold);
+}
+
+/* ------------------------------------------------------------------ */
+/* Pivot selection: m-1 samples with replacement from the node input A,
+ * sorted (MergeSort), strict flags on every pivot followed by an equal one.
+ * The paper's Alg. 1 samples distinct pivots from D and resamples on a
+ * repeat; its C code samples independently and tolerates repeats.  The
+ * multiset of D equals that of A, so positions drawn uniformly from A give
+ * the same distribution.                                                  */
+static int choose_pivots(uint64_t K, uint64_t n, uint64_t m, const uint64_t *a_keys,
+                         uint64_t *piv, uint8_t *strict)
+{
+    for (uint64_t t = 0; t + 1 < m; ++t) piv[t] = a_keys[orc_draw_pos(K, t, n)];
+    int rc = orc_stable_sort(m - 1, piv, NULL);
+    if (rc) return rc;
+    for (uint64_t t = 0; t + 1 < m; ++t)
+        strict[t] = (t + 2 < m && piv[t] == piv[t + 1]) ? 1 : 0;
+    return 0;
+}
+
+int orc_root_pivots(uint64_t n, const uint64_t *keys_in, uint64_t seed,
+                    uint64_t *pivots, uint8_t *strict)
+{
+    if (n < 2 || !keys_in || !pivots || !strict) return -1;
+    uint64_t m = orc_ceil_isqrt(n);
+    return choose_pivots(orc_root_key(seed), n, m, keys_in, pivots, strict);
+}
+
+/* A non-empty bucket j admits exactly one key value.  Inclusive bounds:
+ *   upper U_j = s_j (plain) or s_j - 1 (strict); U_{m-1} = +inf;
+ *   lower L_j = s_{j-1} + 1 (plain) or s_{j-1} (strict); L_0 = -inf.
+ * For a non-empty bucket neither adjustment can wrap around.              */
+static int single_value_bucket(uint64_t j, uint64_t m, const uint64_t *piv, const uint8_t *strict)
+{
+    if (j == 0 || j == m - 1) {
+        /* an unbounded side admits more than one value unless pinned at
+         * the type's end: L_0 = 0 so bucket 0 is single-valued iff U_0 = 0;
+         * U_{m-1} = max so bucket m-1 is single-valued iff L_{m-1} = max.
+         * Keys are held as u64; for u32 inputs max is 2^32-1, handled by
+         * the caller through `key_max`.                                   */
+        return -1;
+    }
+    uint64_t lo = strict[j - 1] ? piv[j - 1] : piv[j - 1] + 1;
+    uint64_t hi = strict[j] ? piv[j] - 1 : piv[j];
+    return lo == hi;
+}
+
+static int is_single_value(uint64_t j, uint64_t m, const uint64_t *piv, const uint8_t *strict,
+                           uint64_t key_max)
+{
+    int r = single_value_bucket(j, m, piv, strict);
+    if (r >= 0) return r;
+    if (m == 1) return 0;
+    if (j == 0) {                       /* [0, U_0] */
+        uint64_t hi = strict[0] ? piv[0] - 1 : piv[0];
+        return hi == 0;
+    }
+    /* j == m-1: [L_{m-1}, key_max] */
+    uint64_t lo = strict[m - 2] ? piv[m - 2] : piv[m - 2] + 1;
+    return lo == key_max;
+}
+
+/* ------------------------------------------------------------------ */
+/* Alg. 1 SquareSort(A, D, n).                                            */
+typedef struct {
+    uint64_t cutoff, key_max;
+    uint64_t digest, nodes;
+    /* tree statistics (optional) */
+    uint64_t max_depth, *node_count, *size_sum, depth_reached;
+    int err;
+} sqs_ctx;
+
+static uint64_t elem_hash_x(uint64_t key, const uint32_t *vals, uint64_t r)
+{
+    return vals ? (key ^ orc_sm64(vals[r])) : key;
+}
+
+static void squaresort_rec(sqs_ctx *g, uint64_t K, uint64_t n,
+                           uint64_t *ak, uint32_t *av, uint64_t *dk, uint32_t *dv,
+                           uint64_t depth)
+{
+    if (g->err) return;
+    if (n <= g->cutoff) {                       /* base case: sort small arrays directly */
+        memcpy(dk, ak, n * sizeof *dk);
+        if (dv) memcpy(dv, av, n * sizeof *dv);
+        int rc = orc_stable_sort(n, dk, dv);
+        if (rc) g->err = rc;
+        return;
+    }
+    if (depth + 1 > g->depth_reached) g->depth_reached = depth + 1;
+    if (g->node_count && depth < g->max_depth) {
+        g->node_count[depth]++;
+        g->size_sum[depth] += n;
+    }
+    uint64_t m = orc_ceil_isqrt(n);
+    uint64_t *piv = malloc((m - 1) * sizeof *piv);
+    uint8_t *strict = malloc(m - 1);
+    uint64_t *bs = malloc((m + 1) * sizeof *bs);
+    if (!piv || !strict || !bs) { g->err = -2; goto out; }
+
+    /* pivots come from the node input before the column children clobber it */
+    int rc = choose_pivots(K, n, m, ak, piv, strict);
+    if (rc) { g->err = rc; goto out; }
+
+    /* sort each column of A into the same position of D */
+    for (uint64_t i = 0; i < m; ++i) {
+        uint64_t lo = (i * m < n) ? i * m : n;
+        uint64_t hi = ((i + 1) * m < n) ? (i + 1) * m : n;
+        if (hi > lo)
+            squaresort_rec(g, orc_child_key(K, 0, i), hi - lo,
+                           ak + lo, av ? av + lo : NULL, dk + lo, dv ? dv + lo : NULL, depth + 1);
+    }
+    if (g->err) goto out;
+
+    /* bucket positions, then SkewTranspose D -> A (Alg. 2 with threshold 4) */
+    rc = skew_transpose_node(n, m, dk, dv, ak, av, piv, strict, bs, 4);
+    if (rc) { g->err = rc; goto out; }
+
+    /* digest of this node's post-transpose array */
+    {
+        uint64_t H = 0;
+        for (uint64_t r = 0; r < n; ++r) H += orc_sm64(elem_hash_x(ak[r], av, r) ^ orc_sm64(r));
+        g->digest += orc_sm64(K ^ H);
+        g->nodes++;
+    }
+
+    /* sort each bucket from A into D; single-value buckets are copied */
+    for (uint64_t j = 0; j < m; ++j) {
+        uint64_t lo = bs[j], hi = bs[j + 1];
+        if (hi == lo) continue;
+        if (is_single_value(j, m, piv, strict, g->key_max)) {
+            memcpy(dk + lo, ak + lo, (hi - lo) * sizeof *dk);
+            if (dv) memcpy(dv + lo, av + lo, (hi - lo) * sizeof *dv);
+        } else {
+            squaresort_rec(g, orc_child_key(K, 1, j), hi - lo,
+                           ak + lo, av ? av + lo : NULL, dk + lo, dv ? dv + lo : NULL, depth + 1);
+        }
+    }
+out:
+    free(piv); free(strict); free(bs);
+}
+
+static int run_squaresort(uint64_t n, uint64_t *ak, uint32_t *av, uint64_t *dk, uint32_t *dv,
+                          uint64_t seed, uint64_t cutoff, uint64_t key_max,
+                          uint64_t *digest, uint64_t *nodes)
+{
+    if (cutoff < 4) return -1;
+    if (n > 0 && (!ak || !dk)) return -1;
+    sqs_ctx g = { cutoff, key_max, 0, 0, 0, NULL, NULL, 0, 0 };
+    squaresort_rec(&g, orc_root_key(seed), n, ak, av, dk, dv, 0);
+    if (digest) *digest = g.digest;
+    if (nodes) *nodes = g.nodes;
+    return g.err;
+}
+
+int orc_squaresort(uint64_t n, uint64_t *keys_a, uint32_t *vals_a,
+                   uint64_t *keys_d, uint32_t *vals_d,
+                   uint64_t seed, uint64_t cutoff, uint64_t *digest, uint64_t *nodes)
+{
+    if ((vals_a == NULL) != (vals_d == NULL)) return -1;
+    return run_squaresort(n, keys_a, vals_a, keys_d, vals_d, seed, cutoff, UINT64_MAX,
+                          digest, nodes);
+}
+
+int orc_squaresort_u32(uint64_t n, const uint32_t *in, uint32_t *out,
+                       uint64_t seed, uint64_t cutoff, uint64_t *digest, uint64_t *nodes)
+{
+    if (n > 0 && (!in || !out)) return -1;
+    uint64_t *a = malloc((n ? n : 1) * sizeof *a), *d = malloc((n ? n : 1) * sizeof *d);
+    if (!a || !d) { free(a); free(d); return -2; }
+    for (uint64_t r = 0; r < n; ++r) a[r] = in[r];
+    int rc = run_squaresort(n, a, NULL, d, NULL, seed, cutoff, UINT32_MAX, digest, nodes);
+    for (uint64_t r = 0; r < n && rc == 0; ++r) out[r] = (uint32_t)d[r];
+    free(a); free(d);
+    return rc;
+}
+
+int orc_squaresort_u64(uint64_t n, const uint64_t *in, uint64_t *out,
+                       uint64_t seed, uint64_t cutoff, uint64_t *digest, uint64_t *nodes)
+{
+    if (n > 0 && (!in || !out)) return -1;
+    uint64_t *a = malloc((n ? n : 1) * sizeof *a);
+    if (!a) return -2;
+    if (n) memcpy(a, in, n * sizeof *a);
+    int rc = run_squaresort(n, a, NULL, out, NULL, seed, cutoff, UINT64_MAX, digest, nodes);
+    free(a);
+    return rc;
+}
+
+int orc_squaresort_kv(uint64_t n, const uint64_t *keys_in, const uint32_t *vals_in,
+                      uint64_t *keys_out, uint32_t *vals_out,
+                      uint64_t seed, uint64_t cutoff, uint64_t *digest, uint64_t *nodes)
+{
+    if (n > 0 && (!keys_in || !vals_in || !keys_out || !vals_out)) return -1;
+    uint64_t *ak = malloc((n ? n : 1) * sizeof *ak);
+    uint32_t *av = malloc((n ? n : 1) * sizeof *av);
+    if (!ak || !av) { free(ak); free(av); return -2; }
+    if (n) { memcpy(ak, keys_in, n * sizeof *ak); memcpy(av, vals_in, n * sizeof *av); }
+    int rc = run_squaresort(n, ak, av, keys_out, vals_out, seed, cutoff, UINT64_MAX,
+                            digest, nodes);
+    free(ak); free(av);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+int orc_root_intermediate(uint64_t n, const uint64_t *keys_in, const uint32_t *vals_in,
+                          uint64_t *keys_out, uint32_t *vals_out,
+                          uint64_t *bucket_start, uint64_t seed)
+{
+    if (n < 2 || !keys_in || !keys_out) return -1;
+    if ((vals_in == NULL) != (vals_out == NULL)) return -1;
+    uint64_t m = orc_ceil_isqrt(n);
+    uint64_t *piv = malloc((m - 1) * sizeof *piv);
+    uint8_t *strict = malloc(m - 1);
+    uint64_t *bs = malloc((m + 1) * sizeof *bs);
+    uint64_t *dk = malloc(n * sizeof *dk);
+    uint32_t *dv = vals_in ? malloc(n * sizeof *dv) : NULL;
+    int rc = -2;
+    if (!piv || !strict || !bs || !dk || (vals_in && !dv)) goto out;
+    rc = choose_pivots(orc_root_key(seed), n, m, keys_in, piv, strict);
+    if (rc) goto out;
+    /* the column children leave every column of D sorted */
+    memcpy(dk, keys_in, n * sizeof *dk);
+    if (dv) memcpy(dv, vals_in, n * sizeof *dv);
+    for (uint64_t i = 0; i < m && rc == 0; ++i) {
+        uint64_t lo = (i * m < n) ? i * m : n;
+        uint64_t hi = ((i + 1) * m < n) ? (i + 1) * m : n;
+        if (hi > lo) rc = orc_stable_sort(hi - lo, dk + lo, dv ? dv + lo : NULL);
+    }
+    if (rc) goto out;
+    rc = skew_transpose_node(n, m, dk, dv, keys_out, vals_out, piv, strict, bs, 4);
+    if (rc == 0 && bucket_start) memcpy(bucket_start, bs, (m + 1) * sizeof *bs);
+out:
+    free(piv); free(strict); free(bs); free(dk); free(dv);
+    return rc;
+}
+
+int orc_tree_stats(uint64_t n, const uint64_t *keys_in, uint64_t seed, uint64_t cutoff,
+                   uint64_t max_depth, uint64_t *node_count, uint64_t *size_sum,
+                   uint64_t *depth)
+{
+    if (cutoff < 4 || (n > 0 && !keys_in) || !node_count || !size_sum) return -1;
+    uint64_t *a = malloc((n ? n : 1) * sizeof *a), *d = malloc((n ? n : 1) * sizeof *d);
+    if (!a || !d) { free(a); free(d); return -2; }
+    if (n) memcpy(a, keys_in, n * sizeof *a);
+    memset(node_count, 0, max_depth * sizeof *node_count);
+    memset(size_sum, 0, max_depth * sizeof *size_sum);
+    sqs_ctx g = { cutoff, UINT64_MAX, 0, 0, max_depth, node_count, size_sum, 0, 0 };
+    squaresort_rec(&g, orc_root_key(seed), n, a, NULL, d, NULL, 0);
+    if (depth) *depth = g.depth_reached;
+    free(a); free(d);
+    return g.err;
+}

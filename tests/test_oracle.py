@@ -1,0 +1,300 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle is checked against things other than itself: a published
+generator test vector, brute force over every permutation of tiny inputs,
+numpy's sort (the plain definition of the final result), closed forms of
+SkewTranspose (a stable partition by bucket; a plain matrix transpose in the
+balanced case), Alg. 2 vs Alg. 3, and the paper's probabilistic bounds on
+bucket sizes and recursion shape.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2407_14801_amd import datagen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+GAMMA = 0x9E3779B97F4A7C15
+
+
+# --------------------------------------------------------------------- RNG
+def test_splitmix64_published_vector(orc):
+    vals = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    for k, want in enumerate(vals):
+        assert orc.sm64((k * GAMMA) % (1 << 64)) == want
+
+
+def test_ceil_isqrt_exact(orc):
+    for n in list(range(0, 5000)) + [2**20, 2**27, 2**28, 2**28 + 1, 2**32 - 1, 2**40 + 7,
+                                     (2**32 - 1) ** 2, 2**64 - 1]:
+        r = math.isqrt(n)
+        want = r + (r * r < n)
+        assert orc.ceil_isqrt(n) == want, n
+
+
+def test_draw_pos_range_and_uniformity(orc):
+    K = orc.root_key(1)
+    n = 97
+    counts = np.zeros(n, np.int64)
+    for t in range(20000):
+        p = orc.draw_pos(K, t, n)
+        assert 0 <= p < n
+        counts[p] += 1
+    # chi-square with 96 dof: mean 96, sd ~13.9; 200 is > 7 sd out
+    e = 20000 / n
+    chi2 = float(((counts - e) ** 2 / e).sum())
+    assert chi2 < 200, chi2
+
+
+def test_child_keys_distinct(orc):
+    K = orc.root_key(5)
+    keys = {orc.child_key(K, p, i) for p in (0, 1) for i in range(2000)}
+    assert len(keys) == 4000
+
+
+# -------------------------------------------------- brute force, tiny inputs
+@pytest.mark.parametrize("n", range(0, 9))
+def test_every_permutation_small(orc, n):
+    """Every permutation of 0..n-1 at cut-off 4 (n = 5..8 really recurse, m = 3)."""
+    want = np.arange(n, dtype=np.uint32)
+    for perm in itertools.permutations(range(n)):
+        x = np.array(perm, dtype=np.uint32)
+        for seed in (1, 2):
+            out = orc.squaresort_u32(x, seed, 4)
+            assert np.array_equal(out, want), (perm, seed)
+
+
+def test_every_multiset_permutation(orc):
+    base = [3, 1, 1, 2, 2, 3, 3, 4]
+    want = np.array(sorted(base), dtype=np.uint32)
+    for perm in set(itertools.permutations(base)):
+        x = np.array(perm, dtype=np.uint32)
+        assert np.array_equal(orc.squaresort_u32(x, 7, 4), want)
+
+
+def test_every_permutation_kv_stable(orc):
+    """Key/value output is ordered by (key, original index) on all permutations."""
+    keys = [2, 0, 1, 0, 2, 1, 0]
+    for perm in set(itertools.permutations(keys)):
+        k = np.array(perm, dtype=np.uint64)
+        v = np.arange(len(perm), dtype=np.uint32)
+        ko, vo = orc.squaresort_kv(k, v, 3, 4)
+        order = sorted(range(len(perm)), key=lambda i: (perm[i], i))
+        assert list(vo) == order
+        assert list(ko) == [perm[i] for i in order]
+
+
+# ----------------------------------------------- random sizes vs numpy sort
+SIZES = [0, 1, 2, 3, 4, 5, 15, 16, 17, 63, 64, 65, 99, 100, 101, 255, 256, 257,
+         1023, 1024, 1025, 4095, 4096, 4097, 10000, 65535, 65536]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("cutoff", [4, 64])
+def test_u32_matches_numpy(orc, n, cutoff):
+    x = datagen.uniform_u32(n, seed=n + 11)
+    assert np.array_equal(orc.squaresort_u32(x, 1, cutoff), np.sort(x))
+
+
+@pytest.mark.parametrize("kind", ["perm", "binary", "uniform_n", "uniform_sqrt"])
+@pytest.mark.parametrize("n", [1000, 4097, 30000])
+def test_paper_distributions(orc, kind, n):
+    x = datagen.paper_u32(kind, n, seed=3)
+    assert np.array_equal(orc.squaresort_u32(x, 9, 16), np.sort(x))
+
+
+def test_u64_random_and_extremes(orc):
+    x = datagen.uniform_u64(50000, seed=4)
+    x[:50] = 0
+    x[50:100] = np.uint64(2**64 - 1)
+    assert np.array_equal(orc.squaresort_u64(x, 2, 16), np.sort(x))
+
+
+def test_u32_extremes_and_degenerate(orc):
+    n = 5000
+    cases = [
+        np.full(n, 7, np.uint32),
+        np.full(n, 0, np.uint32),
+        np.full(n, 2**32 - 1, np.uint32),
+        np.arange(n, dtype=np.uint32),
+        np.arange(n, dtype=np.uint32)[::-1].copy(),
+        np.concatenate([np.arange(n // 2), np.arange(n - n // 2)[::-1]]).astype(np.uint32),
+        np.where(np.arange(n) % 2 == 0, 0, 2**32 - 1).astype(np.uint32),
+    ]
+    for x in cases:
+        assert np.array_equal(orc.squaresort_u32(x, 1, 4), np.sort(x))
+
+
+def test_kv_mixture_stable(orc):
+    k, v = datagen.kv_mixture(40000, seed=4)
+    ko, vo = orc.squaresort_kv(k, v, 1, 64)
+    order = np.argsort(k, kind="stable")
+    assert np.array_equal(ko, k[order])
+    assert np.array_equal(vo, v[order])
+
+
+def test_bad_cutoff_rejected(orc):
+    with pytest.raises(RuntimeError):
+        orc.squaresort_u32(np.arange(10, dtype=np.uint32), 1, 3)
+
+
+# ------------------------------------------------- SkewTranspose closed forms
+def _strict_flags(piv):
+    s = np.zeros(piv.size, np.uint8)
+    s[:-1] = piv[:-1] == piv[1:]
+    return s
+
+
+def _buckets_closed_form(x, piv, strict):
+    """bucket(x) = #{t: s_t < x} + #{t: s_t = x and strict_t}, via searchsorted."""
+    lo = np.searchsorted(piv, x, side="left")
+    hi = np.searchsorted(piv, x, side="right")
+    cstrict = np.concatenate([[0], np.cumsum(strict.astype(np.int64))])
+    return lo + (cstrict[hi] - cstrict[lo])
+
+
+def _sorted_columns(x, m):
+    d = x.copy()
+    for i in range(m):
+        lo, hi = min(i * m, x.size), min((i + 1) * m, x.size)
+        d[lo:hi] = np.sort(d[lo:hi], kind="stable")
+    return d
+
+
+@pytest.mark.parametrize("n", [4, 5, 17, 100, 1000, 1025, 4096, 9999])
+@pytest.mark.parametrize("dup", [False, True])
+@pytest.mark.parametrize("threshold", [0, 2, 4, 10])
+def test_skew_transpose_is_stable_partition(orc, n, dup, threshold):
+    g = np.random.default_rng(n * 3 + dup)
+    m = orc.ceil_isqrt(n)
+    hi = 20 if dup else 2**40
+    x = g.integers(0, hi, size=n, dtype=np.uint64)
+    d = _sorted_columns(x, m)
+    piv = np.sort(g.choice(x, size=m - 1, replace=True))
+    st = _strict_flags(piv)
+    out, bs = orc.skew_transpose_explicit(d, piv, st, threshold=threshold)
+    b = _buckets_closed_form(d, piv, st)
+    order = np.argsort(b, kind="stable")
+    assert np.array_equal(out, d[order])
+    counts = np.bincount(b, minlength=m)
+    assert np.array_equal(bs, np.concatenate([[0], np.cumsum(counts)]).astype(np.uint64))
+
+
+def test_distinct_pivots_follow_le_rule(orc):
+    """With distinct pivots bucket j is (s_{j-1}, s_j] (the <= test of Alg. 3)."""
+    g = np.random.default_rng(0)
+    piv = np.sort(g.choice(1000, size=30, replace=False)).astype(np.uint64)
+    st = _strict_flags(piv)
+    assert st.sum() == 0
+    for x in range(0, 1002):
+        assert orc.bucket_of(x, piv, st) == int(np.searchsorted(piv, x, side="left"))
+
+
+def test_balanced_case_is_matrix_transpose(orc):
+    """Each sorted column holds exactly one key of each bucket: the skew
+    transposition is the ordinary transpose (Section 2, overview)."""
+    m = 37
+    n = m * m
+    d = np.empty(n, np.uint64)
+    for i in range(m):                       # column i = {j*m + i : j}
+        d[i * m:(i + 1) * m] = np.arange(m, dtype=np.uint64) * m + i
+    piv = (np.arange(m - 1, dtype=np.uint64) * m + (m - 1))   # s_j = j*m + m-1
+    st = _strict_flags(piv)
+    for thr in (0, 4, 10):
+        out, bs = orc.skew_transpose_explicit(d, piv, st, threshold=thr)
+        want = d.reshape(m, m).T.reshape(-1)
+        assert np.array_equal(out, want)
+        assert np.array_equal(bs, np.arange(m + 1, dtype=np.uint64) * m)
+
+
+def test_root_intermediate_buckets_hold_their_range(orc):
+    x = datagen.uniform_u32(65536 + 123, seed=5).astype(np.uint64)
+    out, bs = orc.root_intermediate(x, seed=1)
+    piv, st = orc.root_pivots(x, seed=1)
+    m = orc.ceil_isqrt(x.size)
+    assert bs[0] == 0 and bs[-1] == x.size and np.all(np.diff(bs.astype(np.int64)) >= 0)
+    assert np.array_equal(np.sort(out), np.sort(x))              # a bijection
+    b = _buckets_closed_form(out, piv, st)
+    want_b = np.repeat(np.arange(m), np.diff(bs.astype(np.int64)))
+    assert np.array_equal(b, want_b)
+    # pivots are samples of the input, sorted
+    assert np.all(np.diff(piv.astype(np.float64)) >= 0)
+    assert np.isin(piv, x).all()
+
+
+def test_root_intermediate_kv_layout(orc):
+    k, v = datagen.kv_mixture(20000, seed=6)
+    ko, vo, bs = orc.root_intermediate(k, seed=3, vals=v)
+    m = orc.ceil_isqrt(k.size)
+    # columns sorted stably, then partitioned stably by bucket
+    d_order = np.concatenate([lo + np.argsort(k[lo:hi], kind="stable")
+                              for lo, hi in ((min(i * m, k.size), min((i + 1) * m, k.size))
+                                             for i in range(m)) if hi > lo])
+    dk, dv = k[d_order], v[d_order]
+    piv, st = orc.root_pivots(k, seed=3)
+    b = _buckets_closed_form(dk, piv, st)
+    order = np.argsort(b, kind="stable")
+    assert np.array_equal(ko, dk[order]) and np.array_equal(vo, dv[order])
+
+
+# ------------------------------------------------- single-value buckets, digest
+def test_all_equal_tree_by_hand(orc):
+    """n=100 equal keys, C=4: the root (m=10) sends every key to the
+    single-value bucket at the end of the run of equal pivots and copies it;
+    each of its 10 columns (10 keys, m=4) does the same; their columns hold
+    <= 4 keys (base).  So there are exactly 11 internal nodes."""
+    x = np.full(100, 7, np.uint32)
+    out, dg, nodes = orc.squaresort_u32(x, 1, 4, want_digest=True)
+    assert np.array_equal(out, x)
+    assert nodes == 11
+
+
+def test_digest_deterministic_and_seed_dependent(orc):
+    x = datagen.uniform_u32(1 << 16, seed=1)
+    a = orc.squaresort_u32(x, 1, 64, want_digest=True)
+    b = orc.squaresort_u32(x, 1, 64, want_digest=True)
+    c = orc.squaresort_u32(x, 2, 64, want_digest=True)
+    assert a[1] == b[1] and a[2] == b[2]
+    assert a[1] != c[1]
+    assert np.array_equal(a[0], c[0])
+
+
+# --------------------------------------------- the paper's probabilistic bounds
+def _root_bucket_sizes(orc, n, seed):
+    x = (np.random.default_rng(seed).permutation(n) + 1).astype(np.uint64)   # distinct keys
+    _, bs = orc.root_intermediate(x, seed=seed)
+    return np.diff(bs.astype(np.int64))
+
+
+def test_bucket_size_tails(orc):
+    """Upper tail Pr[n_i >= t sqrt n] <= e^{-0.9t+0.1} and lower tail
+    Pr[n_1 <= s] <= e^2 s / sqrt n (Section 3.2 propositions), and
+    E[sum n_i log n_i] <= n log n / 2 + 4 e n (Section 3.2 lemma)."""
+    n = 10000
+    sizes = [_root_bucket_sizes(orc, n, s) for s in range(1, 81)]
+    allsz = np.concatenate(sizes)
+    for t in (1, 2, 3, 4):
+        freq = float(np.mean(allsz >= t * math.sqrt(n)))
+        assert freq <= math.exp(-0.9 * t + 0.1) + 0.01, (t, freq)
+    first = np.array([s[0] for s in sizes])
+    for s in (2, 10, 30):
+        assert float(np.mean(first <= s)) <= math.e ** 2 * s / math.sqrt(n) + 0.05
+    ent = [float(np.sum(s[s > 0] * np.log2(s[s > 0]))) for s in sizes]
+    assert np.mean(ent) <= 0.5 * n * math.log2(n) + 4 * math.e * n
+    for s in sizes:
+        assert s.sum() == n
+
+
+def test_tree_shape_doubles_per_level(orc):
+    """The total size of the nodes at depth d is at most 2^d n (Section 3.4)."""
+    n = 1 << 16
+    x = datagen.uniform_u32(n, seed=2).astype(np.uint64)
+    cnt, ssum, depth = orc.tree_stats(x, seed=1, cutoff=16)
+    assert cnt[0] == 1 and ssum[0] == n
+    for d in range(depth):
+        assert ssum[d] <= (2 ** d) * n
+    assert 2 <= depth <= 8
