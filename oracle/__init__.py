@@ -47,6 +47,7 @@ def _load():
         "orc_skew_transpose_explicit": (ctypes.c_int, [u64, vp, vp, vp, vp, vp, vp, vp, u32]),
         "orc_root_intermediate": (ctypes.c_int, [u64, vp, vp, vp, vp, vp, u64]),
         "orc_tree_stats": (ctypes.c_int, [u64, vp, u64, u64, u64, vp, vp, vp]),
+        "orc_root_buckets": (ctypes.c_int, [u64, vp, u64, u64, vp, vp, vp]),
         "orc_stable_sort": (ctypes.c_int, [u64, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -182,3 +183,18 @@ def tree_stats(keys, seed, cutoff, max_depth=16):
     _check(_load().orc_tree_stats(k.size, _p(k), seed, cutoff, max_depth, _p(cnt), _p(ssum),
                                   ctypes.addressof(depth)), "tree_stats")
     return cnt, ssum, depth.value
+
+
+def root_buckets(keys, seed, sel):
+    """Bounds and keys of selected buckets of the root intermediate, without
+    building the whole intermediate.  Returns (sel, bounds[nsel, 2], keys)."""
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    sel = np.ascontiguousarray(np.sort(np.unique(sel)), dtype=np.uint64)
+    bounds = np.empty((sel.size, 2), np.uint64)
+    _check(_load().orc_root_buckets(k.size, _p(k), seed, sel.size, _p(sel), _p(bounds), None),
+           "root_buckets")
+    total = int((bounds[:, 1] - bounds[:, 0]).sum())
+    out = np.empty(max(total, 1), np.uint64)
+    _check(_load().orc_root_buckets(k.size, _p(k), seed, sel.size, _p(sel), _p(bounds), _p(out)),
+           "root_buckets")
+    return sel, bounds, out[:total]

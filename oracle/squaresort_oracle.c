@@ -455,3 +455,63 @@ int orc_tree_stats(uint64_t n, const uint64_t *keys_in, uint64_t seed, uint64_t 
     free(a); free(d);
     return g.err;
 }
+
+/* ------------------------------------------------------------------ */
+/* Selected buckets of the root intermediate, computed one bucket set at a
+ * time for sizes where the whole intermediate is too slow to build: every
+ * bucket j is, column by column, the column's keys of bucket j in sorted
+ * order (the SkewTranspose layout).  Writes all m+1 bucket bounds and, for
+ * the nsel requested buckets (ascending), their keys back to back.        */
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+int orc_root_buckets(uint64_t n, const uint64_t *keys_in, uint64_t seed,
+                     uint64_t nsel, const uint64_t *sel, uint64_t *sel_bounds,
+                     uint64_t *sel_keys_out)
+{
+    if (n < 2 || !keys_in || !sel || !sel_bounds) return -1;
+    uint64_t m = orc_ceil_isqrt(n);
+    for (uint64_t s2 = 0; s2 < nsel; ++s2) if (sel[s2] >= m) return -1;
+    uint64_t *piv = malloc((m - 1) * sizeof *piv);
+    uint8_t *strict = malloc(m - 1);
+    int rc = -2;
+    if (!piv || !strict) goto out;
+    rc = choose_pivots(orc_root_key(seed), n, m, keys_in, piv, strict);
+    if (rc) goto out;
+    uint64_t at = 0;
+    for (uint64_t s2 = 0; s2 < nsel; ++s2) {
+        uint64_t j = sel[s2];
+        /* x is in bucket j iff it is at-or-below pivot j (or j is the last
+         * bucket) and not at-or-below pivot j-1 (or j is the first) */
+        uint64_t below = 0, count = 0;
+        for (uint64_t r = 0; r < n; ++r) {
+            uint64_t x = keys_in[r];
+            int after_prev = (j == 0) || !le_pivot(x, piv[j - 1], strict[j - 1]);
+            int upto_this = (j == m - 1) || le_pivot(x, piv[j], strict[j]);
+            if (!after_prev) ++below;
+            else if (upto_this) ++count;
+        }
+        sel_bounds[2 * s2] = below;
+        sel_bounds[2 * s2 + 1] = below + count;
+        if (!sel_keys_out) continue;
+        /* the bucket's keys, column by column, sorted within a column */
+        for (uint64_t i = 0; i < m; ++i) {
+            uint64_t lo = (i * m < n) ? i * m : n, hi = ((i + 1) * m < n) ? (i + 1) * m : n;
+            uint64_t first = at;
+            for (uint64_t r = lo; r < hi; ++r) {
+                uint64_t x = keys_in[r];
+                if ((j == 0 || !le_pivot(x, piv[j - 1], strict[j - 1])) &&
+                    (j == m - 1 || le_pivot(x, piv[j], strict[j])))
+                    sel_keys_out[at++] = x;
+            }
+            qsort(sel_keys_out + first, at - first, sizeof *sel_keys_out, cmp_u64);
+        }
+    }
+    rc = 0;
+out:
+    free(piv); free(strict);
+    return rc;
+}

@@ -98,6 +98,15 @@ int orc_root_intermediate(uint64_t n, const uint64_t *keys_in, const uint32_t *v
                           uint64_t *keys_out, uint32_t *vals_out,
                           uint64_t *bucket_start, uint64_t seed);
 
+/* ---- selected buckets of the root intermediate, for sizes where the
+ * whole intermediate is too slow to build: for each j = sel[s], the bounds
+ * [bucket_start[j], bucket_start[j+1]) into sel_bounds[2s], sel_bounds[2s+1]
+ * and, if sel_keys_out is not NULL, the bucket's keys back to back in the
+ * SkewTranspose layout (column by column, sorted within a column). */
+int orc_root_buckets(uint64_t n, const uint64_t *keys_in, uint64_t seed,
+                     uint64_t nsel, const uint64_t *sel, uint64_t *sel_bounds,
+                     uint64_t *sel_keys_out);
+
 /* ---- recursion-tree statistics (for the tree-shape checks): for each
  * depth d < max_depth, the number of internal nodes and the sum of their
  * sizes; returns the depth reached via *depth. */

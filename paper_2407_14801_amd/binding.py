@@ -1,0 +1,163 @@
+"""Thin ctypes binding of libsquaresort (include/squaresort.h).
+
+Argument marshalling only: device pointers and the current HIP stream are
+taken from torch tensors; every step of the sort runs in the HIP library.
+Importing this module raises if the library has not been built -- there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsquaresort.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libsquaresort.so not found at {LIB_PATH}; run paper_2407_14801_amd/build.py")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+KIND_U32, KIND_U64, KIND_KV = 0, 1, 2
+FLAG_DIGEST = 1
+STATUS = {0: "SQS_OK", -1: "SQS_ERR_ARG", -2: "SQS_ERR_ALIAS", -3: "SQS_ERR_WORKSPACE",
+          -4: "SQS_ERR_DEVICE", -6: "SQS_ERR_DEPTH", -7: "SQS_ERR_UNSUPPORTED"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("cutoff", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
+                ("digest", ctypes.c_void_p)]
+
+
+_u64, _vp, _i = ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
+_P = ctypes.POINTER(Params)
+_SIGS = {
+    "sqs_max_cutoff": (_u64, [_i]),
+    "sqs_max_n": (_u64, [_i]),
+    "squaresort_workspace_bytes": (_u64, [_u64, _i, _u64]),
+    "squaresort_u32": (_i, [_u64, _vp, _vp, _u64, _P, _vp]),
+    "squaresort_u64": (_i, [_u64, _vp, _vp, _u64, _P, _vp]),
+    "squaresort_kv": (_i, [_u64, _vp, _vp, _vp, _vp, _u64, _P, _vp]),
+    "skew_transpose_u32": (_i, [_u64, _vp, _vp, _vp, _u64, _P, _vp]),
+    "sqs_status_string": (ctypes.c_char_p, [_i]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class SquareSortError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({_lib.sqs_status_string(status).decode()})")
+        self.status = status
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise SquareSortError(status, what)
+
+
+def max_cutoff(kind: int) -> int:
+    return _lib.sqs_max_cutoff(kind)
+
+
+def max_n(kind: int) -> int:
+    return _lib.sqs_max_n(kind)
+
+
+def workspace_bytes(n: int, kind: int, cutoff: int = 0) -> int:
+    return _lib.squaresort_workspace_bytes(n, kind, cutoff)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Workspace:
+    """Caller-owned device workspace, grown on demand (allocation happens
+    here, outside the library)."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def _params(n, kind, cutoff, ws, digest):
+    nbytes = workspace_bytes(n, kind, cutoff)
+    buf = (ws or Workspace()).get(nbytes) if n > 0 else None
+    p = Params()
+    p.cutoff = cutoff
+    p.flags = FLAG_DIGEST if digest is not None else 0
+    p.workspace = None if buf is None else buf.data_ptr()
+    p.workspace_bytes = 0 if buf is None else buf.numel()
+    p.digest = None if digest is None else digest.data_ptr()
+    return p, buf
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("tensors must be contiguous device tensors")
+
+
+def squaresort_u32(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: int = 0,
+                   ws: Workspace | None = None, digest: torch.Tensor | None = None) -> int:
+    """Sort inp (uint32 bits in an int32 tensor; clobbered) into out.  Returns
+    the cut-off used."""
+    _check_dev(inp, out)
+    assert inp.dtype == torch.int32 and out.dtype == torch.int32 and inp.numel() == out.numel()
+    n = inp.numel()
+    p, _keep = _params(n, KIND_U32, cutoff, ws, digest)
+    _check(_lib.squaresort_u32(n, _ptr(inp), _ptr(out), seed, ctypes.byref(p), _stream(inp.device)),
+           "squaresort_u32")
+    return p.cutoff
+
+
+def squaresort_u64(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: int = 0,
+                   ws: Workspace | None = None, digest: torch.Tensor | None = None) -> int:
+    _check_dev(inp, out)
+    assert inp.dtype == torch.int64 and out.dtype == torch.int64 and inp.numel() == out.numel()
+    n = inp.numel()
+    p, _keep = _params(n, KIND_U64, cutoff, ws, digest)
+    _check(_lib.squaresort_u64(n, _ptr(inp), _ptr(out), seed, ctypes.byref(p), _stream(inp.device)),
+           "squaresort_u64")
+    return p.cutoff
+
+
+def squaresort_kv(keys_in, vals_in, keys_out, vals_out, seed: int = 1, cutoff: int = 0,
+                  ws: Workspace | None = None, digest: torch.Tensor | None = None) -> int:
+    _check_dev(keys_in, vals_in, keys_out, vals_out)
+    assert keys_in.dtype == torch.int64 and vals_in.dtype == torch.int32
+    n = keys_in.numel()
+    p, _keep = _params(n, KIND_KV, cutoff, ws, digest)
+    _check(_lib.squaresort_kv(n, _ptr(keys_in), _ptr(vals_in), _ptr(keys_out), _ptr(vals_out), seed,
+                              ctypes.byref(p), _stream(keys_in.device)), "squaresort_kv")
+    return p.cutoff
+
+
+def skew_transpose_u32(inp: torch.Tensor, out: torch.Tensor, bucket_start: torch.Tensor | None = None,
+                       seed: int = 1, ws: Workspace | None = None) -> None:
+    """Root step up to SkewTranspose: columns of inp sorted in place, pivots
+    drawn from the original inp, skew-transposed result in out."""
+    _check_dev(inp, out)
+    n = inp.numel()
+    p, _keep = _params(n, KIND_U32, 0, ws, None)
+    _check(_lib.skew_transpose_u32(n, _ptr(inp), _ptr(out), _ptr(bucket_start), seed, ctypes.byref(p),
+                                   _stream(inp.device)), "skew_transpose_u32")
+
+
+# raw entry points for tests that exercise the C ABI directly
+lib = _lib

@@ -1,0 +1,393 @@
+// squaresort.hip -- libsquaresort: the C ABI (include/squaresort.h) and the
+// host engine that drives SquareSort's recursion (Alg. 1, arXiv 2407.14801)
+// on one MI355X.
+//
+// Recursion is breadth-wise: all internal nodes produced by one step form a
+// batch that the kernels of sqs_kernels.hpp process together, so a step costs
+// a fixed number of launches however many nodes it holds.  Column children
+// that are internal themselves (m > cutoff) are processed as a nested batch
+// before their parent's counting; bucket children that are internal form the
+// next batch once the bucket sizes of the current one are known on the host
+// (one small device-to-host copy per step).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/squaresort.h"
+#include "sqs_kernels.hpp"
+
+namespace sqs {
+namespace {
+
+// ------------------------------------------------------------ host helpers
+uint64_t ceil_isqrt_host(uint64_t n)
+{
+    uint64_t r = 0;
+    for (int b = 31; b >= 0; --b) {
+        const uint64_t c = r | (1ull << b);
+        if (c * c <= n) r = c;
+    }
+    return r + (r * r < n ? 1 : 0);
+}
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+struct HostNode {
+    uint64_t off;
+    uint32_t n;
+    uint64_t key;
+};
+
+// Bump allocator over the caller's workspace (stack discipline).
+struct Workspace {
+    char *base = nullptr;
+    uint64_t size = 0, top = 0;
+    bool overflow = false;
+    template <class T> T *take(uint64_t count)
+    {
+        const uint64_t at = align_up(top, 256);
+        const uint64_t bytes = align_up(count * sizeof(T), 256);
+        if (at + bytes > size) { overflow = true; return nullptr; }
+        top = at + bytes;
+        return reinterpret_cast<T *>(base + at);
+    }
+};
+
+// Per-batch metadata bytes for one node of size n (as laid out in run_batch).
+uint64_t node_meta_bytes(uint64_t n, uint64_t key_bytes)
+{
+    const uint64_t m = ceil_isqrt_host(n);
+    const uint64_t groups = cdiv(m, TG), nJ = cdiv(m, TB);
+    return sizeof(NodeDesc) + 5 * 4 + (m - 1) * (key_bytes + 1) + 4 * m * (nJ + 1) +
+           4 * groups * m + 4 * (m + 1) + 4 * m + m + 8;
+}
+
+// Upper bound of the metadata of one batch whose nodes are disjoint ranges of
+// total size <= S, each node larger than the cut-off C.
+uint64_t batch_bound(uint64_t S, uint64_t C, uint64_t key_bytes)
+{
+    if (S <= C) return 0;
+    // the largest single node dominates the quadratic terms; the linear
+    // terms are bounded by the count of nodes (< S / C) times a node of
+    // size C+1 and by S / sqrt(C) for the m-proportional parts.
+    const uint64_t big = node_meta_bytes(S, key_bytes);
+    const uint64_t nodes = S / (C + 1) + 1;
+    const uint64_t sq = ceil_isqrt_host(C + 1);
+    const uint64_t per_m = key_bytes + 1 + 4 * 2 + 4 + 4 + 4 + 1 + 8;   // generous
+    return big + nodes * (sizeof(NodeDesc) + 64 + 4 * per_m) + (S / sq + nodes) * per_m * 2 +
+           S / 8 + 16 * 256;
+}
+
+uint64_t workspace_bound(uint64_t n, uint64_t C, uint64_t key_bytes)
+{
+    // n <= C needs no batch; the skew-transpose entry point still runs the
+    // root step, so cover one node of n keys
+    if (n <= C) return node_meta_bytes(std::max<uint64_t>(n, 2), key_bytes) + (64 << 10);
+    // nested batches: a chain of column recursions, each at most the size of n
+    uint64_t chain = 1;
+    for (uint64_t s = ceil_isqrt_host(n); s > C && chain < 8; s = ceil_isqrt_host(s)) ++chain;
+    return chain * batch_bound(n, C, key_bytes) + (1 << 20);
+}
+
+// ------------------------------------------------------------ engine
+template <class K, bool HV> struct Engine {
+    K *A;
+    uint32_t *VA;
+    K *D;
+    uint32_t *VD;
+    uint32_t cutoff;
+    hipStream_t st;
+    Workspace ws;
+    bool digest;
+    unsigned long long *digest_ptr;
+    // skew-transpose mode: only the root's columns and transpose, columns
+    // sorted in place in A, transpose A -> out
+    bool skew_only = false;
+    K *skew_out = nullptr;
+    unsigned long long *skew_bs = nullptr;
+
+    int check() const { return hipGetLastError() == hipSuccess ? SQS_OK : SQS_ERR_DEVICE; }
+
+    int run_batch(const std::vector<HostNode> &nodes, int depth)
+    {
+        if (depth >= SQS_MAX_DEPTH) return SQS_ERR_DEPTH;
+        const uint32_t N = (uint32_t)nodes.size();
+        const uint64_t mark = ws.top;
+
+        // ---- plan the batch on the host
+        std::vector<NodeDesc> desc(N);
+        std::vector<uint32_t> pfx(5 * (N + 1), 0);
+        uint32_t *pivS = &pfx[0], *grpS = &pfx[N + 1], *tileS = &pfx[2 * (N + 1)],
+                 *bucS = &pfx[3 * (N + 1)], *digS = &pfx[4 * (N + 1)];
+        uint64_t srcTot = 0, blkTot = 0;
+        uint32_t bktTot = 0;
+        std::vector<HostNode> col_kids;
+        for (uint32_t k = 0; k < N; ++k) {
+            const HostNode &h = nodes[k];
+            NodeDesc &d = desc[k];
+            d.off = h.off;
+            d.key = h.key;
+            d.n = h.n;
+            d.m = (uint32_t)ceil_isqrt_host(h.n);
+            d.groups = cdiv(d.m, TG);
+            d.nJ = cdiv(d.m, TB);
+            d.piv = pivS[k];
+            d.bkt = bktTot;
+            d.src = srcTot;
+            d.blk = blkTot;
+            d.flags = 0;
+            d.pad = 0;
+            if (d.m > (uint32_t)SORT_CAP) return SQS_ERR_UNSUPPORTED;   // a column is sorted by one work-group
+            if (!skew_only && d.m > cutoff) {
+                d.flags |= NODE_COLS_SORTED;
+                for (uint32_t i = 0; i < d.m; ++i) {
+                    const uint64_t lo = (uint64_t)i * d.m;
+                    if (lo >= h.n) break;
+                    const uint32_t len = (uint32_t)std::min<uint64_t>(d.m, h.n - lo);
+                    // a short tail column may be a base case (sorted by k_colsort)
+                    if (len > cutoff) col_kids.push_back({h.off + lo, len, node_child_key(h.key, 0, i)});
+                }
+            }
+            pivS[k + 1] = pivS[k] + (d.m - 1);
+            grpS[k + 1] = grpS[k] + d.groups;
+            tileS[k + 1] = tileS[k] + d.groups * d.nJ;
+            bucS[k + 1] = bucS[k] + d.m;
+            digS[k + 1] = digS[k] + cdiv(h.n, 16384);
+            bktTot += d.m + 1;
+            srcTot += (uint64_t)(d.nJ + 1) * d.m;
+            blkTot += (uint64_t)d.groups * d.m;
+        }
+
+        // ---- device metadata
+        Batch<K> b;
+        NodeDesc *dDesc = ws.take<NodeDesc>(N);
+        uint32_t *dPfx = ws.take<uint32_t>(5 * (N + 1));
+        b.piv = ws.take<K>(std::max<uint32_t>(pivS[N], 1));
+        b.strict = ws.take<uint8_t>(std::max<uint32_t>(pivS[N], 1));
+        b.srcOff = ws.take<uint32_t>(srcTot);
+        b.blk = ws.take<uint32_t>(blkTot);
+        b.bs = ws.take<uint32_t>(bktTot);
+        b.tot = ws.take<uint32_t>(bktTot);
+        b.cls = ws.take<uint8_t>(bktTot);
+        b.H = ws.take<unsigned long long>(N);
+        if (ws.overflow) return SQS_ERR_WORKSPACE;
+        b.nodes = dDesc;
+        b.N = N;
+        b.pivStart = dPfx;
+        b.grpStart = dPfx + (N + 1);
+        b.tileStart = dPfx + 2 * (N + 1);
+        b.bucStart = dPfx + 3 * (N + 1);
+        b.digStart = dPfx + 4 * (N + 1);
+        if (hipMemcpyAsync(dDesc, desc.data(), N * sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess)
+            return SQS_ERR_DEVICE;
+        if (hipMemcpyAsync(dPfx, pfx.data(), pfx.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+            return SQS_ERR_DEVICE;
+
+        // ---- pivots (drawn from the node inputs before any child clobbers them)
+        if (pivS[N] > 0) k_sample<K><<<cdiv(pivS[N], 256), 256, 0, st>>>(b, A);
+        k_sort_pivots<K><<<N, SORT_NT, 0, st>>>(b);
+        if (int rc = check()) return rc;
+
+        // ---- columns: internal column children first, then sort/count
+        if (!col_kids.empty()) {
+            if (int rc = run_batch(col_kids, depth + 1)) return rc;
+        }
+        K *cdst = skew_only ? A : D;
+        uint32_t *vcdst = skew_only ? VA : VD;
+        k_colsort<K, HV><<<grpS[N], SORT_NT, 0, st>>>(b, A, VA, cdst, vcdst, cutoff);
+        k_colscan<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b);
+        k_bucket_start<K><<<N, 1024, 0, st>>>(b, skew_only ? skew_bs : nullptr);
+        if (int rc = check()) return rc;
+
+        // ---- SkewTranspose D -> A (skew mode: A -> out)
+        if (skew_only) {
+            k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, A, VA, skew_out, nullptr);
+            ws.top = mark;
+            if (int rc = check()) return rc;
+            // the host-side plan must outlive its upload
+            return hipStreamSynchronize(st) == hipSuccess ? SQS_OK : SQS_ERR_DEVICE;
+        }
+        k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, D, VD, A, VA);
+        if (digest) {
+            k_fill_u64<<<cdiv(N, 256), 256, 0, st>>>(b.H, N, 0ull);
+            k_digest<K, HV><<<digS[N], 256, 0, st>>>(b, A, VA);
+            k_digest_finish<K><<<cdiv(N, 256), 256, 0, st>>>(b, digest_ptr);
+        }
+        if (int rc = check()) return rc;
+
+        // ---- buckets A -> D
+        k_bucket<K, HV><<<bucS[N], SORT_NT, 0, st>>>(b, A, VA, D, VD, cutoff);
+        if (int rc = check()) return rc;
+
+        // ---- internal buckets form the next batch
+        std::vector<uint32_t> hbs(bktTot);
+        std::vector<uint8_t> hcls(bktTot);
+        if (hipMemcpyAsync(hbs.data(), b.bs, bktTot * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(hcls.data(), b.cls, bktTot, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return SQS_ERR_DEVICE;
+        std::vector<HostNode> next;
+        for (uint32_t k = 0; k < N; ++k) {
+            const NodeDesc &d = desc[k];
+            for (uint32_t j = 0; j < d.m; ++j)
+                if (hcls[d.bkt + j] == 3) {
+                    const uint32_t lo = hbs[d.bkt + j], hi = hbs[d.bkt + j + 1];
+                    next.push_back({d.off + lo, hi - lo, node_child_key(d.key, 1, j)});
+                }
+        }
+        ws.top = mark;
+        if (!next.empty()) return run_batch(next, depth + 1);
+        return SQS_OK;
+    }
+
+    int sort_root(uint64_t n, uint64_t seed)
+    {
+        if (n == 0) return SQS_OK;
+        if (n <= cutoff) {
+            k_base_sort<K, HV><<<1, SORT_NT, 0, st>>>((uint32_t)n, A, VA, D, VD);
+            return check();
+        }
+        std::vector<HostNode> root{{0, (uint32_t)n, splitmix(seed)}};
+        return run_batch(root, 0);
+    }
+};
+
+constexpr uint64_t key_bytes_of(int kind) { return kind == SQS_KIND_U32 ? 4 : 8; }
+
+uint64_t max_cutoff_of(int kind) { return (kind >= SQS_KIND_U32 && kind <= SQS_KIND_KV) ? SORT_CAP : 0; }
+
+uint64_t max_n_of(int kind)
+{
+    if (kind < SQS_KIND_U32 || kind > SQS_KIND_KV) return 0;
+    // the root's columns (and its m-1 pivots) are sorted by one work-group each
+    const uint64_t mm = (uint64_t)SORT_CAP;
+    return std::min<uint64_t>(mm * mm, 0xFFFFFFFFull);
+}
+
+int resolve_cutoff(int kind, sqs_params *p, uint32_t *out)
+{
+    uint64_t c = p ? p->cutoff : 0;
+    if (c == 0) c = max_cutoff_of(kind);
+    if (c < 4 || c > max_cutoff_of(kind)) return SQS_ERR_ARG;
+    if (p) p->cutoff = c;
+    *out = (uint32_t)c;
+    return SQS_OK;
+}
+
+bool overlap(const void *a, uint64_t abytes, const void *b, uint64_t bbytes)
+{
+    const char *x = static_cast<const char *>(a), *y = static_cast<const char *>(b);
+    return x < y + bbytes && y < x + abytes;
+}
+
+template <class K, bool HV>
+int run_sort(uint64_t n, K *in, uint32_t *vin, K *out, uint32_t *vout, uint64_t seed, sqs_params *p,
+             void *stream, int kind)
+{
+    uint32_t C;
+    if (int rc = resolve_cutoff(kind, p, &C)) return rc;
+    if (n == 0) return SQS_OK;
+    if (!in || !out || (HV && (!vin || !vout))) return SQS_ERR_ARG;
+    if (n > max_n_of(kind)) return SQS_ERR_UNSUPPORTED;
+    if (overlap(in, n * sizeof(K), out, n * sizeof(K))) return SQS_ERR_ALIAS;
+    if (HV && (overlap(vin, n * 4, vout, n * 4) || overlap(vin, n * 4, in, n * sizeof(K)) ||
+               overlap(vin, n * 4, out, n * sizeof(K)) || overlap(vout, n * 4, in, n * sizeof(K)) ||
+               overlap(vout, n * 4, out, n * sizeof(K))))
+        return SQS_ERR_ALIAS;
+    const uint64_t need = workspace_bound(n, C, sizeof(K) + (HV ? 4 : 0));
+    if (n > C && (!p || !p->workspace || p->workspace_bytes < need)) return SQS_ERR_WORKSPACE;
+    const bool dig = p && (p->flags & SQS_FLAG_DIGEST);
+    if (dig && !p->digest) return SQS_ERR_ARG;
+    Engine<K, HV> e;
+    e.A = in; e.VA = vin; e.D = out; e.VD = vout;
+    e.cutoff = C;
+    e.st = (hipStream_t)stream;
+    e.ws.base = p ? static_cast<char *>(p->workspace) : nullptr;
+    e.ws.size = p ? p->workspace_bytes : 0;
+    e.digest = dig;
+    e.digest_ptr = dig ? reinterpret_cast<unsigned long long *>(p->digest) : nullptr;
+    return e.sort_root(n, seed);
+}
+
+}  // namespace
+}  // namespace sqs
+
+using namespace sqs;
+
+extern "C" {
+
+uint64_t sqs_max_cutoff(int kind) { return max_cutoff_of(kind); }
+uint64_t sqs_max_n(int kind) { return max_n_of(kind); }
+
+uint64_t squaresort_workspace_bytes(uint64_t n, int kind, uint64_t cutoff)
+{
+    if (kind < SQS_KIND_U32 || kind > SQS_KIND_KV) return 0;
+    if (cutoff == 0) cutoff = max_cutoff_of(kind);
+    if (cutoff < 4) cutoff = 4;
+    return workspace_bound(n, cutoff, key_bytes_of(kind) + (kind == SQS_KIND_KV ? 4 : 0));
+}
+
+int squaresort_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t seed, sqs_params *params, void *stream)
+{
+    return run_sort<uint32_t, false>(n, in, nullptr, out, nullptr, seed, params, stream, SQS_KIND_U32);
+}
+
+int squaresort_u64(uint64_t n, uint64_t *in, uint64_t *out, uint64_t seed, sqs_params *params, void *stream)
+{
+    return run_sort<uint64_t, false>(n, in, nullptr, out, nullptr, seed, params, stream, SQS_KIND_U64);
+}
+
+int squaresort_kv(uint64_t n, uint64_t *keys_in, uint32_t *vals_in, uint64_t *keys_out, uint32_t *vals_out,
+                  uint64_t seed, sqs_params *params, void *stream)
+{
+    return run_sort<uint64_t, true>(n, keys_in, vals_in, keys_out, vals_out, seed, params, stream, SQS_KIND_KV);
+}
+
+int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket_start, uint64_t seed,
+                       sqs_params *params, void *stream)
+{
+    uint32_t C;
+    if (int rc = resolve_cutoff(SQS_KIND_U32, params, &C)) return rc;
+    if (n < 2 || !in || !out) return SQS_ERR_ARG;
+    if (n > max_n_of(SQS_KIND_U32)) return SQS_ERR_UNSUPPORTED;
+    if (overlap(in, n * 4, out, n * 4)) return SQS_ERR_ALIAS;
+    const uint64_t m = ceil_isqrt_host(n);
+    if (bucket_start && (overlap(bucket_start, (m + 1) * 8, in, n * 4) || overlap(bucket_start, (m + 1) * 8, out, n * 4)))
+        return SQS_ERR_ALIAS;
+    // one batch of the root alone, columns sorted completely in LDS
+    const uint64_t need = node_meta_bytes(n, 4) + (64 << 10);
+    if (!params || !params->workspace || params->workspace_bytes < need) return SQS_ERR_WORKSPACE;
+    Engine<uint32_t, false> e;
+    e.A = in; e.VA = nullptr; e.D = nullptr; e.VD = nullptr;
+    e.cutoff = C;
+    e.st = (hipStream_t)stream;
+    e.ws.base = static_cast<char *>(params->workspace);
+    e.ws.size = params->workspace_bytes;
+    e.digest = false;
+    e.digest_ptr = nullptr;
+    e.skew_only = true;
+    e.skew_out = out;
+    e.skew_bs = reinterpret_cast<unsigned long long *>(bucket_start);
+    std::vector<HostNode> root{{0, (uint32_t)n, splitmix(seed)}};
+    return e.run_batch(root, 0);
+}
+
+const char *sqs_status_string(int s)
+{
+    switch (s) {
+    case SQS_OK: return "ok";
+    case SQS_ERR_ARG: return "invalid argument";
+    case SQS_ERR_ALIAS: return "input and output overlap";
+    case SQS_ERR_WORKSPACE: return "workspace missing or too small";
+    case SQS_ERR_DEVICE: return "HIP launch or copy failed";
+    case SQS_ERR_DEPTH: return "recursion too deep";
+    case SQS_ERR_UNSUPPORTED: return "size not supported";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+"""The C-ABI library loads and exports every symbol its header declares; the
+host-side argument checks return before any GPU work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "squaresort.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|uint64_t|char|void)\s*\*?\s*(\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_2407_14801_amd import binding
+    return binding
+
+
+def test_every_declared_symbol_is_exported(b):
+    names = _declared_functions()
+    assert {"squaresort_u32", "squaresort_u64", "squaresort_kv", "skew_transpose_u32",
+            "squaresort_workspace_bytes"} <= set(names)
+    for name in names:
+        assert hasattr(b.lib, name), name
+
+
+def test_limits_and_workspace(b):
+    for kind in (b.KIND_U32, b.KIND_U64, b.KIND_KV):
+        assert b.max_cutoff(kind) >= 4096
+        assert b.max_n(kind) >= 1 << 28
+        small = b.workspace_bytes(1000, kind, 64)
+        big = b.workspace_bytes(1 << 28, kind, 0)
+        assert 0 < small < big
+    assert b.max_cutoff(7) == 0 and b.workspace_bytes(10, 7, 0) == 0
+
+
+def _params(cutoff=0, ws=None, nbytes=0):
+    p = b_mod().Params()
+    p.cutoff = cutoff
+    p.workspace = ws
+    p.workspace_bytes = nbytes
+    return p
+
+
+def b_mod():
+    from paper_2407_14801_amd import binding
+    return binding
+
+
+def _call_u32(b, n, inp, out, p):
+    return b.lib.squaresort_u32(n, inp, out, 1, ctypes.byref(p), None)
+
+
+def test_argument_errors_before_gpu_work(b):
+    fake_in, fake_out = 0x10000000, 0x20000000
+    # n = 0 is a no-op even with null pointers
+    assert _call_u32(b, 0, None, None, _params()) == 0
+    # cut-off below 4 or above the maximum
+    assert _call_u32(b, 10, fake_in, fake_out, _params(cutoff=3)) == -1
+    assert _call_u32(b, 10, fake_in, fake_out, _params(cutoff=b.max_cutoff(0) + 1)) == -1
+    # null pointers
+    assert _call_u32(b, 10, None, fake_out, _params()) == -1
+    # overlapping in/out
+    assert _call_u32(b, 100, fake_in, fake_in + 8, _params()) == -2
+    # too large
+    assert _call_u32(b, b.max_n(0) + 1, fake_in, fake_out, _params()) == -7
+    # internal node but no workspace
+    n = b.max_cutoff(0) + 1
+    assert _call_u32(b, n, fake_in, fake_in + 4 * n, _params()) == -3
+    # cut-off echoed when automatic
+    p = _params()
+    assert _call_u32(b, 0, None, None, p) == 0 and p.cutoff == b.max_cutoff(0)
+    # skew transpose needs n >= 2
+    assert b.lib.skew_transpose_u32(1, fake_in, fake_out, None, 1, ctypes.byref(_params()), None) == -1
+    assert b.lib.sqs_status_string(-3) == b"workspace missing or too small"

@@ -1,0 +1,215 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bit-exact on every check: sorted keys, key/value pairs in (key, original
+index) order, the root SkewTranspose intermediate at the same seed, and the
+recursion-tree digest at the same seed and cut-off.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2407_14801_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def b():
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    from paper_2407_14801_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ws(b):
+    return b.Workspace(DEV)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def gpu_u32(b, ws, x, seed, cutoff, digest=False):
+    inp = torch.from_numpy(np.ascontiguousarray(x, np.uint32).view(np.int32)).to(DEV)
+    out = torch.empty_like(inp)
+    dg = torch.zeros(1, dtype=torch.int64, device=DEV) if digest else None
+    used = b.squaresort_u32(inp, out, seed=seed, cutoff=cutoff, ws=ws, digest=dg)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().view(np.uint32)
+    if digest:
+        return res, int(dg.cpu().numpy().view(np.uint64)[0]), used
+    return res, used
+
+
+def gpu_u64(b, ws, x, seed, cutoff, digest=False):
+    inp = torch.from_numpy(np.ascontiguousarray(x, np.uint64).view(np.int64)).to(DEV)
+    out = torch.empty_like(inp)
+    dg = torch.zeros(1, dtype=torch.int64, device=DEV) if digest else None
+    used = b.squaresort_u64(inp, out, seed=seed, cutoff=cutoff, ws=ws, digest=dg)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().view(np.uint64)
+    if digest:
+        return res, int(dg.cpu().numpy().view(np.uint64)[0]), used
+    return res, used
+
+
+def gpu_kv(b, ws, k, v, seed, cutoff, digest=False):
+    ki = torch.from_numpy(np.ascontiguousarray(k, np.uint64).view(np.int64)).to(DEV)
+    vi = torch.from_numpy(np.ascontiguousarray(v, np.uint32).view(np.int32)).to(DEV)
+    ko, vo = torch.empty_like(ki), torch.empty_like(vi)
+    dg = torch.zeros(1, dtype=torch.int64, device=DEV) if digest else None
+    used = b.squaresort_kv(ki, vi, ko, vo, seed=seed, cutoff=cutoff, ws=ws, digest=dg)
+    torch.cuda.synchronize()
+    out = (ko.cpu().numpy().view(np.uint64), vo.cpu().numpy().view(np.uint32))
+    if digest:
+        return out + (int(dg.cpu().numpy().view(np.uint64)[0]), used)
+    return out + (used,)
+
+
+def gpu_skew(b, ws, x, seed):
+    n = x.size
+    m = oracle.ceil_isqrt(n)
+    inp = torch.from_numpy(np.ascontiguousarray(x, np.uint32).view(np.int32)).to(DEV)
+    out = torch.empty_like(inp)
+    bs = torch.empty(m + 1, dtype=torch.int64, device=DEV)
+    b.skew_transpose_u32(inp, out, bs, seed=seed, ws=ws)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32), bs.cpu().numpy().view(np.uint64)
+
+
+# ------------------------------------------------------------------ u32
+U32_CASES = [
+    # (n, cutoff): spans base cases, one internal level, nested column
+    # recursion (m > cutoff), ragged tails (n not a square, empty last column)
+    (1, 0), (2, 0), (3, 4), (5, 4), (8, 4), (100, 4), (1000, 16), (4097, 64),
+    (16384, 0), (16385, 0), (65537, 0), (65537, 64), (1_000_003, 0),
+    ((1 << 20) + 3, 0), (3_000_017, 0), (130_000, 256),
+]
+
+
+@pytest.mark.parametrize("n,cutoff", U32_CASES)
+def test_u32_matches_oracle(b, ws, n, cutoff):
+    _say(f"u32 n={n} cutoff={cutoff}")
+    x = datagen.uniform_u32(n, seed=n)
+    got, used = gpu_u32(b, ws, x, seed=3, cutoff=cutoff)
+    assert np.array_equal(got, np.sort(x))
+    want = oracle.squaresort_u32(x, 3, used)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("kind", ["perm", "binary", "uniform_n", "uniform_sqrt"])
+def test_u32_paper_distributions(b, ws, kind):
+    n = 300_007
+    _say(f"u32 paper distribution {kind} n={n}")
+    x = datagen.paper_u32(kind, n, seed=5)
+    got, used = gpu_u32(b, ws, x, seed=2, cutoff=0)
+    assert np.array_equal(got, np.sort(x))
+
+
+def _degenerate(n):
+    g = np.random.default_rng(n)
+    return {
+        "all_equal": np.full(n, 12345, np.uint32),
+        "all_zero": np.zeros(n, np.uint32),
+        "all_max": np.full(n, 2**32 - 1, np.uint32),
+        "two_values": np.where(g.random(n) < 0.5, 7, 8).astype(np.uint32),
+        "extremes": np.where(g.random(n) < 0.5, 0, 2**32 - 1).astype(np.uint32),
+        "sorted": np.arange(n, dtype=np.uint32),
+        "reversed": np.arange(n, dtype=np.uint32)[::-1].copy(),
+        "organ_pipe": np.concatenate([np.arange(n // 2), np.arange(n - n // 2)[::-1]]).astype(np.uint32),
+        "dup16": datagen.uniform_u32(n, seed=7, hi=1 << 16),
+        "few_runs": np.repeat(g.integers(0, 2**32, size=50, dtype=np.uint64), n // 50 + 1)[:n].astype(np.uint32),
+    }
+
+
+@pytest.mark.parametrize("n,cutoff", [(200_003, 0), (70_000, 64)])
+@pytest.mark.parametrize("name", list(_degenerate(10).keys()))
+def test_u32_degenerate_inputs(b, ws, n, cutoff, name):
+    _say(f"u32 degenerate {name} n={n} cutoff={cutoff}")
+    x = _degenerate(n)[name]
+    got, dg, used = gpu_u32(b, ws, x, seed=1, cutoff=cutoff, digest=True)
+    want, wdg, _ = oracle.squaresort_u32(x, 1, used, want_digest=True)
+    assert np.array_equal(got, want)
+    assert dg == wdg
+
+
+@pytest.mark.parametrize("n,cutoff", [(1 << 20, 64), (100_000, 16), (1 << 20, 0)])
+def test_u32_digest_matches_oracle(b, ws, n, cutoff):
+    """The recursion tree (pivots, layouts of every internal node) matches."""
+    _say(f"u32 digest n={n} cutoff={cutoff}")
+    x = datagen.uniform_u32(n, seed=1)
+    got, dg, used = gpu_u32(b, ws, x, seed=1, cutoff=cutoff, digest=True)
+    want, wdg, nodes = oracle.squaresort_u32(x, 1, used, want_digest=True)
+    assert np.array_equal(got, want)
+    assert dg == wdg, f"digest {dg:#x} != {wdg:#x} ({nodes} internal nodes)"
+
+
+# ------------------------------------------------------------------ SkewTranspose
+@pytest.mark.parametrize("n", [2, 4, 5, 17, 1000, 4096, 65541, 1 << 20, 3_000_001])
+def test_skew_transpose_matches_oracle(b, ws, n):
+    _say(f"skew n={n}")
+    x = datagen.uniform_u32(n, seed=n + 1)
+    got, bs = gpu_skew(b, ws, x, seed=7)
+    want, wbs = oracle.root_intermediate(x.astype(np.uint64), seed=7)
+    assert np.array_equal(bs, wbs)
+    assert np.array_equal(got.astype(np.uint64), want)
+
+
+@pytest.mark.parametrize("name", ["dup16", "two_values", "all_equal", "sorted", "few_runs"])
+def test_skew_transpose_degenerate(b, ws, name):
+    x = _degenerate(250_000)[name]
+    _say(f"skew degenerate {name}")
+    got, bs = gpu_skew(b, ws, x, seed=3)
+    want, wbs = oracle.root_intermediate(x.astype(np.uint64), seed=3)
+    assert np.array_equal(bs, wbs)
+    assert np.array_equal(got.astype(np.uint64), want)
+
+
+def test_skew_transpose_is_root_of_sort(b, ws):
+    """The entry point's output is SquareSort's array A after the root step."""
+    n = 500_000
+    x = datagen.uniform_u32(n, seed=11)
+    got, _ = gpu_skew(b, ws, x, seed=9)
+    want_sort, used = gpu_u32(b, ws, x, seed=9, cutoff=0)
+    want_root, _ = oracle.root_intermediate(x.astype(np.uint64), seed=9)
+    assert np.array_equal(got.astype(np.uint64), want_root)
+    assert np.array_equal(want_sort, np.sort(x))
+
+
+# ------------------------------------------------------------------ u64, kv
+@pytest.mark.parametrize("n,cutoff", [(1, 0), (7, 4), (5000, 16), (16385, 0), (300_001, 0), (70_001, 64)])
+def test_u64_matches_oracle(b, ws, n, cutoff):
+    _say(f"u64 n={n} cutoff={cutoff}")
+    x = datagen.uniform_u64(n, seed=n)
+    x[: n // 10] = x[0]
+    got, dg, used = gpu_u64(b, ws, x, seed=4, cutoff=cutoff, digest=True)
+    want, wdg, _ = oracle.squaresort_u64(x, 4, used, want_digest=True)
+    assert np.array_equal(got, want)
+    assert np.array_equal(got, np.sort(x))
+    assert dg == wdg
+
+
+@pytest.mark.parametrize("n,cutoff", [(9, 4), (5000, 16), (40_000, 64), (300_007, 0)])
+def test_kv_matches_oracle(b, ws, n, cutoff):
+    _say(f"kv n={n} cutoff={cutoff}")
+    k, v = datagen.kv_mixture(n, seed=4)
+    ko, vo, dg, used = gpu_kv(b, ws, k, v, seed=1, cutoff=cutoff, digest=True)
+    order = np.argsort(k, kind="stable")
+    assert np.array_equal(ko, k[order])
+    assert np.array_equal(vo, v[order])
+    wk, wv, wdg, _ = oracle.squaresort_kv(k, v, 1, used, want_digest=True)
+    assert np.array_equal(ko, wk) and np.array_equal(vo, wv)
+    assert dg == wdg
+
+
+# ------------------------------------------------------------------ determinism
+def test_repeat_runs_identical(b, ws):
+    x = datagen.uniform_u32(2_000_003, seed=2)
+    a, da, _ = gpu_u32(b, ws, x, seed=5, cutoff=0, digest=True)
+    c, dc, _ = gpu_u32(b, ws, x, seed=5, cutoff=0, digest=True)
+    d, dd, _ = gpu_u32(b, ws, x, seed=6, cutoff=0, digest=True)
+    assert np.array_equal(a, c) and da == dc
+    assert np.array_equal(a, d) and da != dd

@@ -298,3 +298,13 @@ def test_tree_shape_doubles_per_level(orc):
     for d in range(depth):
         assert ssum[d] <= (2 ** d) * n
     assert 2 <= depth <= 8
+
+
+def test_root_buckets_match_full_intermediate(orc):
+    x = datagen.uniform_u32(50000, seed=9).astype(np.uint64)
+    full, bs = orc.root_intermediate(x, seed=4)
+    sel, bounds, keys = orc.root_buckets(x, 4, [0, 3, 17, 100, 223])
+    assert np.array_equal(bounds[:, 0], bs[sel.astype(np.int64)])
+    assert np.array_equal(bounds[:, 1], bs[sel.astype(np.int64) + 1])
+    want = np.concatenate([full[int(bs[j]):int(bs[j + 1])] for j in sel])
+    assert np.array_equal(keys, want)
