@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of libsquaresort on one MI355X.
+
+Default workload: SquareSort of n = 2^28 uint32 keys drawn i.i.d. uniform over
+[0, 2^32) (data seed 2, pivot seed 1, automatic cut-off).  One step is one
+full sort (every recursion level) of one resident copy of the input; the
+input is clobbered by a sort, so W+K copies are staged in HBM before the
+timed region.  Prints one JSON line.
+
+  value        whole-job throughput, keys sorted per second (GKeys/s)
+  roofline     the dominant kernel (largest share of device time) against the
+               HBM peak: its algorithmic bytes (read + write of every key it
+               processes) over its measured duration (HIP events on the launch
+               stream, from the library's timing table)
+  path_roofline  the whole step against the HBM roofline of the method:
+               6 * w * n algorithmic bytes per HBM-resident level
+  cpu_baseline the CPU oracle on a bounded sample of the same input
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "u32_uniform": dict(kind="u32", log2n=28, dist="uniform[0,2^32)", data_seed=2),
+    "u32_dup16": dict(kind="u32", log2n=28, dist="uniform[0,2^16)", data_seed=3),
+    "kv_mixture": dict(kind="kv", log2n=27, dist="80% Zipf(1.1) over 2^20 u64 / 10% constant / "
+                                                  "10% sorted run with 1% swaps", data_seed=4),
+}
+
+
+def make_input(wl, n):
+    from paper_2407_14801_amd import datagen
+    if wl["kind"] == "u32":
+        hi = 1 << 16 if "2^16" in wl["dist"] else 1 << 32
+        return (datagen.uniform_u32(n, seed=wl["data_seed"], hi=hi),)
+    return datagen.kv_mixture(n, seed=wl["data_seed"])
+
+
+def cpu_baseline(wl, host, cutoff, seed, log2_sample):
+    """The CPU oracle, as it stands, on the first 2^log2_sample keys."""
+    import oracle
+    s = 1 << log2_sample
+    t0 = time.perf_counter()
+    if wl["kind"] == "u32":
+        out = oracle.squaresort_u32(host[0][:s], seed, cutoff)
+        ok = bool(np.all(out[1:] >= out[:-1]))
+    else:
+        ko, _ = oracle.squaresort_kv(host[0][:s], host[1][:s], seed, cutoff)
+        ok = bool(np.all(ko[1:] >= ko[:-1]))
+    dt = time.perf_counter() - t0
+    return {"value": s / dt / 1e9, "unit": "GKeys/s" if wl["kind"] == "u32" else "GPairs/s",
+            "cores": 1, "kind": "oracle", "seconds": round(dt, 3), "sorted": ok,
+            "sample": f"full oracle SquareSort (single thread) of the first 2^{log2_sample} keys "
+                      f"of the same input, same seed and cut-off"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="u32_uniform", choices=sorted(WORKLOADS))
+    ap.add_argument("--log2n", type=int, default=None, help="override the size (2^k keys)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU exchange is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2407_14801_amd import binding
+
+    wl = WORKLOADS[args.workload]
+    log2n = args.log2n or wl["log2n"]
+    n = 1 << log2n
+    dev = torch.device("cuda:0")
+    seed = 1
+    print(f"# generating {args.workload} n=2^{log2n}", file=sys.stderr, flush=True)
+    host = make_input(wl, n)
+    ws = binding.Workspace(dev)
+    copies = args.warmup + args.steps
+
+    if wl["kind"] == "u32":
+        base = torch.from_numpy(host[0].view(np.int32)).to(dev)
+        ins = [base.clone() for _ in range(copies)]
+        out = torch.empty_like(base)
+        w = 4
+
+        def step(i):
+            return binding.squaresort_u32(ins[i], out, seed=seed, cutoff=0, ws=ws)
+    else:
+        bk = torch.from_numpy(host[0].view(np.int64)).to(dev)
+        bv = torch.from_numpy(host[1].view(np.int32)).to(dev)
+        ins = [(bk.clone(), bv.clone()) for _ in range(copies)]
+        ko, vo = torch.empty_like(bk), torch.empty_like(bv)
+        w = 12
+
+        def step(i):
+            return binding.squaresort_kv(ins[i][0], ins[i][1], ko, vo, seed=seed, cutoff=0, ws=ws)
+    torch.cuda.synchronize()
+
+    print(f"# warmup {args.warmup}", file=sys.stderr, flush=True)
+    cutoff = 0
+    for i in range(args.warmup):
+        cutoff = step(i)
+    torch.cuda.synchronize()
+    if not args.no_timing:
+        binding.timing_enable(True)
+    print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, copies):
+        cutoff = step(i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = binding.timing_report() if not args.no_timing else {}
+    binding.timing_enable(False)
+
+    # the last output must be sorted (cheap device check)
+    if wl["kind"] == "u32":
+        o = out.to(torch.int64) & 0xFFFFFFFF
+    else:
+        o = ko
+        o = o.view(torch.int64)
+    if wl["kind"] == "u32":
+        sorted_ok = bool((o[1:] >= o[:-1]).all().item())
+    else:   # compare unsigned 64-bit keys by flipping the sign bit
+        f = o ^ torch.tensor(-(1 << 63), dtype=torch.int64, device=dev)
+        sorted_ok = bool((f[1:] >= f[:-1]).all().item())
+
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms / 1e3) / 1e9
+    b_alg = 6 * w * n
+    path = {"bytes_alg_per_level": b_alg, "levels": 1, "achieved_gbs": b_alg / (ms / 1e3) / 1e9,
+            "peak_gbs": HBM_PEAK_GBS}
+    path["frac"] = path["achieved_gbs"] / HBM_PEAK_GBS
+
+    roof = None
+    kern = {}
+    if timing:
+        tot = sum(v["ms"] for v in timing.values())
+        for k, v in timing.items():
+            kern[k] = {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
+                       "share": v["ms"] / tot if tot else 0.0}
+        dom = max(timing, key=lambda k: timing[k]["ms"])
+        d = timing[dom]
+        avg_ms = d["ms"] / d["launches"]
+        bytes_per_launch = 2 * w * d["units"] / d["launches"]     # read + write of each key
+        ach = bytes_per_launch / (avg_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 5), "alg_bytes_per_launch": int(bytes_per_launch)}
+
+    res = {
+        "metric": "GKeys/s" if wl["kind"] == "u32" else "GPairs/s",
+        "value": round(value, 4),
+        "unit": "GKeys/s" if wl["kind"] == "u32" else "GPairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32" if wl["kind"] == "u32" else "u64+u32",
+        "data": "synthetic",
+        "config": {"workload": f"squaresort_{args.workload}_2^{log2n}", "n": n, "key_dist": wl["dist"],
+                   "data_seed": wl["data_seed"], "seed": seed, "cutoff": cutoff},
+        "roofline": roof,
+        "path_roofline": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in path.items()},
+        "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in kern.items()},
+        "sorted_check": sorted_ok,
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(wl, host, cutoff, seed, min(args.cpu_sample_log2, log2n))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,16 @@ int squaresort_kv(uint64_t n, uint64_t *keys_in, uint32_t *vals_in,
 int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket_start,
                        uint64_t seed, sqs_params *params, void *stream);
 
+/* Measurement support (not part of the sort): while enabled, every launch is
+ * bracketed by HIP events on its stream and the elapsed times are summed per
+ * kernel.  sqs_timing_enable clears the table.  sqs_timing_report writes a
+ * JSON object {"kernel": [total_ms, launches, units], ...} into buf
+ * (truncated to len-1 bytes, NUL-terminated) and returns the full length;
+ * units counts the keys the launches processed (pivots for the pivot
+ * kernels, buckets for the scans). */
+int sqs_timing_enable(int on);
+int64_t sqs_timing_report(char *buf, uint64_t len);
+
 /* Human-readable name of a status code. */
 const char *sqs_status_string(int status);
 

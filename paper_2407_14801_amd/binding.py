@@ -43,6 +43,8 @@ _SIGS = {
     "squaresort_kv": (_i, [_u64, _vp, _vp, _vp, _vp, _u64, _P, _vp]),
     "skew_transpose_u32": (_i, [_u64, _vp, _vp, _vp, _u64, _P, _vp]),
     "sqs_status_string": (ctypes.c_char_p, [_i]),
+    "sqs_timing_enable": (_i, [_i]),
+    "sqs_timing_report": (ctypes.c_int64, [ctypes.c_char_p, _u64]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -157,6 +159,19 @@ def skew_transpose_u32(inp: torch.Tensor, out: torch.Tensor, bucket_start: torch
     p, _keep = _params(n, KIND_U32, 0, ws, None)
     _check(_lib.skew_transpose_u32(n, _ptr(inp), _ptr(out), _ptr(bucket_start), seed, ctypes.byref(p),
                                    _stream(inp.device)), "skew_transpose_u32")
+
+
+def timing_enable(on: bool = True) -> None:
+    _lib.sqs_timing_enable(1 if on else 0)
+
+
+def timing_report() -> dict:
+    import json
+    n = _lib.sqs_timing_report(None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    _lib.sqs_timing_report(buf, n + 1)
+    return {k: {"ms": v[0], "launches": int(v[1]), "units": int(v[2])}
+            for k, v in json.loads(buf.value.decode()).items()}
 
 
 # raw entry points for tests that exercise the C ABI directly

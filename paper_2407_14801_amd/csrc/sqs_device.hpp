@@ -2,18 +2,19 @@
 //
 //  * the counter-based generator that draws pivot positions (SplitMix64 of
 //    Steele, Lea and Flood, OOPSLA 2014, keyed per recursion node);
-//  * key traits for u32 / u64 keys;
-//  * a stable work-group radix sort whose keys live in registers and whose
-//    LDS holds only the rank tables and one 32-bit exchange buffer.
+//  * key traits for u32 / u64 keys and the pivot rule;
+//  * stable LSD radix sorts whose keys live in registers: a work-group sort
+//    (up to NW*64*IPT keys) and a wave sort (up to 64*R keys, no barriers).
 //
 // Ranking is deterministic and stable without relying on the order in which
-// the LDS serves colliding atomics: for every 64-key row of a wave, each lane
-// ORs its lane bit into a per-wave 64-bit mask of its digit (OR commutes, so
-// the mask is the same whatever the service order), reads the mask back, and
-// gets its rank among equal digits of the row with v_mbcnt and the row count
-// with v_bcnt.  Rows are processed in order, so ranks follow the position
-// order (wave, row, lane); a digit-major / wave-minor exclusive scan of the
-// per-wave counts then gives every key its destination.
+// the LDS serves colliding atomics.  Each wave owns a table of 16-byte
+// entries {mask_lo, mask_hi, count, offset}, one per digit value.  For every
+// 64-key row, each lane ORs its lane bit into its half of the mask of its
+// digit (OR commutes, so the result does not depend on service order), reads
+// the entry back, takes its rank among equal digits of the row with v_mbcnt
+// and the row's count with v_bcnt, and every peer writes the same updated
+// entry {0, 0, count + row count, -}.  Rows are processed in position order,
+// so ranks are stable; an exclusive scan of the counts then places every key.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -45,15 +46,14 @@ __device__ inline uint32_t pivot_draw(uint64_t K, uint64_t t, uint32_t n)
 // ---------------------------------------------------------------- keys
 template <class K> struct KeyT;
 template <> struct KeyT<uint32_t> {
-    static constexpr int BITS = 32;
     static constexpr int WORDS = 1;
     static constexpr uint32_t MAXV = 0xFFFFFFFFu;
     __device__ static int bitlen(uint32_t x) { return x ? 32 - __clz(x) : 0; }
     __device__ static uint32_t word(uint32_t x, int) { return x; }
     __device__ static uint32_t set_word(uint32_t, int, uint32_t w) { return w; }
+    __device__ static uint32_t digit(uint32_t x, uint32_t lo, int sh) { return ((x - lo) >> sh) & 255u; }
 };
 template <> struct KeyT<uint64_t> {
-    static constexpr int BITS = 64;
     static constexpr int WORDS = 2;
     static constexpr uint64_t MAXV = 0xFFFFFFFFFFFFFFFFull;
     __device__ static int bitlen(uint64_t x) { return x ? 64 - __clzll(x) : 0; }
@@ -62,6 +62,7 @@ template <> struct KeyT<uint64_t> {
     {
         return i == 0 ? ((x & 0xFFFFFFFF00000000ull) | w) : ((x & 0xFFFFFFFFull) | ((uint64_t)w << 32));
     }
+    __device__ static uint32_t digit(uint64_t x, uint64_t lo, int sh) { return (uint32_t)((x - lo) >> sh) & 255u; }
 };
 
 // Pivot rule: key x belongs to bucket t or an earlier one iff x <= s_t, or
@@ -72,12 +73,21 @@ template <class K> __device__ inline bool le_pivot(K x, K s, bool strict)
 }
 
 // ---------------------------------------------------------------- wave helpers
-__device__ inline uint32_t lane_id() { return threadIdx.x & (WAVE - 1); }
-__device__ inline uint32_t wave_id() { return threadIdx.x / WAVE; }
+__device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+// the wave index, as a wave-uniform (scalar) value
+__device__ inline uint32_t wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); }
 
-__device__ inline uint32_t rank_in_mask(unsigned long long m)
+// orders this wave's LDS accesses before and after (no work-group barrier)
+__device__ inline void wave_lds_sync()
 {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint32_t rank_in_mask(uint32_t lo, uint32_t hi)
+{
+    return __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
 }
 
 template <class T> __device__ inline T wave_min(T v)
@@ -105,88 +115,40 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// ---------------------------------------------------------------- rank tables
-// Per-wave digit tables for a ranking pass over RDX digit values.
-template <int NW, int RDX> struct RankTables {
-    unsigned long long mask[NW][RDX];
-    uint32_t cnt[NW][RDX];
-    uint32_t offs[NW][RDX];
-    uint32_t wsum[NW];
+// ---------------------------------------------------------------- ranking
+struct alignas(16) RankEnt {
+    uint32_t mlo, mhi, cnt, off;
 };
 
-template <int NW, int RDX>
-__device__ inline void rank_tables_init(RankTables<NW, RDX> &rt)
+// Rank one 64-key row against a wave's digit table: returns the count of
+// equal digits in earlier rows plus the rank among equal digits of this row.
+__device__ inline uint32_t rank_row(RankEnt *tab, uint32_t d)
 {
-    for (int i = threadIdx.x; i < NW * RDX; i += NW * WAVE) {
-        (&rt.mask[0][0])[i] = 0ull;
-        (&rt.cnt[0][0])[i] = 0u;
-    }
-}
-
-// Stable ranking of IPT digits per thread.  Thread (w, lane) holds the keys
-// at positions w*IPT*64 + r*64 + lane.  On return pos[r] is the destination
-// position of key r; offs[0][d] is the first position of digit d.  Requires
-// the mask table zero and cnt zero on entry; leaves both zero.  Contains two
-// work-group barriers.
-template <int NW, int IPT, int RDX>
-__device__ inline void rank_digits(const uint32_t (&dig)[IPT], uint32_t (&pos)[IPT],
-                                   RankTables<NW, RDX> &rt)
-{
-    const uint32_t l = lane_id(), w = wave_id();
-    const unsigned long long bit = 1ull << l;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t d = dig[r];
-        atomicOr(&rt.mask[w][d], bit);
-        const unsigned long long pm =
-            __hip_atomic_load(&rt.mask[w][d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        const uint32_t old = rt.cnt[w][d];
-        pos[r] = old + rank_in_mask(pm);
-        rt.cnt[w][d] = old + (uint32_t)__popcll(pm);   // every peer stores the same value
-        rt.mask[w][d] = 0ull;                            // likewise
-    }
-    __syncthreads();
-    // digit-major, wave-minor exclusive scan of the per-wave counts
-    constexpr int NT = NW * WAVE;
-    static_assert(RDX <= NT, "one thread per digit");
-    const uint32_t t = threadIdx.x;
-    uint32_t c[NW];
-    uint32_t tot = 0;
-    if (t < (uint32_t)RDX) {
-#pragma unroll
-        for (int ww = 0; ww < NW; ++ww) { c[ww] = rt.cnt[ww][t]; tot += c[ww]; }
-    }
-    const uint32_t incl = wave_incl_scan(tot);
-    if (l == WAVE - 1) rt.wsum[w] = incl;
-    __syncthreads();
-    if (t < (uint32_t)RDX) {
-        uint32_t run = incl - tot;
-        for (uint32_t ww = 0; ww < w; ++ww) run += rt.wsum[ww];
-#pragma unroll
-        for (int ww = 0; ww < NW; ++ww) {
-            rt.offs[ww][t] = run;
-            run += c[ww];
-            rt.cnt[ww][t] = 0u;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) pos[r] += rt.offs[w][dig[r]];
+    const uint32_t l = lane_id();
+    RankEnt *e = tab + d;
+    atomicOr(l < 32 ? &e->mlo : &e->mhi, 1u << (l & 31));
+    const uint4 v = *reinterpret_cast<const uint4 *>(e);
+    const uint32_t r = v.z + rank_in_mask(v.x, v.y);
+    *reinterpret_cast<uint4 *>(e) = make_uint4(0u, 0u, v.z + __popc(v.x) + __popc(v.y), 0u);
+    return r;
 }
 
 // ---------------------------------------------------------------- block sort
-// Shared memory of the block sort: rank tables plus a 32-bit exchange buffer
-// of CAP words.  Once a sort is done the whole region may be reused.
+// Work-group sort of up to CAP = NW*64*IPT keys.  Thread (w, lane) holds the
+// keys at positions w*IPT*64 + r*64 + lane, r < IPT.  Shared memory: the
+// per-wave digit tables and one 32-bit exchange buffer; once a sort has
+// returned, the whole region may be reused.
 template <int NW, int IPT> struct SortSmem {
     static constexpr int CAP = NW * WAVE * IPT;
     union {
         struct {
-            RankTables<NW, 256> rt;
+            RankEnt tab[NW][256];
             uint32_t buf[CAP];
         } s;
-        uint64_t k64[CAP];    // reuse after a sort: up to CAP 64-bit words
+        uint64_t k64[CAP];
         uint32_t k32[2 * CAP];
     };
+    uint32_t wsum[NW];
     uint32_t red32[2 * NW];
     unsigned long long red64[2 * NW];
 };
@@ -195,6 +157,23 @@ template <int NW, int IPT>
 __device__ inline uint32_t item_pos(int r)
 {
     return wave_id() * (IPT * WAVE) + r * WAVE + lane_id();
+}
+
+// rows of the calling wave that hold at least one of the first `count` positions
+template <int IPT>
+__device__ inline int wave_rows(uint32_t count)
+{
+    const int64_t left = (int64_t)count - (int64_t)wave_id() * IPT * WAVE;
+    if (left <= 0) return 0;
+    const int64_t r = (left + WAVE - 1) / WAVE;
+    return r < IPT ? (int)r : IPT;
+}
+
+template <int NW, int RDX>
+__device__ inline void tables_clear(RankEnt (*tab)[RDX])
+{
+    for (int i = threadIdx.x; i < NW * RDX; i += NW * WAVE)
+        (&tab[0][0])[i] = RankEnt{0u, 0u, 0u, 0u};
 }
 
 template <class K, int NW>
@@ -219,47 +198,172 @@ __device__ inline void block_minmax(K &lo, K &hi, uint32_t *red32, unsigned long
     __syncthreads();
 }
 
-// Stable LSD radix sort of `count` keys (and values) held in registers at
-// positions item_pos(r); positions >= count are padding and stay at the end.
-// Only the bits in which the keys differ are sorted: the keys are offset by
-// their minimum and ceil(bits(max-min)/8) 8-bit passes run.  rank tables must
-// be zero on entry (rank_tables_init); they are zero again on return.  Ends
-// with a barrier, after which the shared memory may be reused.
+// Digit-major, wave-minor exclusive scan of the per-wave counts of RDX digit
+// values: off := first position of (digit, wave); cnt := 0.  wsum has NW
+// words.  Two barriers inside; call after a barrier that follows ranking.
+template <int NW, int RDX>
+__device__ inline void scan_tables(RankEnt (*tab)[RDX], uint32_t *wsum)
+{
+    static_assert(RDX <= NW * WAVE, "one thread per digit value");
+    const uint32_t t = threadIdx.x;
+    uint32_t tot = 0;
+    if (t < (uint32_t)RDX)
+        for (int ww = 0; ww < NW; ++ww) tot += tab[ww][t].cnt;
+    const uint32_t incl = wave_incl_scan(tot);
+    if (lane_id() == WAVE - 1) wsum[wave_id()] = incl;
+    __syncthreads();
+    if (t < (uint32_t)RDX) {
+        uint32_t run = incl - tot;
+        for (uint32_t ww = 0; ww < wave_id(); ++ww) run += wsum[ww];
+        for (int ww = 0; ww < NW; ++ww) {
+            const uint32_t c = tab[ww][t].cnt;
+            tab[ww][t].off = run;
+            tab[ww][t].cnt = 0u;
+            run += c;
+        }
+    }
+    __syncthreads();
+}
+
+// Stable LSD radix sort of `count` keys (and values) in registers; positions
+// >= count are padding and stay at the end.  Only the bits in which the keys
+// differ are sorted: keys are offset by their minimum and ceil(bits/8) 8-bit
+// passes run.  Tables must be clear on entry (tables_clear + barrier); they
+// are clear again on return.  Ends with a barrier.
 template <class K, bool HV, int NW, int IPT>
 __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, SortSmem<NW, IPT> &sm)
 {
     using T = KeyT<K>;
+    const int nrows = wave_rows<IPT>(count);
     K lo = (K)T::MAXV, hi = (K)0;
 #pragma unroll
     for (int r = 0; r < IPT; ++r)
-        if (item_pos<NW, IPT>(r) < count) { lo = k[r] < lo ? k[r] : lo; hi = k[r] > hi ? k[r] : hi; }
+        if (r < nrows && item_pos<NW, IPT>(r) < count) { lo = k[r] < lo ? k[r] : lo; hi = k[r] > hi ? k[r] : hi; }
     block_minmax<K, NW>(lo, hi, sm.red32, sm.red64);
     if (count <= 1 || !(lo < hi)) return;          // already in order (uniform branch)
     const int passes = (T::bitlen((K)(hi - lo)) + 7) / 8;
-    uint32_t dig[IPT], pos[IPT];
+    RankEnt *tab = sm.s.tab[wave_id()];
+    uint32_t pos[IPT];
     for (int ps = 0; ps < passes; ++ps) {
         const int sh = 8 * ps;
 #pragma unroll
-        for (int r = 0; r < IPT; ++r)
-            dig[r] = item_pos<NW, IPT>(r) < count ? (uint32_t)(((K)(k[r] - lo) >> sh) & 255u) : 255u;
-        rank_digits<NW, IPT, 256>(dig, pos, sm.s.rt);
-        // move the keys (and values) word by word through the exchange buffer
+        for (int r = 0; r < IPT; ++r) {
+            if (r < nrows) {
+                const uint32_t d = item_pos<NW, IPT>(r) < count ? T::digit(k[r], lo, sh) : 255u;
+                pos[r] = rank_row(tab, d);
+            }
+        }
+        __syncthreads();
+        scan_tables<NW, 256>(sm.s.tab, sm.wsum);
+#pragma unroll
+        for (int r = 0; r < IPT; ++r) {
+            if (r < nrows) {
+                const uint32_t d = item_pos<NW, IPT>(r) < count ? T::digit(k[r], lo, sh) : 255u;
+                pos[r] += tab[d].off;
+            }
+        }
+        // move keys (and values) word by word through the exchange buffer
 #pragma unroll
         for (int wd = 0; wd < T::WORDS; ++wd) {
 #pragma unroll
-            for (int r = 0; r < IPT; ++r) sm.s.buf[pos[r]] = T::word(k[r], wd);
+            for (int r = 0; r < IPT; ++r)
+                if (r < nrows) sm.s.buf[pos[r]] = T::word(k[r], wd);
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < IPT; ++r) k[r] = T::set_word(k[r], wd, sm.s.buf[item_pos<NW, IPT>(r)]);
+            for (int r = 0; r < IPT; ++r)
+                if (r < nrows) k[r] = T::set_word(k[r], wd, sm.s.buf[item_pos<NW, IPT>(r)]);
             __syncthreads();
         }
         if (HV) {
 #pragma unroll
-            for (int r = 0; r < IPT; ++r) sm.s.buf[pos[r]] = v[r];
+            for (int r = 0; r < IPT; ++r)
+                if (r < nrows) sm.s.buf[pos[r]] = v[r];
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < IPT; ++r) v[r] = sm.s.buf[item_pos<NW, IPT>(r)];
+            for (int r = 0; r < IPT; ++r)
+                if (r < nrows) v[r] = sm.s.buf[item_pos<NW, IPT>(r)];
             __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------- wave sort
+// One wave sorts up to 64*R keys at positions r*64 + lane with its own table
+// and buffer; no work-group barrier.  The table must be clear on entry and is
+// clear on return.
+template <int R> struct WaveSmem {
+    RankEnt tab[256];
+    uint32_t buf[R * WAVE];
+};
+
+template <class K, bool HV, int R>
+__device__ void wave_sort(K (&k)[R], uint32_t (&v)[R], uint32_t count, WaveSmem<R> &sm)
+{
+    using T = KeyT<K>;
+    const uint32_t l = lane_id();
+    const int nrows = (int)min((count + WAVE - 1) / WAVE, (uint32_t)R);
+    K lo = (K)T::MAXV, hi = (K)0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < nrows && r * WAVE + l < count) { lo = k[r] < lo ? k[r] : lo; hi = k[r] > hi ? k[r] : hi; }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (count <= 1 || !(lo < hi)) return;
+    const int passes = (T::bitlen((K)(hi - lo)) + 7) / 8;
+    uint32_t pos[R];
+    for (int ps = 0; ps < passes; ++ps) {
+        const int sh = 8 * ps;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r < nrows) {
+                const uint32_t d = r * WAVE + l < count ? T::digit(k[r], lo, sh) : 255u;
+                pos[r] = rank_row(sm.tab, d);
+            }
+        }
+        wave_lds_sync();
+        // exclusive scan over the 256 digit counts: lane l owns digits 4l..4l+3
+        {
+            uint32_t c0 = sm.tab[4 * l].cnt, c1 = sm.tab[4 * l + 1].cnt;
+            uint32_t c2 = sm.tab[4 * l + 2].cnt, c3 = sm.tab[4 * l + 3].cnt;
+            const uint32_t s = c0 + c1 + c2 + c3;
+            uint32_t run = wave_incl_scan(s) - s;
+            sm.tab[4 * l].off = run;     run += c0;
+            sm.tab[4 * l + 1].off = run; run += c1;
+            sm.tab[4 * l + 2].off = run; run += c2;
+            sm.tab[4 * l + 3].off = run;
+            sm.tab[4 * l].cnt = 0u;
+            sm.tab[4 * l + 1].cnt = 0u;
+            sm.tab[4 * l + 2].cnt = 0u;
+            sm.tab[4 * l + 3].cnt = 0u;
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r < nrows) {
+                const uint32_t d = r * WAVE + l < count ? T::digit(k[r], lo, sh) : 255u;
+                pos[r] += sm.tab[d].off;
+            }
+        }
+#pragma unroll
+        for (int wd = 0; wd < T::WORDS; ++wd) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r < nrows) sm.buf[pos[r]] = T::word(k[r], wd);
+            wave_lds_sync();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r < nrows) k[r] = T::set_word(k[r], wd, sm.buf[r * WAVE + l]);
+            wave_lds_sync();
+        }
+        if (HV) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r < nrows) sm.buf[pos[r]] = v[r];
+            wave_lds_sync();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r < nrows) v[r] = sm.buf[r * WAVE + l];
+            wave_lds_sync();
         }
     }
 }

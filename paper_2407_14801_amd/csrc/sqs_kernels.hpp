@@ -3,17 +3,22 @@
 //
 // A node owns the range [off, off+n) of both global arrays A (its input,
 // clobbered) and D (its output).  For a batch of nodes the step runs:
-//   k_sample         m-1 pivot draws per node from its input A
-//   k_sort_pivots    sort them, strict flags (pivot equal to the next one)
-//   k_colsort        sort each column A -> D and count, per column i and
-//                    bucket block J, how many keys precede J; per column
-//                    group g and bucket j, how many keys of g fall in j
-//   k_colscan        prefix over groups per bucket, bucket totals
-//   k_bucket_start   exclusive scan of totals: bucket j = [bs[j], bs[j+1])
-//   k_transpose      SkewTranspose D -> A over (column group x bucket block)
-//                    tiles, staged through LDS
-//   k_bucket         per bucket: skip (empty), copy (single key value), sort
-//                    in LDS (base case), or mark for the next batch
+//   k_sample          m-1 pivot draws per node from its input A
+//   k_sort_pivots*    sort them; strict flags (pivot equal to the next one)
+//   k_colsort_*       sort each column A -> D (base case) or take it sorted
+//                     from deeper recursion, and count: per column i and
+//                     bucket block J the keys before J; per column group g
+//                     and bucket j the keys of g in j
+//   k_colscan         prefix of the group counts over groups, bucket totals
+//   k_bucket_start    exclusive scan of totals: bucket j = [bs[j], bs[j+1])
+//   k_transpose       SkewTranspose D -> A over (column group x bucket block)
+//                     tiles, staged through LDS
+//   k_classify        per bucket: empty / single value / small / mid / internal
+//   k_bucket_*        copy single-value buckets, sort small (one wave) and mid
+//                     (one work-group) buckets A -> D; internal buckets form
+//                     the next batch
+// Columns and buckets of at most WCAP keys are sorted by one wave each; the
+// block kernels handle up to CAP keys.
 #pragma once
 
 #include "sqs_device.hpp"
@@ -21,15 +26,18 @@
 namespace sqs {
 
 // ------------------------------------------------------------ configuration
-constexpr int SORT_NW = 16;                  // waves of the sorting work-groups
+constexpr int SORT_NW = 16;                  // waves of the block-sort work-groups
 constexpr int SORT_IPT = 16;                 // keys per thread
 constexpr int SORT_NT = SORT_NW * WAVE;      // 1024 threads
-constexpr int SORT_CAP = SORT_NT * SORT_IPT; // 16384 keys per LDS sort
+constexpr int SORT_CAP = SORT_NT * SORT_IPT; // 16384 keys per block sort
+constexpr int WR = 16;                       // rows of a wave sort
+constexpr int WCAP = WR * WAVE;              // 1024 keys per wave sort
+constexpr int SM_NW = 4;                     // waves of the small-segment work-groups
 constexpr int TG = 64;                       // columns per column group
 constexpr int TB = 64;                       // buckets per bucket block
-constexpr int TR_NW = 16;                    // waves of the transpose work-group
-constexpr int TR_IPT = 8;                    // keys per thread per chunk
-constexpr int TR_CH = TR_NW * WAVE * TR_IPT; // 8192 keys per transpose chunk
+constexpr int TR_NW = 4;                     // waves of the transpose work-group
+constexpr int TR_IPT = 16;                   // keys per thread per chunk
+constexpr int TR_CH = TR_NW * WAVE * TR_IPT; // 4096 keys per transpose chunk
 
 using SortSm = SortSmem<SORT_NW, SORT_IPT>;
 
@@ -41,29 +49,41 @@ struct NodeDesc {
     uint32_t groups;   // ceil(m / TG)
     uint32_t nJ;       // ceil(m / TB)
     uint32_t piv;      // first pivot slot (m-1 slots)
-    uint32_t bkt;      // first bucket slot (m+1 slots in bs, m in tot/cls)
+    uint32_t bkt;      // first bucket slot (m+1 slots in bs, m in tot)
     uint64_t src;      // first slot of the column/bucket-block offsets ((nJ+1)*m)
     uint64_t blk;      // first slot of the group/bucket counts (groups*m)
-    uint32_t flags;    // NODE_COLS_SORTED: columns already sorted into D
+    uint32_t flags;    // NODE_COLS_RECURSED: columns > cut-off come sorted in D
     uint32_t pad;
 };
-constexpr uint32_t NODE_COLS_SORTED = 1u;
+constexpr uint32_t NODE_COLS_RECURSED = 1u;
+
+struct BucketItem {
+    uint32_t node, j, lo, size;   // lo: node-local first slot
+};
+enum { CLS_COPY = 0, CLS_SMALL = 1, CLS_MID = 2, CLS_INTERNAL = 3, NCLS = 4 };
 
 template <class K> struct Batch {
     const NodeDesc *nodes;
     uint32_t N;
     const uint32_t *pivStart;    // N+1 prefix of m-1
-    const uint32_t *grpStart;    // N+1 prefix of groups
     const uint32_t *tileStart;   // N+1 prefix of groups*nJ
     const uint32_t *bucStart;    // N+1 prefix of m
     const uint32_t *digStart;    // N+1 prefix of digest chunks
+    // nodes whose columns / pivots are handled by work-groups (m > WCAP) and
+    // by waves (m <= WCAP): node index lists and their group prefixes
+    const uint32_t *bigIdx, *bigGrp;
+    uint32_t NB;
+    const uint32_t *smlIdx, *smlGrp;
+    uint32_t NS;
     K *piv;
     uint8_t *strict;
     uint32_t *srcOff;   // [J][i] per node: keys of column i in buckets < J*TB
     uint32_t *blk;      // [g][j] per node: keys of group g in bucket j (then prefix over g)
     uint32_t *bs;       // [j] per node, m+1 entries
     uint32_t *tot;      // [j] per node
-    uint8_t *cls;       // [j] per node: 0 empty, 1 single value, 2 base, 3 internal
+    BucketItem *list[NCLS];
+    uint32_t cap[NCLS];
+    uint32_t *ctr;      // NCLS counters
     unsigned long long *H;
 };
 
@@ -78,7 +98,24 @@ __device__ inline uint32_t find_node(const uint32_t *prefix, uint32_t N, uint32_
     return lo;
 }
 
+// bucket of x among npiv sorted pivots (count of pivots x is not at-or-below)
+template <class K>
+__device__ inline uint32_t bucket_search(K x, const K *piv, const uint8_t *st, uint32_t npiv)
+{
+    uint32_t a = 0, e = npiv;
+    while (a < e) {
+        const uint32_t mid = (a + e) >> 1;
+        if (le_pivot(x, piv[mid], st[mid] != 0)) e = mid; else a = mid + 1;
+    }
+    return a;
+}
+
 // ------------------------------------------------------------ utility kernels
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
 __global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v)
 {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -99,17 +136,17 @@ __global__ void k_sample(Batch<K> b, const K *A)
     b.piv[nd.piv + t] = A[nd.off + pivot_draw(nd.key, t, nd.n)];
 }
 
-// Sort the samples of one node (any correct sort; the paper uses MergeSort)
-// and mark strict pivots.
+// Sort the samples of one node (any correct sort; the paper uses MergeSort):
+// one work-group per node with more than WCAP pivots ...
 template <class K>
-__global__ __launch_bounds__(SORT_NT) void k_sort_pivots(Batch<K> b)
+__global__ __launch_bounds__(SORT_NT) void k_sort_pivots_big(Batch<K> b)
 {
     __shared__ SortSm sm;
-    const NodeDesc nd = b.nodes[blockIdx.x];
+    const NodeDesc nd = b.nodes[b.bigIdx[blockIdx.x]];
     const uint32_t cnt = nd.m - 1;
     K k[SORT_IPT];
     uint32_t v[SORT_IPT];
-    rank_tables_init(sm.s.rt);
+    tables_clear<SORT_NW, 256>(sm.s.tab);
 #pragma unroll
     for (int r = 0; r < SORT_IPT; ++r) {
         const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
@@ -123,61 +160,89 @@ __global__ __launch_bounds__(SORT_NT) void k_sort_pivots(Batch<K> b)
         if (p < cnt) { b.piv[nd.piv + p] = k[r]; sm.k64[p] = (uint64_t)k[r]; }
     }
     __syncthreads();
-    for (uint32_t p = threadIdx.x; p < cnt; p += SORT_NT)
-        b.strict[nd.piv + p] = (p + 1 < cnt && sm.k64[p] == sm.k64[p + 1]) ? 1 : 0;
+    for (uint32_t t = threadIdx.x; t < cnt; t += SORT_NT)
+        b.strict[nd.piv + t] = (t + 1 < cnt && sm.k64[t] == sm.k64[t + 1]) ? 1 : 0;
+}
+
+// ... and one wave per node with at most WCAP pivots.
+template <class K>
+__global__ __launch_bounds__(SM_NW * WAVE) void k_sort_pivots_small(Batch<K> b)
+{
+    __shared__ WaveSmem<WR> wsm[SM_NW];
+    const uint32_t w = wave_id(), l = lane_id();
+    for (int i = l; i < 256; i += WAVE) wsm[w].tab[i] = RankEnt{0u, 0u, 0u, 0u};
+    wave_lds_sync();
+    const uint32_t slot = blockIdx.x * SM_NW + w;
+    if (slot >= b.NS) return;
+    const NodeDesc nd = b.nodes[b.smlIdx[slot]];
+    const uint32_t cnt = nd.m - 1;
+    K k[WR];
+    uint32_t v[WR];
+#pragma unroll
+    for (int r = 0; r < WR; ++r) {
+        const uint32_t p = r * WAVE + l;
+        k[r] = p < cnt ? b.piv[nd.piv + p] : (K)0;
+    }
+    wave_sort<K, false, WR>(k, v, cnt, wsm[w]);
+    // strict: the next pivot (lane l+1, or lane 0 of the next row) is equal
+#pragma unroll
+    for (int r = 0; r < WR; ++r) {
+        const uint32_t p = r * WAVE + l;
+        K nx = __shfl_down(k[r], 1, WAVE);
+        const K first_next = __shfl(k[r + 1 < WR ? r + 1 : r], 0, WAVE);
+        if (l == WAVE - 1) nx = first_next;
+        if (p < cnt) {
+            b.piv[nd.piv + p] = k[r];
+            b.strict[nd.piv + p] = (p + 1 < cnt && nx == k[r]) ? 1 : 0;
+        }
+    }
 }
 
 // ------------------------------------------------------------ column phase
-// One work-group per (node, column group).  Each column of the group is
-// sorted in LDS (base case of the column children) unless the columns were
-// already sorted by deeper recursion; then the sorted column is merged with
-// the pivots by a galloping search per pivot.
+__device__ inline uint32_t column_len(uint32_t i, uint32_t m, uint32_t n)
+{
+    const uint64_t lo = (uint64_t)i * m;
+    return lo < n ? (uint32_t)min((uint64_t)m, (uint64_t)n - lo) : 0u;
+}
+
+// Nodes with m > WCAP: one work-group per (node, column group).  Each column
+// is sorted in LDS (base case) unless deeper recursion already sorted it;
+// then every pivot finds, by a galloping search in the sorted column, how
+// many keys are at-or-below it.  Summed over the group these positions give
+// the group's bucket counts.
 template <class K, bool HV>
-__global__ __launch_bounds__(SORT_NT) void k_colsort(Batch<K> b, const K *src, const uint32_t *vsrc,
-                                                      K *dst, uint32_t *vdst, uint32_t cutoff)
+__global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *src, const uint32_t *vsrc,
+                                                          K *dst, uint32_t *vdst, uint32_t cutoff)
 {
     __shared__ SortSm sm;
-    const uint32_t k = find_node(b.grpStart, b.N, blockIdx.x);
-    const NodeDesc nd = b.nodes[k];
-    const uint32_t g = blockIdx.x - b.grpStart[k];
+    const uint32_t bi = find_node(b.bigGrp, b.NB, blockIdx.x);
+    const NodeDesc nd = b.nodes[b.bigIdx[bi]];
+    const uint32_t g = blockIdx.x - b.bigGrp[bi];
     const uint32_t m = nd.m, n = nd.n, npiv = m - 1;
     const uint32_t i0 = g * TG;
     const uint32_t ncol = min((uint32_t)TG, m - i0);
-    const bool cols_recursed = nd.flags & NODE_COLS_SORTED;
+    const bool recursed = nd.flags & NODE_COLS_RECURSED;
     const uint32_t ppt = (npiv + SORT_NT - 1) / SORT_NT;   // <= SORT_IPT
     const uint32_t t0 = threadIdx.x * ppt;
 
-    K pv[SORT_IPT];
-    bool ps[SORT_IPT];
     uint32_t P[SORT_IPT];
 #pragma unroll
-    for (int q = 0; q < SORT_IPT; ++q) {
-        const uint32_t t = t0 + q;
-        const bool ok = q < (int)ppt && t < npiv;
-        pv[q] = ok ? b.piv[nd.piv + t] : (K)0;
-        ps[q] = ok ? b.strict[nd.piv + t] != 0 : false;
-        P[q] = 0;
-    }
-    rank_tables_init(sm.s.rt);
-    __syncthreads();
+    for (int q = 0; q < SORT_IPT; ++q) P[q] = 0;
 
     uint32_t total = 0;
     for (uint32_t c = 0; c < ncol; ++c) {
         const uint32_t i = i0 + c;
-        const uint64_t lo = (uint64_t)i * m;
-        const uint32_t len = lo < n ? (uint32_t)min((uint64_t)m, (uint64_t)n - lo) : 0u;
+        const uint32_t len = column_len(i, m, n);
         total += len;
-        if (len == 0) {
+        if (len == 0) {                                   // uniform over the work-group
             for (uint32_t J = threadIdx.x; J <= nd.nJ; J += SORT_NT) b.srcOff[nd.src + (uint64_t)J * m + i] = 0;
             continue;
         }
-        // columns larger than the cut-off were sorted by their own recursion
-        const bool sorted = cols_recursed && len > cutoff;
+        const bool sorted = recursed && len > cutoff;   // sorted by its own recursion
+        const uint64_t base = nd.off + (uint64_t)i * m;
         K kk[SORT_IPT];
         uint32_t vv[SORT_IPT];
-        const uint64_t base = nd.off + lo;
-        rank_tables_init(sm.s.rt);        // the previous column's search reused this LDS
-        __syncthreads();
+        tables_clear<SORT_NW, 256>(sm.s.tab);           // the previous search reused this LDS
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
             const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
@@ -185,6 +250,7 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort(Batch<K> b, const K *src, c
             kk[r] = ok ? (sorted ? dst[base + p] : src[base + p]) : (K)0;
             if (HV) vv[r] = ok && !sorted ? vsrc[base + p] : 0u;
         }
+        __syncthreads();
         if (!sorted) {
             block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm);
 #pragma unroll
@@ -203,36 +269,33 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort(Batch<K> b, const K *src, c
             if (p < len) { if (sizeof(K) == 4) sm.k32[p] = (uint32_t)kk[r]; else sm.k64[p] = (uint64_t)kk[r]; }
         }
         __syncthreads();
-        // merge with the pivots: pos = number of keys at-or-below pivot t
         uint32_t prev = 0;
-#pragma unroll
-        for (int q = 0; q < SORT_IPT; ++q) {
+        for (uint32_t q = 0; q < ppt; ++q) {
             const uint32_t t = t0 + q;
-            if (q < (int)ppt && t < npiv) {
-                uint32_t a, e;
-                if (q == 0) { a = 0; e = len; }
-                else {
-                    // gallop from the previous answer
-                    a = prev; e = len;
-                    uint32_t step = 1;
-                    while (true) {
-                        const uint32_t c2 = a + step - 1;
-                        if (c2 >= len) break;
-                        const K x = sizeof(K) == 4 ? (K)sm.k32[c2] : (K)sm.k64[c2];
-                        if (!le_pivot(x, pv[q], ps[q])) { e = c2; break; }
-                        a = c2 + 1;
-                        step <<= 1;
-                    }
+            if (t >= npiv) break;
+            const K pv = b.piv[nd.piv + t];
+            const bool ps = b.strict[nd.piv + t] != 0;
+            uint32_t a = prev, e = len;
+            if (q > 0) {                                  // gallop from the previous answer
+                uint32_t step = 1;
+                while (true) {
+                    const uint32_t c2 = a + step - 1;
+                    if (c2 >= len) break;
+                    const K x = sizeof(K) == 4 ? (K)sm.k32[c2] : (K)sm.k64[c2];
+                    if (!le_pivot(x, pv, ps)) { e = c2; break; }
+                    a = c2 + 1;
+                    step <<= 1;
                 }
-                while (a < e) {
-                    const uint32_t mid = (a + e) >> 1;
-                    const K x = sizeof(K) == 4 ? (K)sm.k32[mid] : (K)sm.k64[mid];
-                    if (le_pivot(x, pv[q], ps[q])) a = mid + 1; else e = mid;
-                }
-                prev = a;
-                P[q] += a;
-                if ((t + 1) % TB == 0) b.srcOff[nd.src + (uint64_t)((t + 1) / TB) * m + i] = a;
             }
+            while (a < e) {
+                const uint32_t mid = (a + e) >> 1;
+                const K x = sizeof(K) == 4 ? (K)sm.k32[mid] : (K)sm.k64[mid];
+                if (le_pivot(x, pv, ps)) a = mid + 1; else e = mid;
+            }
+            prev = a;
+#pragma unroll
+            for (int qq = 0; qq < SORT_IPT; ++qq) if (qq == (int)q) P[qq] += a;
+            if ((t + 1) % TB == 0) b.srcOff[nd.src + (uint64_t)((t + 1) / TB) * m + i] = a;
         }
         if (threadIdx.x == 0) {
             b.srcOff[nd.src + i] = 0;
@@ -249,12 +312,95 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort(Batch<K> b, const K *src, c
     }
     __syncthreads();
     uint32_t *blk = b.blk + nd.blk + (uint64_t)g * m;
-#pragma unroll
-    for (int q = 0; q < SORT_IPT; ++q) {
-        const uint32_t t = t0 + q;
-        if (q < (int)ppt && t < npiv) blk[t] = P[q] - (t > 0 ? Pl[t - 1] : 0u);
-    }
+    for (uint32_t t = threadIdx.x; t < npiv; t += SORT_NT) blk[t] = Pl[t] - (t > 0 ? Pl[t - 1] : 0u);
     if (threadIdx.x == 0) blk[m - 1] = total - (npiv > 0 ? Pl[npiv - 1] : 0u);
+}
+
+// Nodes with m <= WCAP: one work-group of SM_NW waves per (node, column
+// group), one wave per column.  Every key finds its bucket by a binary search
+// over the node's pivots in LDS; the group's bucket counts are LDS atomic
+// adds (commutative, so the counts do not depend on order) and the column's
+// bucket-block offsets are read off where the bucket index crosses a block.
+template <class K, bool HV>
+__global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, const K *src, const uint32_t *vsrc,
+                                                                 K *dst, uint32_t *vdst, uint32_t cutoff)
+{
+    __shared__ WaveSmem<WR> wsm[SM_NW];
+    __shared__ K spiv[WCAP];
+    __shared__ uint8_t sst[WCAP];
+    __shared__ uint32_t hist[WCAP];
+    const uint32_t si = find_node(b.smlGrp, b.NS, blockIdx.x);
+    const NodeDesc nd = b.nodes[b.smlIdx[si]];
+    const uint32_t g = blockIdx.x - b.smlGrp[si];
+    const uint32_t m = nd.m, n = nd.n, npiv = m - 1, nJ = nd.nJ;
+    const uint32_t i0 = g * TG, ncol = min((uint32_t)TG, m - i0);
+    const bool recursed = nd.flags & NODE_COLS_RECURSED;
+    const uint32_t w = wave_id(), l = lane_id();
+
+    for (uint32_t t = threadIdx.x; t < m; t += SM_NW * WAVE) {
+        if (t < npiv) { spiv[t] = b.piv[nd.piv + t]; sst[t] = b.strict[nd.piv + t]; }
+        hist[t] = 0;
+    }
+    for (int i = l; i < 256; i += WAVE) wsm[w].tab[i] = RankEnt{0u, 0u, 0u, 0u};
+    __syncthreads();
+
+    for (uint32_t c = w; c < ncol; c += SM_NW) {
+        const uint32_t i = i0 + c;
+        const uint32_t len = __builtin_amdgcn_readfirstlane(column_len(i, m, n));
+        uint32_t *so = b.srcOff + nd.src + i;              // so[J*m]
+        if (len == 0) {
+            for (uint32_t J = l; J <= nJ; J += WAVE) so[(uint64_t)J * m] = 0;
+        } else {
+        const bool sorted = recursed && len > cutoff;
+        const uint64_t base = nd.off + (uint64_t)i * m;
+        K kk[WR];
+        uint32_t vv[WR];
+#pragma unroll
+        for (int r = 0; r < WR; ++r) {
+            const uint32_t p = r * WAVE + l;
+            const bool ok = p < len;
+            kk[r] = ok ? (sorted ? dst[base + p] : src[base + p]) : (K)0;
+            if (HV) vv[r] = ok && !sorted ? vsrc[base + p] : 0u;
+        }
+        if (!sorted) {
+            wave_sort<K, HV, WR>(kk, vv, len, wsm[w]);
+#pragma unroll
+            for (int r = 0; r < WR; ++r) {
+                const uint32_t p = r * WAVE + l;
+                if (p < len) {
+                    dst[base + p] = kk[r];
+                    if (HV) vdst[base + p] = vv[r];
+                }
+            }
+        }
+        // counting: bucket of every key; block offsets where the bucket crosses a block
+        const int nrows = (int)((len + WAVE - 1) / WAVE);
+        uint32_t carry = 0xFFFFFFFFu;                      // bucket of the previous row's last key
+#pragma unroll
+        for (int r = 0; r < WR; ++r) {
+            if (r < nrows) {
+                const uint32_t p = r * WAVE + l;
+                const bool ok = p < len;
+                const uint32_t bk = ok ? bucket_search(kk[r], spiv, sst, npiv) : 0xFFFFFFFFu;
+                if (ok) atomicAdd(&hist[bk], 1u);
+                uint32_t bp = __shfl_up(bk, 1, WAVE);
+                if (l == 0) bp = carry;
+                carry = __shfl(bk, WAVE - 1, WAVE);
+                if (ok) {
+                    const uint32_t Ja = (p == 0) ? 1u : bp / TB + 1;
+                    const uint32_t Jb = min(bk / TB, nJ - 1);
+                    for (uint32_t J = Ja; J <= Jb; ++J) so[(uint64_t)J * m] = p;
+                    if (p == len - 1)
+                        for (uint32_t J = max(bk / TB + 1, 1u); J < nJ; ++J) so[(uint64_t)J * m] = len;
+                }
+            }
+        }
+        if (l == 0) { so[0] = 0; so[(uint64_t)nJ * m] = len; }
+        }
+    }
+    __syncthreads();
+    uint32_t *blk = b.blk + nd.blk + (uint64_t)g * m;
+    for (uint32_t t = threadIdx.x; t < m; t += SM_NW * WAVE) blk[t] = hist[t];
 }
 
 // Per node and bucket j: exclusive prefix of the group counts over groups
@@ -315,7 +461,8 @@ __global__ __launch_bounds__(1024) void k_bucket_start(Batch<K> b, unsigned long
 // column's keys of bucket j in sorted order.  Tiles larger than one chunk
 // are processed chunk by chunk in column order, which keeps that order.
 template <class K> struct TileSmem {
-    RankTables<TR_NW, TB> rt;
+    RankEnt tab[TR_NW][TB];
+    uint32_t wsum[TR_NW];
     uint32_t buf[TR_CH];
     uint8_t jl[TR_CH];
     uint32_t cOff[TG + 1];
@@ -341,7 +488,7 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
     const uint32_t npv = (j0 + nb <= m - 1) ? nb : nb - 1;   // real pivots of the block
     const uint32_t tid = threadIdx.x;
 
-    rank_tables_init(sm.rt);
+    tables_clear<TR_NW, TB>(sm.tab);
     if (tid < WAVE) {                      // one wave builds the run table
         uint32_t a = 0, len = 0;
         if (tid < ncol) {
@@ -359,74 +506,82 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
     }
     __syncthreads();
     const uint32_t N = sm.cOff[ncol];
+    RankEnt *tab = sm.tab[wave_id()];
 
     for (uint32_t q0 = 0; q0 < N; q0 += TR_CH) {
         const uint32_t chN = min((uint32_t)TR_CH, N - q0);
+        const int nrows = wave_rows<TR_IPT>(chN);
         K kk[TR_IPT];
         uint32_t vv[TR_IPT], dig[TR_IPT], pos[TR_IPT];
 #pragma unroll
         for (int r = 0; r < TR_IPT; ++r) {
-            const uint32_t p = item_pos<TR_NW, TR_IPT>(r);
-            kk[r] = (K)0;
-            vv[r] = 0;
             dig[r] = TB - 1;
-            if (p < chN) {
-                const uint32_t q = q0 + p;
-                uint32_t lo = 0, hi = ncol - 1;          // last column whose run starts at or before q
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1;
-                    if (sm.cOff[mid] <= q) lo = mid; else hi = mid - 1;
+            if (r < nrows) {
+                const uint32_t p = item_pos<TR_NW, TR_IPT>(r);
+                kk[r] = (K)0;
+                vv[r] = 0;
+                if (p < chN) {
+                    const uint32_t q = q0 + p;
+                    uint32_t lo = 0, hi = ncol - 1;          // last column whose run starts at or before q
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi + 1) >> 1;
+                        if (sm.cOff[mid] <= q) lo = mid; else hi = mid - 1;
+                    }
+                    const uint64_t rel = (uint64_t)(i0 + lo) * m + sm.aOf[lo] + (q - sm.cOff[lo]);
+                    const uint64_t at = nd.off + (rel < nd.n ? rel : 0);   // guard: inside the node
+                    kk[r] = src[at];
+                    if (HV) vv[r] = vsrc[at];
+                    dig[r] = bucket_search(kk[r], sm.piv, sm.st, npv);
                 }
-                const uint64_t rel = (uint64_t)(i0 + lo) * m + sm.aOf[lo] + (q - sm.cOff[lo]);
-                const uint64_t at = nd.off + (rel < nd.n ? rel : 0);   // guard: stays inside the node
-                kk[r] = src[at];
-                if (HV) vv[r] = vsrc[at];
-                uint32_t a = 0, e = npv;                  // bucket within the block
-                while (a < e) {
-                    const uint32_t mid = (a + e) >> 1;
-                    if (le_pivot(kk[r], sm.piv[mid], sm.st[mid] != 0)) e = mid; else a = mid + 1;
-                }
-                dig[r] = a;
+                pos[r] = rank_row(tab, dig[r]);
             }
         }
-        rank_digits<TR_NW, TR_IPT, TB>(dig, pos, sm.rt);
+        __syncthreads();
+        scan_tables<TR_NW, TB>(sm.tab, sm.wsum);
+#pragma unroll
+        for (int r = 0; r < TR_IPT; ++r) if (r < nrows) pos[r] += tab[dig[r]].off;
 #pragma unroll
         for (int wd = 0; wd < T::WORDS; ++wd) {
 #pragma unroll
             for (int r = 0; r < TR_IPT; ++r) {
-                sm.buf[pos[r]] = T::word(kk[r], wd);
-                if (wd == 0) sm.jl[pos[r]] = (uint8_t)dig[r];
+                if (r < nrows) {
+                    sm.buf[pos[r]] = T::word(kk[r], wd);
+                    if (wd == 0) sm.jl[pos[r]] = (uint8_t)dig[r];
+                }
             }
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < TR_IPT; ++r) kk[r] = T::set_word(kk[r], wd, sm.buf[item_pos<TR_NW, TR_IPT>(r)]);
+            for (int r = 0; r < TR_IPT; ++r)
+                if (r < nrows) kk[r] = T::set_word(kk[r], wd, sm.buf[item_pos<TR_NW, TR_IPT>(r)]);
             __syncthreads();
         }
         if (HV) {
 #pragma unroll
-            for (int r = 0; r < TR_IPT; ++r) sm.buf[pos[r]] = vv[r];
+            for (int r = 0; r < TR_IPT; ++r) if (r < nrows) sm.buf[pos[r]] = vv[r];
             __syncthreads();
 #pragma unroll
-            for (int r = 0; r < TR_IPT; ++r) vv[r] = sm.buf[item_pos<TR_NW, TR_IPT>(r)];
+            for (int r = 0; r < TR_IPT; ++r) if (r < nrows) vv[r] = sm.buf[item_pos<TR_NW, TR_IPT>(r)];
             __syncthreads();
         }
+        // digit d of this chunk starts at tab[0][d].off (wave 0, the first in order)
 #pragma unroll
         for (int r = 0; r < TR_IPT; ++r) {
-            const uint32_t p = item_pos<TR_NW, TR_IPT>(r);
-            if (p < chN) {
-                const uint32_t d = sm.jl[p];
-                const uint64_t rel = (uint64_t)sm.dstb[d] + (p - sm.rt.offs[0][d]);
-                if (rel < nd.n) {                                        // guard: stays inside the node
-                    dst[nd.off + rel] = kk[r];
-                    if (HV) vdst[nd.off + rel] = vv[r];
+            if (r < nrows) {
+                const uint32_t p = item_pos<TR_NW, TR_IPT>(r);
+                if (p < chN) {
+                    const uint32_t d = sm.jl[p];
+                    const uint64_t rel = (uint64_t)sm.dstb[d] + (p - sm.tab[0][d].off);
+                    if (rel < nd.n) {                                        // guard: inside the node
+                        dst[nd.off + rel] = kk[r];
+                        if (HV) vdst[nd.off + rel] = vv[r];
+                    }
                 }
             }
         }
         __syncthreads();
         if (tid < nb) {
-            const uint32_t end = tid + 1 < TB ? sm.rt.offs[0][tid + 1] : (uint32_t)TR_CH;
-            const uint32_t c = min(end, chN) - min(sm.rt.offs[0][tid], chN);
-            sm.dstb[tid] += c;
+            const uint32_t end = tid + 1 < TB ? sm.tab[0][tid + 1].off : (uint32_t)TR_CH;
+            sm.dstb[tid] += min(end, chN) - min(sm.tab[0][tid].off, chN);
         }
         __syncthreads();
     }
@@ -478,47 +633,121 @@ __device__ inline bool single_value_bucket(const Batch<K> &b, const NodeDesc &nd
     return lo == hi;
 }
 
-template <class K, bool HV>
-__global__ __launch_bounds__(SORT_NT) void k_bucket(Batch<K> b, const K *A, const uint32_t *VA,
-                                                     K *D, uint32_t *VD, uint32_t cutoff)
+// Classify every bucket and append it to its work list (wave-aggregated
+// atomics; list order does not affect any result).
+template <class K>
+__global__ void k_classify(Batch<K> b, uint32_t cutoff)
 {
-    __shared__ SortSm sm;
-    const uint32_t k = find_node(b.bucStart, b.N, blockIdx.x);
-    const NodeDesc nd = b.nodes[k];
-    const uint32_t j = blockIdx.x - b.bucStart[k];
-    const uint32_t lo = b.bs[nd.bkt + j], s = b.bs[nd.bkt + j + 1] - lo;
-    const uint64_t base = nd.off + lo;
-    uint8_t c;
-    if (s == 0) c = 0;
-    else if (single_value_bucket(b, nd, j)) {
-        c = 1;
-        for (uint32_t p = threadIdx.x; p < s; p += SORT_NT) {
+    const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+    int cls = -1;
+    BucketItem it{0, 0, 0, 0};
+    if (item < b.bucStart[b.N]) {
+        const uint32_t k = find_node(b.bucStart, b.N, item);
+        const NodeDesc nd = b.nodes[k];
+        const uint32_t j = item - b.bucStart[k];
+        const uint32_t lo = b.bs[nd.bkt + j], s = b.bs[nd.bkt + j + 1] - lo;
+        it = BucketItem{k, j, lo, s};
+        if (s > 0) {
+            if (single_value_bucket(b, nd, j)) cls = CLS_COPY;
+            else if (s <= cutoff) cls = s <= (uint32_t)WCAP ? CLS_SMALL : CLS_MID;
+            else cls = CLS_INTERNAL;
+        }
+    }
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) {
+        const unsigned long long m = __ballot(cls == c);
+        if (m == 0) continue;
+        uint32_t base = 0;
+        const uint32_t leader = __ffsll((long long)m) - 1;
+        if (l == leader) base = atomicAdd(&b.ctr[c], (uint32_t)__popcll(m));
+        base = __shfl(base, leader, WAVE);
+        if (cls == c) {
+            const uint32_t at = base + rank_in_mask((uint32_t)m, (uint32_t)(m >> 32));
+            if (at < b.cap[c]) b.list[c][at] = it;
+        }
+    }
+}
+
+// Single-value buckets: copy A -> D (one work-group per bucket, persistent).
+template <class K, bool HV>
+__global__ __launch_bounds__(256) void k_bucket_copy(Batch<K> b, const K *A, const uint32_t *VA, K *D, uint32_t *VD)
+{
+    const uint32_t cnt = min(b.ctr[CLS_COPY], b.cap[CLS_COPY]);
+    for (uint32_t it = blockIdx.x; it < cnt; it += gridDim.x) {
+        const BucketItem e = b.list[CLS_COPY][it];
+        const uint64_t base = b.nodes[e.node].off + e.lo;
+        for (uint32_t p = threadIdx.x; p < e.size; p += 256) {
             D[base + p] = A[base + p];
             if (HV) VD[base + p] = VA[base + p];
         }
-    } else if (s <= cutoff) {
-        c = 2;
-        K kk[SORT_IPT];
-        uint32_t vv[SORT_IPT];
-        rank_tables_init(sm.s.rt);
+    }
+}
+
+// Buckets of at most WCAP keys: one wave per bucket (persistent).
+template <class K, bool HV>
+__global__ __launch_bounds__(SM_NW * WAVE) void k_bucket_small(Batch<K> b, const K *A, const uint32_t *VA,
+                                                               K *D, uint32_t *VD)
+{
+    __shared__ WaveSmem<WR> wsm[SM_NW];
+    const uint32_t w = wave_id(), l = lane_id();
+    for (int i = l; i < 256; i += WAVE) wsm[w].tab[i] = RankEnt{0u, 0u, 0u, 0u};
+    wave_lds_sync();
+    const uint32_t cnt = min(b.ctr[CLS_SMALL], b.cap[CLS_SMALL]);
+    for (uint32_t it = blockIdx.x * SM_NW + w; it < cnt; it += gridDim.x * SM_NW) {
+        const BucketItem e = b.list[CLS_SMALL][it];
+        const uint64_t base = b.nodes[e.node].off + e.lo;
+        K kk[WR];
+        uint32_t vv[WR];
 #pragma unroll
-        for (int r = 0; r < SORT_IPT; ++r) {
-            const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-            kk[r] = p < s ? A[base + p] : (K)0;
-            if (HV) vv[r] = p < s ? VA[base + p] : 0u;
+        for (int r = 0; r < WR; ++r) {
+            const uint32_t p = r * WAVE + l;
+            kk[r] = p < e.size ? A[base + p] : (K)0;
+            if (HV) vv[r] = p < e.size ? VA[base + p] : 0u;
         }
-        __syncthreads();
-        block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, s, sm);
+        wave_sort<K, HV, WR>(kk, vv, e.size, wsm[w]);
 #pragma unroll
-        for (int r = 0; r < SORT_IPT; ++r) {
-            const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-            if (p < s) {
+        for (int r = 0; r < WR; ++r) {
+            const uint32_t p = r * WAVE + l;
+            if (p < e.size) {
                 D[base + p] = kk[r];
                 if (HV) VD[base + p] = vv[r];
             }
         }
-    } else c = 3;
-    if (threadIdx.x == 0) b.cls[nd.bkt + j] = c;
+    }
+}
+
+// Buckets of WCAP+1 .. cutoff keys: one work-group per bucket (persistent).
+template <class K, bool HV>
+__global__ __launch_bounds__(SORT_NT) void k_bucket_mid(Batch<K> b, const K *A, const uint32_t *VA,
+                                                        K *D, uint32_t *VD)
+{
+    __shared__ SortSm sm;
+    tables_clear<SORT_NW, 256>(sm.s.tab);
+    __syncthreads();
+    const uint32_t cnt = min(b.ctr[CLS_MID], b.cap[CLS_MID]);
+    for (uint32_t it = blockIdx.x; it < cnt; it += gridDim.x) {
+        const BucketItem e = b.list[CLS_MID][it];
+        const uint64_t base = b.nodes[e.node].off + e.lo;
+        K kk[SORT_IPT];
+        uint32_t vv[SORT_IPT];
+#pragma unroll
+        for (int r = 0; r < SORT_IPT; ++r) {
+            const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
+            kk[r] = p < e.size ? A[base + p] : (K)0;
+            if (HV) vv[r] = p < e.size ? VA[base + p] : 0u;
+        }
+        block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, e.size, sm);
+#pragma unroll
+        for (int r = 0; r < SORT_IPT; ++r) {
+            const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
+            if (p < e.size) {
+                D[base + p] = kk[r];
+                if (HV) VD[base + p] = vv[r];
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // A whole (sub)array that is a base case: n <= cutoff, one work-group.
@@ -529,7 +758,7 @@ __global__ __launch_bounds__(SORT_NT) void k_base_sort(uint32_t n, const K *A, c
     __shared__ SortSm sm;
     K kk[SORT_IPT];
     uint32_t vv[SORT_IPT];
-    rank_tables_init(sm.s.rt);
+    tables_clear<SORT_NW, 256>(sm.s.tab);
 #pragma unroll
     for (int r = 0; r < SORT_IPT; ++r) {
         const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);

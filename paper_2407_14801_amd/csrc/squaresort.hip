@@ -13,7 +13,12 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/squaresort.h"
@@ -21,6 +26,42 @@
 
 namespace sqs {
 namespace {
+
+// ------------------------------------------------------------ kernel timing
+// Optional per-kernel timing: HIP events recorded on the launch stream around
+// every launch, resolved at the call's synchronisation points.
+struct Timing {
+    bool on = false;
+    std::mutex mu;
+    struct Acc { double ms = 0; uint64_t launches = 0, units = 0; };
+    std::map<std::string, Acc> acc;   // per kernel: time, launches, keys processed
+    struct Pending { const char *name; hipEvent_t a, b; uint64_t units; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get()
+    {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void resolve()
+    {
+        for (auto &p : pending) {
+            float ms = 0.f;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                auto &e = acc[p.name];
+                e.ms += ms;
+                e.launches += 1;
+                e.units += p.units;
+            }
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pending.clear();
+    }
+};
+Timing g_timing;
 
 // ------------------------------------------------------------ host helpers
 uint64_t ceil_isqrt_host(uint64_t n)
@@ -34,6 +75,13 @@ uint64_t ceil_isqrt_host(uint64_t n)
 }
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// SQS_DEBUG=1 in the environment prints one line per recursion step
+bool debug_on()
+{
+    static const bool on = [] { const char *e = getenv("SQS_DEBUG"); return e && *e && *e != '0'; }();
+    return on;
+}
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
 struct HostNode {
@@ -62,8 +110,8 @@ uint64_t node_meta_bytes(uint64_t n, uint64_t key_bytes)
 {
     const uint64_t m = ceil_isqrt_host(n);
     const uint64_t groups = cdiv(m, TG), nJ = cdiv(m, TB);
-    return sizeof(NodeDesc) + 5 * 4 + (m - 1) * (key_bytes + 1) + 4 * m * (nJ + 1) +
-           4 * groups * m + 4 * (m + 1) + 4 * m + m + 8;
+    return sizeof(NodeDesc) + 7 * 4 + (m - 1) * (key_bytes + 1) + 4 * m * (nJ + 1) +
+           4 * groups * m + 4 * (m + 1) + 4 * m + 4 * sizeof(BucketItem) * m + 8;
 }
 
 // Upper bound of the metadata of one batch whose nodes are disjoint ranges of
@@ -77,9 +125,9 @@ uint64_t batch_bound(uint64_t S, uint64_t C, uint64_t key_bytes)
     const uint64_t big = node_meta_bytes(S, key_bytes);
     const uint64_t nodes = S / (C + 1) + 1;
     const uint64_t sq = ceil_isqrt_host(C + 1);
-    const uint64_t per_m = key_bytes + 1 + 4 * 2 + 4 + 4 + 4 + 1 + 8;   // generous
+    const uint64_t per_m = key_bytes + 1 + 4 * 2 + 4 + 4 + 4 + 4 * sizeof(BucketItem) + 8;   // generous
     return big + nodes * (sizeof(NodeDesc) + 64 + 4 * per_m) + (S / sq + nodes) * per_m * 2 +
-           S / 8 + 16 * 256;
+           S / 8 + 32 * 256;
 }
 
 uint64_t workspace_bound(uint64_t n, uint64_t C, uint64_t key_bytes)
@@ -112,18 +160,54 @@ template <class K, bool HV> struct Engine {
 
     int check() const { return hipGetLastError() == hipSuccess ? SQS_OK : SQS_ERR_DEVICE; }
 
+    // launch f() on st, bracketed by timing events when timing is enabled
+    int cur_depth = 0;
+    template <class F> void launch(const char *name0, uint64_t units, F f)
+    {
+        if (!g_timing.on) { f(); return; }
+        // kernels of deeper recursion steps are reported as name@d
+        static thread_local std::string tmp;
+        tmp = name0;
+        if (cur_depth > 0) tmp += "@" + std::to_string(cur_depth);
+        const char *name = intern(tmp);
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        hipEvent_t a = g_timing.get(), b = g_timing.get();
+        if (a) hipEventRecord(a, st);
+        f();
+        if (b) hipEventRecord(b, st);
+        if (a && b) g_timing.pending.push_back({name, a, b, units});
+    }
+    void resolve_timing()
+    {
+        if (!g_timing.on) return;
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        g_timing.resolve();
+    }
+
+    static const char *intern(const std::string &s)
+    {
+        static std::mutex mu;
+        static std::vector<std::string *> names;
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto *p : names) if (*p == s) return p->c_str();
+        names.push_back(new std::string(s));
+        return names.back()->c_str();
+    }
+
     int run_batch(const std::vector<HostNode> &nodes, int depth)
     {
         if (depth >= SQS_MAX_DEPTH) return SQS_ERR_DEPTH;
+        cur_depth = depth;
         const uint32_t N = (uint32_t)nodes.size();
         const uint64_t mark = ws.top;
 
         // ---- plan the batch on the host
         std::vector<NodeDesc> desc(N);
-        std::vector<uint32_t> pfx(5 * (N + 1), 0);
-        uint32_t *pivS = &pfx[0], *grpS = &pfx[N + 1], *tileS = &pfx[2 * (N + 1)],
-                 *bucS = &pfx[3 * (N + 1)], *digS = &pfx[4 * (N + 1)];
-        uint64_t srcTot = 0, blkTot = 0;
+        // prefixes: piv, tile, buc, dig (N+1 each), then big/small index lists and group prefixes
+        std::vector<uint32_t> bigIdx, smlIdx, bigGrp{0}, smlGrp{0};
+        std::vector<uint32_t> pfx(4 * (N + 1), 0);
+        uint32_t *pivS = &pfx[0], *tileS = &pfx[(N + 1)], *bucS = &pfx[2 * (N + 1)], *digS = &pfx[3 * (N + 1)];
+        uint64_t srcTot = 0, blkTot = 0, keysTot = 0;
         uint32_t bktTot = 0;
         std::vector<HostNode> col_kids;
         for (uint32_t k = 0; k < N; ++k) {
@@ -141,77 +225,109 @@ template <class K, bool HV> struct Engine {
             d.blk = blkTot;
             d.flags = 0;
             d.pad = 0;
-            if (d.m > (uint32_t)SORT_CAP) return SQS_ERR_UNSUPPORTED;   // a column is sorted by one work-group
+            if (d.m > (uint32_t)SORT_CAP) {                                 // a column is sorted by one work-group
+                if (debug_on()) fprintf(stderr, "[sqs] depth %d node %u: n=%u m=%u unsupported\n", depth, k, h.n, d.m);
+                return SQS_ERR_UNSUPPORTED;
+            }
             if (!skew_only && d.m > cutoff) {
-                d.flags |= NODE_COLS_SORTED;
+                d.flags |= NODE_COLS_RECURSED;
                 for (uint32_t i = 0; i < d.m; ++i) {
                     const uint64_t lo = (uint64_t)i * d.m;
                     if (lo >= h.n) break;
                     const uint32_t len = (uint32_t)std::min<uint64_t>(d.m, h.n - lo);
-                    // a short tail column may be a base case (sorted by k_colsort)
+                    // a short tail column may be a base case (sorted by the column kernel)
                     if (len > cutoff) col_kids.push_back({h.off + lo, len, node_child_key(h.key, 0, i)});
                 }
             }
+            if (d.m > (uint32_t)WCAP) { bigIdx.push_back(k); bigGrp.push_back(bigGrp.back() + d.groups); }
+            else { smlIdx.push_back(k); smlGrp.push_back(smlGrp.back() + d.groups); }
             pivS[k + 1] = pivS[k] + (d.m - 1);
-            grpS[k + 1] = grpS[k] + d.groups;
             tileS[k + 1] = tileS[k] + d.groups * d.nJ;
             bucS[k + 1] = bucS[k] + d.m;
             digS[k + 1] = digS[k] + cdiv(h.n, 16384);
             bktTot += d.m + 1;
+            keysTot += h.n;
             srcTot += (uint64_t)(d.nJ + 1) * d.m;
             blkTot += (uint64_t)d.groups * d.m;
         }
+        const uint32_t NB = (uint32_t)bigIdx.size(), NS = (uint32_t)smlIdx.size();
+        std::vector<uint32_t> idx;
+        idx.reserve(pfx.size() + 2 * N + 2);
+        idx.insert(idx.end(), pfx.begin(), pfx.end());
+        const size_t oBigIdx = idx.size(); idx.insert(idx.end(), bigIdx.begin(), bigIdx.end());
+        const size_t oBigGrp = idx.size(); idx.insert(idx.end(), bigGrp.begin(), bigGrp.end());
+        const size_t oSmlIdx = idx.size(); idx.insert(idx.end(), smlIdx.begin(), smlIdx.end());
+        const size_t oSmlGrp = idx.size(); idx.insert(idx.end(), smlGrp.begin(), smlGrp.end());
+
+        // work-list capacities: every bucket may be small or single-valued;
+        // mid buckets hold > WCAP keys and internal ones > cutoff keys
+        const uint32_t capSmall = bucS[N], capCopy = bucS[N];
+        const uint32_t capMid = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (WCAP + 1) + 1);
+        const uint32_t capInt = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / ((uint64_t)cutoff + 1) + 1);
 
         // ---- device metadata
         Batch<K> b;
         NodeDesc *dDesc = ws.take<NodeDesc>(N);
-        uint32_t *dPfx = ws.take<uint32_t>(5 * (N + 1));
+        uint32_t *dIdx = ws.take<uint32_t>(idx.size());
         b.piv = ws.take<K>(std::max<uint32_t>(pivS[N], 1));
         b.strict = ws.take<uint8_t>(std::max<uint32_t>(pivS[N], 1));
         b.srcOff = ws.take<uint32_t>(srcTot);
         b.blk = ws.take<uint32_t>(blkTot);
         b.bs = ws.take<uint32_t>(bktTot);
         b.tot = ws.take<uint32_t>(bktTot);
-        b.cls = ws.take<uint8_t>(bktTot);
+        b.list[CLS_COPY] = ws.take<BucketItem>(capCopy);
+        b.list[CLS_SMALL] = ws.take<BucketItem>(capSmall);
+        b.list[CLS_MID] = ws.take<BucketItem>(capMid);
+        b.list[CLS_INTERNAL] = ws.take<BucketItem>(capInt);
+        b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID] = capMid; b.cap[CLS_INTERNAL] = capInt;
+        b.ctr = ws.take<uint32_t>(NCLS);
         b.H = ws.take<unsigned long long>(N);
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         b.nodes = dDesc;
         b.N = N;
-        b.pivStart = dPfx;
-        b.grpStart = dPfx + (N + 1);
-        b.tileStart = dPfx + 2 * (N + 1);
-        b.bucStart = dPfx + 3 * (N + 1);
-        b.digStart = dPfx + 4 * (N + 1);
+        b.pivStart = dIdx;
+        b.tileStart = dIdx + (N + 1);
+        b.bucStart = dIdx + 2 * (N + 1);
+        b.digStart = dIdx + 3 * (N + 1);
+        b.bigIdx = dIdx + oBigIdx; b.bigGrp = dIdx + oBigGrp; b.NB = NB;
+        b.smlIdx = dIdx + oSmlIdx; b.smlGrp = dIdx + oSmlGrp; b.NS = NS;
         if (hipMemcpyAsync(dDesc, desc.data(), N * sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess)
             return SQS_ERR_DEVICE;
-        if (hipMemcpyAsync(dPfx, pfx.data(), pfx.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+        if (hipMemcpyAsync(dIdx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
             return SQS_ERR_DEVICE;
 
         // ---- pivots (drawn from the node inputs before any child clobbers them)
-        if (pivS[N] > 0) k_sample<K><<<cdiv(pivS[N], 256), 256, 0, st>>>(b, A);
-        k_sort_pivots<K><<<N, SORT_NT, 0, st>>>(b);
+        if (pivS[N] > 0) launch("k_sample", pivS[N], [&] { k_sample<K><<<cdiv(pivS[N], 256), 256, 0, st>>>(b, A); });
+        if (NB) launch("k_sort_pivots", pivS[N], [&] { k_sort_pivots_big<K><<<NB, SORT_NT, 0, st>>>(b); });
+        if (NS) launch("k_sort_pivots_w", pivS[N], [&] { k_sort_pivots_small<K><<<cdiv(NS, SM_NW), SM_NW * WAVE, 0, st>>>(b); });
         if (int rc = check()) return rc;
 
         // ---- columns: internal column children first, then sort/count
         if (!col_kids.empty()) {
             if (int rc = run_batch(col_kids, depth + 1)) return rc;
+            cur_depth = depth;
         }
         K *cdst = skew_only ? A : D;
         uint32_t *vcdst = skew_only ? VA : VD;
-        k_colsort<K, HV><<<grpS[N], SORT_NT, 0, st>>>(b, A, VA, cdst, vcdst, cutoff);
-        k_colscan<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b);
-        k_bucket_start<K><<<N, 1024, 0, st>>>(b, skew_only ? skew_bs : nullptr);
+        if (NB) launch("k_colsort", keysTot, [&] {
+            k_colsort_big<K, HV><<<bigGrp.back(), SORT_NT, 0, st>>>(b, A, VA, cdst, vcdst, cutoff); });
+        if (NS) launch("k_colsort_w", keysTot, [&] {
+            k_colsort_small<K, HV><<<smlGrp.back(), SM_NW * WAVE, 0, st>>>(b, A, VA, cdst, vcdst, cutoff); });
+        launch("k_colscan", bucS[N], [&] { k_colscan<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b); });
+        launch("k_bucket_start", bucS[N], [&] { k_bucket_start<K><<<N, 1024, 0, st>>>(b, skew_only ? skew_bs : nullptr); });
         if (int rc = check()) return rc;
 
         // ---- SkewTranspose D -> A (skew mode: A -> out)
         if (skew_only) {
-            k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, A, VA, skew_out, nullptr);
+            launch("k_transpose", keysTot, [&] { k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, A, VA, skew_out, nullptr); });
             ws.top = mark;
             if (int rc = check()) return rc;
             // the host-side plan must outlive its upload
-            return hipStreamSynchronize(st) == hipSuccess ? SQS_OK : SQS_ERR_DEVICE;
+            if (hipStreamSynchronize(st) != hipSuccess) return SQS_ERR_DEVICE;
+            resolve_timing();
+            return SQS_OK;
         }
-        k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, D, VD, A, VA);
+        launch("k_transpose", keysTot, [&] { k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, D, VD, A, VA); });
         if (digest) {
             k_fill_u64<<<cdiv(N, 256), 256, 0, st>>>(b.H, N, 0ull);
             k_digest<K, HV><<<digS[N], 256, 0, st>>>(b, A, VA);
@@ -219,26 +335,50 @@ template <class K, bool HV> struct Engine {
         }
         if (int rc = check()) return rc;
 
-        // ---- buckets A -> D
-        k_bucket<K, HV><<<bucS[N], SORT_NT, 0, st>>>(b, A, VA, D, VD, cutoff);
+        // ---- buckets A -> D, by class
+        k_fill_u32<<<1, 64, 0, st>>>(b.ctr, NCLS, 0u);
+        launch("k_classify", bucS[N], [&] { k_classify<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b, cutoff); });
+        launch("k_bucket_copy", keysTot, [&] { k_bucket_copy<K, HV><<<512, 256, 0, st>>>(b, A, VA, D, VD); });
+        launch("k_bucket_w", keysTot, [&] {
+            k_bucket_small<K, HV><<<std::min<uint32_t>(cdiv(capSmall, SM_NW), 2048), SM_NW * WAVE, 0, st>>>(b, A, VA, D, VD); });
+        launch("k_bucket", keysTot, [&] {
+            k_bucket_mid<K, HV><<<std::min<uint32_t>(capMid, 512), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
         if (int rc = check()) return rc;
 
         // ---- internal buckets form the next batch
-        std::vector<uint32_t> hbs(bktTot);
-        std::vector<uint8_t> hcls(bktTot);
-        if (hipMemcpyAsync(hbs.data(), b.bs, bktTot * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(hcls.data(), b.cls, bktTot, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        std::vector<uint32_t> hctr(NCLS);
+        std::vector<BucketItem> hint(capInt);
+        if (hipMemcpyAsync(hctr.data(), b.ctr, NCLS * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(hint.data(), b.list[CLS_INTERNAL], capInt * sizeof(BucketItem), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return SQS_ERR_DEVICE;
-        std::vector<HostNode> next;
-        for (uint32_t k = 0; k < N; ++k) {
-            const NodeDesc &d = desc[k];
-            for (uint32_t j = 0; j < d.m; ++j)
-                if (hcls[d.bkt + j] == 3) {
-                    const uint32_t lo = hbs[d.bkt + j], hi = hbs[d.bkt + j + 1];
-                    next.push_back({d.off + lo, hi - lo, node_child_key(d.key, 1, j)});
-                }
+        resolve_timing();
+        for (int c = 0; c < NCLS; ++c)
+            if (hctr[c] > b.cap[c]) return SQS_ERR_DEVICE;   // cannot happen: capacities are bounds
+        if (debug_on()) {
+            fprintf(stderr, "[sqs] depth %d: %u nodes, %llu keys; buckets copy %u small %u mid %u internal %u\n",
+                    depth, N, (unsigned long long)keysTot, hctr[0], hctr[1], hctr[2], hctr[3]);
+            if (bktTot <= 64) {
+                std::vector<uint32_t> hb(bktTot), ht(bktTot), hblk(blkTot), hsrc(srcTot);
+                hipMemcpy(hb.data(), b.bs, bktTot * 4, hipMemcpyDeviceToHost);
+                hipMemcpy(ht.data(), b.tot, bktTot * 4, hipMemcpyDeviceToHost);
+                hipMemcpy(hblk.data(), b.blk, blkTot * 4, hipMemcpyDeviceToHost);
+                hipMemcpy(hsrc.data(), b.srcOff, srcTot * 4, hipMemcpyDeviceToHost);
+                fprintf(stderr, "  bs:"); for (auto x : hb) fprintf(stderr, " %u", x);
+                fprintf(stderr, "\n  tot:"); for (auto x : ht) fprintf(stderr, " %u", x);
+                fprintf(stderr, "\n  blk:"); for (auto x : hblk) fprintf(stderr, " %u", x);
+                fprintf(stderr, "\n  src:"); for (auto x : hsrc) fprintf(stderr, " %u", x);
+                fprintf(stderr, "\n");
+            }
         }
+        hint.resize(hctr[CLS_INTERNAL]);
+        std::sort(hint.begin(), hint.end(), [](const BucketItem &x, const BucketItem &y) {
+            return x.node != y.node ? x.node < y.node : x.j < y.j;
+        });
+        std::vector<HostNode> next;
+        next.reserve(hint.size());
+        for (const BucketItem &e : hint)
+            next.push_back({desc[e.node].off + e.lo, e.size, node_child_key(desc[e.node].key, 1, e.j)});
         ws.top = mark;
         if (!next.empty()) return run_batch(next, depth + 1);
         return SQS_OK;
@@ -248,7 +388,8 @@ template <class K, bool HV> struct Engine {
     {
         if (n == 0) return SQS_OK;
         if (n <= cutoff) {
-            k_base_sort<K, HV><<<1, SORT_NT, 0, st>>>((uint32_t)n, A, VA, D, VD);
+            launch("k_base_sort", n, [&] { k_base_sort<K, HV><<<1, SORT_NT, 0, st>>>((uint32_t)n, A, VA, D, VD); });
+            if (g_timing.on && hipStreamSynchronize(st) == hipSuccess) resolve_timing();
             return check();
         }
         std::vector<HostNode> root{{0, (uint32_t)n, splitmix(seed)}};
@@ -374,6 +515,37 @@ int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket
     e.skew_bs = reinterpret_cast<unsigned long long *>(bucket_start);
     std::vector<HostNode> root{{0, (uint32_t)n, splitmix(seed)}};
     return e.run_batch(root, 0);
+}
+
+int sqs_timing_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.resolve();
+    g_timing.acc.clear();
+    g_timing.on = on != 0;
+    return SQS_OK;
+}
+
+int64_t sqs_timing_report(char *buf, uint64_t len)
+{
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.resolve();
+    std::string js = "{";
+    bool first = true;
+    for (auto &kv : g_timing.acc) {
+        char item[256];
+        snprintf(item, sizeof item, "%s\"%s\": [%.6f, %llu, %llu]", first ? "" : ", ", kv.first.c_str(),
+                 kv.second.ms, (unsigned long long)kv.second.launches, (unsigned long long)kv.second.units);
+        js += item;
+        first = false;
+    }
+    js += "}";
+    if (buf && len > 0) {
+        const uint64_t c = std::min<uint64_t>(len - 1, js.size());
+        memcpy(buf, js.data(), c);
+        buf[c] = 0;
+    }
+    return (int64_t)js.size();
 }
 
 const char *sqs_status_string(int s)

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "squaresort.h")
 def _declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int|uint64_t|char|void)\s*\*?\s*(\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:int64_t|uint64_t|int|char|void)\s*\*?\s*(\w+)\s*\(", src, re.M)))
 
 
 @pytest.fixture(scope="module")
