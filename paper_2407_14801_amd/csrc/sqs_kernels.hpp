@@ -60,7 +60,8 @@ constexpr uint32_t NODE_COLS_RECURSED = 1u;
 struct BucketItem {
     uint32_t node, j, lo, size;   // lo: node-local first slot
 };
-enum { CLS_COPY = 0, CLS_SMALL = 1, CLS_MID = 2, CLS_INTERNAL = 3, NCLS = 4 };
+enum { CLS_COPY = 0, CLS_SMALL = 1, CLS_MID = 2, CLS_BIG = 3, CLS_INTERNAL = 4, NCLS = 5 };
+constexpr uint32_t BIG_CAP = 4 * SORT_CAP;   // largest automatic cut-off: 65536 keys
 
 template <class K> struct Batch {
     const NodeDesc *nodes;
@@ -649,8 +650,10 @@ __global__ void k_classify(Batch<K> b, uint32_t cutoff)
         it = BucketItem{k, j, lo, s};
         if (s > 0) {
             if (single_value_bucket(b, nd, j)) cls = CLS_COPY;
-            else if (s <= cutoff) cls = s <= (uint32_t)WCAP ? CLS_SMALL : CLS_MID;
-            else cls = CLS_INTERNAL;
+            else if (s > cutoff) cls = CLS_INTERNAL;
+            else if (s <= (uint32_t)WCAP) cls = CLS_SMALL;
+            else if (s <= (uint32_t)SORT_CAP) cls = CLS_MID;
+            else cls = CLS_BIG;
         }
     }
     const uint32_t l = lane_id();
@@ -745,6 +748,206 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_mid(Batch<K> b, const K *A, 
                 D[base + p] = kk[r];
                 if (HV) VD[base + p] = vv[r];
             }
+        }
+        __syncthreads();
+    }
+}
+
+// Inclusive key bounds of bucket j (see single_value_bucket).
+template <class K>
+__device__ inline void bucket_bounds(const Batch<K> &b, const NodeDesc &nd, uint32_t j, K &lo, K &hi)
+{
+    const K MAXV = (K)KeyT<K>::MAXV;
+    if (j == 0) lo = 0;
+    else { const K s = b.piv[nd.piv + j - 1]; lo = b.strict[nd.piv + j - 1] ? s : (K)(s + 1); }
+    if (j == nd.m - 1) hi = MAXV;
+    else { const K s = b.piv[nd.piv + j]; hi = b.strict[nd.piv + j] ? (K)(s - 1) : s; }
+}
+
+// Buckets of CAP+1 .. cutoff keys (a base case larger than one LDS sort):
+// one work-group per bucket (persistent) runs an MSD radix split through
+// global memory and sorts the parts in LDS.  A split counts the top bits of
+// (x - lo) over the segment, then scatters it stably (chunks in order, LDS
+// ranking inside a chunk) into the other buffer; parts that fit one LDS sort
+// are sorted into D in place, larger ones are split again (A and D alternate
+// as source and target), single-value parts are copied.  The result is the
+// stable sort of the bucket, as any base-case sort must produce.
+struct BigSeg {
+    uint32_t off, size;          // bucket-relative
+    uint32_t in_d;               // segment currently lives in D (else in A)
+    uint32_t pad;
+    uint64_t lo, hi;             // inclusive key range of the segment
+};
+constexpr int BIG_STACK = 256;
+constexpr int SPLIT_BITS = 3;
+
+template <class K, bool HV>
+__global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32_t *VA, K *D, uint32_t *VD)
+{
+    using T = KeyT<K>;
+    __shared__ SortSm sm;
+    __shared__ BigSeg stack[BIG_STACK];
+    __shared__ uint32_t hist[256], base[256], run[256];
+    __shared__ uint32_t sp_sh, overflow_sh;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t cnt = min(b.ctr[CLS_BIG], b.cap[CLS_BIG]);
+    for (uint32_t it = blockIdx.x; it < cnt; it += gridDim.x) {
+        const BucketItem e = b.list[CLS_BIG][it];
+        const NodeDesc nd = b.nodes[e.node];
+        const uint64_t bbase = nd.off + e.lo;
+        if (tid == 0) {
+            K lo, hi;
+            bucket_bounds(b, nd, e.j, lo, hi);
+            stack[0] = BigSeg{0u, e.size, 0u, 0u, (uint64_t)lo, (uint64_t)hi};
+            sp_sh = 1;
+            overflow_sh = 0;
+        }
+        __syncthreads();
+        while (true) {
+            const uint32_t sp = sp_sh;
+            if (sp == 0) break;
+            const BigSeg sg = stack[sp - 1];
+            __syncthreads();
+            if (tid == 0) sp_sh = sp - 1;
+            K *src = sg.in_d ? D : A;
+            uint32_t *vsrc = sg.in_d ? VD : VA;
+            const uint64_t sb = bbase + sg.off;
+            if (sg.size <= (uint32_t)SORT_CAP || sg.lo == sg.hi) {
+                if (sg.lo == sg.hi) {                       // one key value: already in order
+                    if (!sg.in_d)
+                        for (uint32_t p = tid; p < sg.size; p += SORT_NT) {
+                            D[sb + p] = A[sb + p];
+                            if (HV) VD[sb + p] = VA[sb + p];
+                        }
+                } else {
+                    K kk[SORT_IPT];
+                    uint32_t vv[SORT_IPT];
+                    tables_clear<SORT_NW, 256>(sm.s.tab);
+#pragma unroll
+                    for (int r = 0; r < SORT_IPT; ++r) {
+                        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
+                        kk[r] = p < sg.size ? src[sb + p] : (K)0;
+                        if (HV) vv[r] = p < sg.size ? vsrc[sb + p] : 0u;
+                    }
+                    __syncthreads();
+                    block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, sg.size, sm);
+#pragma unroll
+                    for (int r = 0; r < SORT_IPT; ++r) {
+                        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
+                        if (p < sg.size) {
+                            D[sb + p] = kk[r];
+                            if (HV) VD[sb + p] = vv[r];
+                        }
+                    }
+                }
+                __syncthreads();
+                continue;
+            }
+            // ---- split by the top SPLIT_BITS bits of (x - lo)
+            K *dstb = sg.in_d ? A : D;
+            uint32_t *vdstb = sg.in_d ? VA : VD;
+            const K klo = (K)sg.lo;
+            const int bits = T::bitlen((K)((K)sg.hi - klo));
+            const int sbits = bits < SPLIT_BITS ? bits : SPLIT_BITS;
+            const int shift = bits - sbits;
+            const uint32_t nparts = 1u << sbits;
+            if (tid < 256) { hist[tid] = 0; run[tid] = 0; }
+            __syncthreads();
+            for (uint32_t c0 = 0; c0 < sg.size; c0 += SORT_CAP)          // count
+                for (uint32_t p = c0 + tid; p < min(sg.size, c0 + (uint32_t)SORT_CAP); p += SORT_NT)
+                    atomicAdd(&hist[min((uint32_t)(((K)(src[sb + p] - klo)) >> shift), nparts - 1)], 1u);
+            __syncthreads();
+            if (tid < WAVE) {                                            // exclusive scan of <= 256 counts
+                uint32_t c[4], t4 = 0;
+                for (int q = 0; q < 4; ++q) { c[q] = 4 * tid + q < nparts ? hist[4 * tid + q] : 0u; t4 += c[q]; }
+                uint32_t r0 = wave_incl_scan(t4) - t4;
+                for (int q = 0; q < 4; ++q) { if (4 * tid + q < 256) base[4 * tid + q] = r0; r0 += c[q]; }
+            }
+            tables_clear<SORT_NW, 256>(sm.s.tab);
+            __syncthreads();
+            for (uint32_t c0 = 0; c0 < sg.size; c0 += SORT_CAP) {       // stable scatter, chunk by chunk
+                const uint32_t chN = min((uint32_t)SORT_CAP, sg.size - c0);
+                const int nrows = wave_rows<SORT_IPT>(chN);
+                RankEnt *tab = sm.s.tab[wave_id()];
+                K kk[SORT_IPT];
+                uint32_t vv[SORT_IPT], pos[SORT_IPT];
+#pragma unroll
+                for (int r = 0; r < SORT_IPT; ++r) {
+                    if (r < nrows) {
+                        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
+                        kk[r] = p < chN ? src[sb + c0 + p] : (K)0;
+                        if (HV) vv[r] = p < chN ? vsrc[sb + c0 + p] : 0u;
+                        const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
+                        pos[r] = rank_row(tab, d);
+                    }
+                }
+                __syncthreads();
+                scan_tables<SORT_NW, 256>(sm.s.tab, sm.wsum);
+#pragma unroll
+                for (int r = 0; r < SORT_IPT; ++r) {
+                    if (r < nrows) {
+                        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
+                        const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
+                        pos[r] += tab[d].off;
+                    }
+                }
+#pragma unroll
+                for (int wd = 0; wd < T::WORDS; ++wd) {
+#pragma unroll
+                    for (int r = 0; r < SORT_IPT; ++r)
+                        if (r < nrows) sm.s.buf[pos[r]] = T::word(kk[r], wd);
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < SORT_IPT; ++r)
+                        if (r < nrows) kk[r] = T::set_word(kk[r], wd, sm.s.buf[item_pos<SORT_NW, SORT_IPT>(r)]);
+                    __syncthreads();
+                }
+                if (HV) {
+#pragma unroll
+                    for (int r = 0; r < SORT_IPT; ++r) if (r < nrows) sm.s.buf[pos[r]] = vv[r];
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < SORT_IPT; ++r) if (r < nrows) vv[r] = sm.s.buf[item_pos<SORT_NW, SORT_IPT>(r)];
+                    __syncthreads();
+                }
+                // element at chunk position p has digit d (recomputed from its key);
+                // it goes to base[d] + run[d] + (p - start of d in this chunk)
+#pragma unroll
+                for (int r = 0; r < SORT_IPT; ++r) {
+                    if (r < nrows) {
+                        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
+                        if (p < chN) {
+                            const uint32_t d = min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1);
+                            const uint32_t at = base[d] + run[d] + (p - sm.s.tab[0][d].off);
+                            if (at < sg.size) {                                  // guard: inside the segment
+                                dstb[sb + at] = kk[r];
+                                if (HV) vdstb[sb + at] = vv[r];
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                if (tid < nparts) {
+                    const uint32_t st0 = sm.s.tab[0][tid].off;
+                    const uint32_t en = tid + 1 < 256 ? sm.s.tab[0][tid + 1].off : chN;
+                    run[tid] += min(en, chN) - min(st0, chN);
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {                                              // push the parts
+                uint32_t top = sp_sh;
+                for (uint32_t q = nparts; q-- > 0;) {
+                    if (hist[q] == 0) continue;
+                    if (top >= BIG_STACK) { overflow_sh = 1; break; }
+                    const uint64_t plo = sg.lo + ((uint64_t)q << shift);
+                    uint64_t phi = plo + (shift >= 64 ? ~0ull : (((uint64_t)1 << shift) - 1));
+                    if (phi > sg.hi || phi < plo) phi = sg.hi;
+                    stack[top++] = BigSeg{sg.off + base[q], hist[q], sg.in_d ? 0u : 1u, 0u, plo, phi};
+                }
+                sp_sh = top;
+            }
+            __syncthreads();
+            if (overflow_sh) break;      // cannot happen: depth <= key bits / SPLIT_BITS
         }
         __syncthreads();
     }

@@ -263,6 +263,7 @@ template <class K, bool HV> struct Engine {
         // mid buckets hold > WCAP keys and internal ones > cutoff keys
         const uint32_t capSmall = bucS[N], capCopy = bucS[N];
         const uint32_t capMid = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (WCAP + 1) + 1);
+        const uint32_t capBig = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (SORT_CAP + 1) + 1);
         const uint32_t capInt = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / ((uint64_t)cutoff + 1) + 1);
 
         // ---- device metadata
@@ -278,8 +279,10 @@ template <class K, bool HV> struct Engine {
         b.list[CLS_COPY] = ws.take<BucketItem>(capCopy);
         b.list[CLS_SMALL] = ws.take<BucketItem>(capSmall);
         b.list[CLS_MID] = ws.take<BucketItem>(capMid);
+        b.list[CLS_BIG] = ws.take<BucketItem>(capBig);
         b.list[CLS_INTERNAL] = ws.take<BucketItem>(capInt);
-        b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID] = capMid; b.cap[CLS_INTERNAL] = capInt;
+        b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID] = capMid;
+        b.cap[CLS_BIG] = capBig; b.cap[CLS_INTERNAL] = capInt;
         b.ctr = ws.take<uint32_t>(NCLS);
         b.H = ws.take<unsigned long long>(N);
         if (ws.overflow) return SQS_ERR_WORKSPACE;
@@ -343,6 +346,9 @@ template <class K, bool HV> struct Engine {
             k_bucket_small<K, HV><<<std::min<uint32_t>(cdiv(capSmall, SM_NW), 2048), SM_NW * WAVE, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket", keysTot, [&] {
             k_bucket_mid<K, HV><<<std::min<uint32_t>(capMid, 512), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
+        if (cutoff > (uint32_t)SORT_CAP)
+            launch("k_bucket_big", keysTot, [&] {
+                k_bucket_big<K, HV><<<std::min<uint32_t>(capBig, 256), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
         if (int rc = check()) return rc;
 
         // ---- internal buckets form the next batch
@@ -356,8 +362,8 @@ template <class K, bool HV> struct Engine {
         for (int c = 0; c < NCLS; ++c)
             if (hctr[c] > b.cap[c]) return SQS_ERR_DEVICE;   // cannot happen: capacities are bounds
         if (debug_on()) {
-            fprintf(stderr, "[sqs] depth %d: %u nodes, %llu keys; buckets copy %u small %u mid %u internal %u\n",
-                    depth, N, (unsigned long long)keysTot, hctr[0], hctr[1], hctr[2], hctr[3]);
+            fprintf(stderr, "[sqs] depth %d: %u nodes, %llu keys; buckets copy %u small %u mid %u big %u internal %u\n",
+                    depth, N, (unsigned long long)keysTot, hctr[0], hctr[1], hctr[2], hctr[3], hctr[4]);
             if (bktTot <= 64) {
                 std::vector<uint32_t> hb(bktTot), ht(bktTot), hblk(blkTot), hsrc(srcTot);
                 hipMemcpy(hb.data(), b.bs, bktTot * 4, hipMemcpyDeviceToHost);
@@ -384,9 +390,43 @@ template <class K, bool HV> struct Engine {
         return SQS_OK;
     }
 
+    // A whole array that is a base case larger than one LDS sort: the
+    // large-bucket kernel on a one-item work list (one node, one bucket
+    // whose bounds are the whole key range).
+    int sort_big_base(uint64_t n)
+    {
+        const uint64_t mark = ws.top;
+        Batch<K> b{};
+        NodeDesc *dDesc = ws.take<NodeDesc>(1);
+        BucketItem *item = ws.take<BucketItem>(1);
+        uint32_t *ctr = ws.take<uint32_t>(NCLS);
+        if (ws.overflow) return SQS_ERR_WORKSPACE;
+        host_node_ = NodeDesc{};
+        host_node_.n = (uint32_t)n;
+        host_node_.m = 1;
+        host_item_ = BucketItem{0u, 0u, 0u, (uint32_t)n};
+        for (int c = 0; c < NCLS; ++c) host_ctr_[c] = c == CLS_BIG ? 1u : 0u;
+        if (hipMemcpyAsync(dDesc, &host_node_, sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(item, &host_item_, sizeof(BucketItem), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(ctr, host_ctr_, sizeof(host_ctr_), hipMemcpyHostToDevice, st) != hipSuccess)
+            return SQS_ERR_DEVICE;
+        b.nodes = dDesc; b.N = 1; b.ctr = ctr;
+        b.list[CLS_BIG] = item; b.cap[CLS_BIG] = 1;
+        launch("k_bucket_big", n, [&] { k_bucket_big<K, HV><<<1, SORT_NT, 0, st>>>(b, A, VA, D, VD); });
+        if (int rc = check()) return rc;
+        if (hipStreamSynchronize(st) != hipSuccess) return SQS_ERR_DEVICE;   // host copies outlive the upload
+        resolve_timing();
+        ws.top = mark;
+        return SQS_OK;
+    }
+    NodeDesc host_node_{};
+    BucketItem host_item_{};
+    uint32_t host_ctr_[NCLS] = {};
+
     int sort_root(uint64_t n, uint64_t seed)
     {
         if (n == 0) return SQS_OK;
+        if (n > (uint64_t)SORT_CAP && n <= cutoff) return sort_big_base(n);
         if (n <= cutoff) {
             launch("k_base_sort", n, [&] { k_base_sort<K, HV><<<1, SORT_NT, 0, st>>>((uint32_t)n, A, VA, D, VD); });
             if (g_timing.on && hipStreamSynchronize(st) == hipSuccess) resolve_timing();
@@ -399,7 +439,9 @@ template <class K, bool HV> struct Engine {
 
 constexpr uint64_t key_bytes_of(int kind) { return kind == SQS_KIND_U32 ? 4 : 8; }
 
-uint64_t max_cutoff_of(int kind) { return (kind >= SQS_KIND_U32 && kind <= SQS_KIND_KV) ? SORT_CAP : 0; }
+// the automatic (and largest) cut-off: a base case is sorted by one
+// work-group, in LDS up to SORT_CAP keys and with MSD splits above
+uint64_t max_cutoff_of(int kind) { return (kind >= SQS_KIND_U32 && kind <= SQS_KIND_KV) ? BIG_CAP : 0; }
 
 uint64_t max_n_of(int kind)
 {
@@ -440,7 +482,7 @@ int run_sort(uint64_t n, K *in, uint32_t *vin, K *out, uint32_t *vout, uint64_t 
                overlap(vout, n * 4, out, n * sizeof(K))))
         return SQS_ERR_ALIAS;
     const uint64_t need = workspace_bound(n, C, sizeof(K) + (HV ? 4 : 0));
-    if (n > C && (!p || !p->workspace || p->workspace_bytes < need)) return SQS_ERR_WORKSPACE;
+    if (n > (uint64_t)SORT_CAP && (!p || !p->workspace || p->workspace_bytes < need)) return SQS_ERR_WORKSPACE;
     const bool dig = p && (p->flags & SQS_FLAG_DIGEST);
     if (dig && !p->digest) return SQS_ERR_ARG;
     Engine<K, HV> e;

@@ -87,6 +87,10 @@ U32_CASES = [
     (1, 0), (2, 0), (3, 4), (5, 4), (8, 4), (100, 4), (1000, 16), (4097, 64),
     (16384, 0), (16385, 0), (65537, 0), (65537, 64), (1_000_003, 0),
     ((1 << 20) + 3, 0), (3_000_017, 0), (130_000, 256),
+    # whole array a base case sorted with MSD splits (16384 < n <= cutoff)
+    (16_385, 0), (50_000, 0), (65_536, 0),
+    # buckets of 16K..64K keys (MSD-split base cases inside the bucket phase)
+    ((1 << 24) + 5, 0), ((1 << 22) + 1, 20_000),
 ]
 
 
@@ -125,7 +129,7 @@ def _degenerate(n):
     }
 
 
-@pytest.mark.parametrize("n,cutoff", [(200_003, 0), (70_000, 64)])
+@pytest.mark.parametrize("n,cutoff", [(200_003, 0), (70_000, 64), (2_000_003, 20_000)])
 @pytest.mark.parametrize("name", list(_degenerate(10).keys()))
 def test_u32_degenerate_inputs(b, ws, n, cutoff, name):
     _say(f"u32 degenerate {name} n={n} cutoff={cutoff}")
@@ -180,7 +184,8 @@ def test_skew_transpose_is_root_of_sort(b, ws):
 
 
 # ------------------------------------------------------------------ u64, kv
-@pytest.mark.parametrize("n,cutoff", [(1, 0), (7, 4), (5000, 16), (16385, 0), (300_001, 0), (70_001, 64)])
+@pytest.mark.parametrize("n,cutoff", [(1, 0), (7, 4), (5000, 16), (16385, 0), (300_001, 0), (70_001, 64),
+                                      (40_000, 0), ((1 << 22) + 7, 30_000)])
 def test_u64_matches_oracle(b, ws, n, cutoff):
     _say(f"u64 n={n} cutoff={cutoff}")
     x = datagen.uniform_u64(n, seed=n)
@@ -192,7 +197,8 @@ def test_u64_matches_oracle(b, ws, n, cutoff):
     assert dg == wdg
 
 
-@pytest.mark.parametrize("n,cutoff", [(9, 4), (5000, 16), (40_000, 64), (300_007, 0)])
+@pytest.mark.parametrize("n,cutoff", [(9, 4), (5000, 16), (40_000, 64), (300_007, 0), (60_000, 0),
+                                      ((1 << 23) + 3, 0)])
 def test_kv_matches_oracle(b, ws, n, cutoff):
     _say(f"kv n={n} cutoff={cutoff}")
     k, v = datagen.kv_mixture(n, seed=4)
