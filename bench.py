@@ -19,8 +19,11 @@ timed region.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import sqlite3
 import sys
 import time
 
@@ -37,6 +40,50 @@ WORKLOADS = {
     "kv_mixture": dict(kind="kv", log2n=27, dist="80% Zipf(1.1) over 2^20 u64 / 10% constant / "
                                                   "10% sorted run with 1% swaps", data_seed=4),
 }
+
+
+# timing-table names of the library -> kernel symbols in rocprofv3 traces
+KERNEL_SYMBOL = {"k_colsort": "k_colsort_big", "k_bucket_big": "k_bucket_big", "k_transpose": "k_transpose",
+                 "k_bucket": "k_bucket_mid", "k_colsort_w": "k_colsort_small", "k_bucket_w": "k_bucket_small"}
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def source_hash():
+    """Hash of the HIP sources: traffic counters are valid only for them."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2407_14801_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def _pmc_rows(db, counter):
+    con = sqlite3.connect(db)
+    rows = con.execute("select dispatch_id, kernel_name, grid_size, value from counters_collection "
+                       "where counter_name = ?", (counter,)).fetchall()
+    con.close()
+    per = {}
+    for d, k, g, v in rows:             # values may be split per shader engine / XCD: sum them
+        e = per.setdefault(d, [k, g, 0.0])
+        e[2] += v
+    return list(per.values())
+
+
+def traffic_from_dbs(fetch_db, write_db, kernel, calib_bytes):
+    """HBM bytes per launch of `kernel` from a FETCH_SIZE run and a WRITE_SIZE
+    run (KiB per dispatch), each scaled by what the same counter reads for the
+    calibration copy of calib_bytes (the largest copy dispatch)."""
+    sym = KERNEL_SYMBOL.get(kernel, kernel)
+    out = {}
+    for name, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
+        rows = _pmc_rows(db, name)
+        copies = [r for r in rows if "copyBuffer" in r[0]]
+        cal = max(copies, key=lambda r: r[1])
+        factor = calib_bytes / (cal[2] * 1024.0)
+        ks = [r[2] for r in rows if sym + "<" in r[0]]
+        out[name] = {"kib_per_launch": sum(ks) / len(ks), "launches": len(ks), "calib_kib": cal[2],
+                     "scale": factor, "bytes_per_launch": sum(ks) / len(ks) * 1024.0 * factor}
+    return out
 
 
 def make_input(wl, n):
@@ -73,9 +120,31 @@ def main():
     ap.add_argument("--workload", default="u32_uniform", choices=sorted(WORKLOADS))
     ap.add_argument("--log2n", type=int, default=None, help="override the size (2^k keys)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, copy one input (n*w bytes) device-to-device: the known-size "
+                         "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
+    ap.add_argument("--traffic-dbs", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="rocprofv3 --pmc results of a --calib-copy run for FETCH_SIZE and WRITE_SIZE: "
+                         "record the dominant kernel's HBM traffic in profiles/traffic.json and exit")
+    ap.add_argument("--traffic-kernel", default="k_colsort")
     args = ap.parse_args()
+
+    if args.traffic_dbs:
+        wl = WORKLOADS[args.workload]
+        log2n = args.log2n or wl["log2n"]
+        calib = (1 << log2n) * (4 if wl["kind"] == "u32" else 8)
+        t = traffic_from_dbs(args.traffic_dbs[0], args.traffic_dbs[1], args.traffic_kernel, calib)
+        rec = {"kernel": args.traffic_kernel, "workload": f"squaresort_{args.workload}_2^{log2n}",
+               "source_hash": source_hash(),
+               "traffic_bytes_per_launch": t["FETCH_SIZE"]["bytes_per_launch"] + t["WRITE_SIZE"]["bytes_per_launch"],
+               "counters": t}
+        os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+        with open(TRAFFIC_JSON, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec))
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
@@ -130,6 +199,11 @@ def main():
     t1 = time.perf_counter()
     timing = binding.timing_report() if not args.no_timing else {}
     binding.timing_enable(False)
+    if args.calib_copy:
+        src = ins[0] if wl["kind"] == "u32" else ins[0][0]
+        _c = src.clone()
+        torch.cuda.synchronize()
+        del _c
 
     # the last output must be sorted (cheap device check)
     if wl["kind"] == "u32":
@@ -162,8 +236,15 @@ def main():
         avg_ms = d["ms"] / d["launches"]
         bytes_per_launch = 2 * w * d["units"] / d["launches"]     # read + write of each key
         ach = bytes_per_launch / (avg_ms / 1e3) / 1e9
+        traffic = None
+        if os.path.exists(TRAFFIC_JSON):
+            with open(TRAFFIC_JSON) as f:
+                tr = json.load(f)
+            if (tr.get("source_hash") == source_hash() and tr.get("kernel") == dom
+                    and tr.get("workload") == f"squaresort_{args.workload}_2^{log2n}"):
+                traffic = int(tr["traffic_bytes_per_launch"])
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "avg_launch_ms": round(avg_ms, 5), "alg_bytes_per_launch": int(bytes_per_launch)}
 
     res = {
