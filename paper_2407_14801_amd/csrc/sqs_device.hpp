@@ -7,14 +7,15 @@
 //    (up to NW*64*IPT keys) and a wave sort (up to 64*R keys, no barriers).
 //
 // Ranking is deterministic and stable without relying on the order in which
-// the LDS serves colliding atomics.  Each wave owns a table of 16-byte
-// entries {mask_lo, mask_hi, count, offset}, one per digit value.  For every
-// 64-key row, each lane ORs its lane bit into its half of the mask of its
-// digit (OR commutes, so the result does not depend on service order), reads
-// the entry back, takes its rank among equal digits of the row with v_mbcnt
-// and the row's count with v_bcnt, and every peer writes the same updated
-// entry {0, 0, count + row count, -}.  Rows are processed in position order,
-// so ranks are stable; an exclusive scan of the counts then places every key.
+// the LDS serves colliding atomics.  Each wave owns a table with, per digit
+// value, a 64-bit lane mask, a running count and an offset (three separate
+// arrays).  For every 64-key row, each lane ORs its lane bit into its half of
+// the mask of its digit (OR commutes, so the result does not depend on
+// service order), reads the whole mask back, takes its rank among equal
+// digits of the row with v_mbcnt, and every peer writes the same new count
+// (old count + popcount of the mask) and clears the mask.  Rows are processed
+// in position order, so ranks are stable; an exclusive scan of the counts
+// then places every key.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -116,21 +117,33 @@ __device__ inline unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // ---------------------------------------------------------------- ranking
-struct alignas(16) RankEnt {
-    uint32_t mlo, mhi, cnt, off;
+// One wave's digit table: mask and count are zero between rows; off is
+// written by the scan.  16 bytes per digit value.
+template <int RDX> struct RankTab {
+    unsigned long long mask[RDX];
+    uint32_t cnt[RDX];
+    uint32_t off[RDX];
 };
 
 // Rank one 64-key row against a wave's digit table: returns the count of
 // equal digits in earlier rows plus the rank among equal digits of this row.
-__device__ inline uint32_t rank_row(RankEnt *tab, uint32_t d)
+template <int RDX>
+__device__ inline uint32_t rank_row(RankTab<RDX> &t, uint32_t d)
 {
     const uint32_t l = lane_id();
-    RankEnt *e = tab + d;
-    atomicOr(l < 32 ? &e->mlo : &e->mhi, 1u << (l & 31));
-    const uint4 v = *reinterpret_cast<const uint4 *>(e);
-    const uint32_t r = v.z + rank_in_mask(v.x, v.y);
-    *reinterpret_cast<uint4 *>(e) = make_uint4(0u, 0u, v.z + __popc(v.x) + __popc(v.y), 0u);
-    return r;
+    atomicOr(reinterpret_cast<uint32_t *>(&t.mask[d]) + (l >> 5), 1u << (l & 31));
+    const unsigned long long pm = t.mask[d];
+    const uint32_t old = t.cnt[d];
+    t.cnt[d] = old + (uint32_t)__popcll(pm);
+    t.mask[d] = 0ull;
+    return old + rank_in_mask((uint32_t)pm, (uint32_t)(pm >> 32));
+}
+
+// clears one wave's table with that wave's lanes
+template <int RDX>
+__device__ inline void wave_table_clear(RankTab<RDX> &t)
+{
+    for (int i = lane_id(); i < RDX; i += WAVE) { t.mask[i] = 0ull; t.cnt[i] = 0u; }
 }
 
 // ---------------------------------------------------------------- block sort
@@ -142,7 +155,7 @@ template <int NW, int IPT> struct SortSmem {
     static constexpr int CAP = NW * WAVE * IPT;
     union {
         struct {
-            RankEnt tab[NW][256];
+            RankTab<256> tab[NW];
             uint32_t buf[CAP];
         } s;
         uint64_t k64[CAP];
@@ -170,10 +183,12 @@ __device__ inline int wave_rows(uint32_t count)
 }
 
 template <int NW, int RDX>
-__device__ inline void tables_clear(RankEnt (*tab)[RDX])
+__device__ inline void tables_clear(RankTab<RDX> *tab)
 {
-    for (int i = threadIdx.x; i < NW * RDX; i += NW * WAVE)
-        (&tab[0][0])[i] = RankEnt{0u, 0u, 0u, 0u};
+    for (int i = threadIdx.x; i < NW * RDX; i += NW * WAVE) {
+        tab[i / RDX].mask[i % RDX] = 0ull;
+        tab[i / RDX].cnt[i % RDX] = 0u;
+    }
 }
 
 template <class K, int NW>
@@ -202,13 +217,13 @@ __device__ inline void block_minmax(K &lo, K &hi, uint32_t *red32, unsigned long
 // values: off := first position of (digit, wave); cnt := 0.  wsum has NW
 // words.  Two barriers inside; call after a barrier that follows ranking.
 template <int NW, int RDX>
-__device__ inline void scan_tables(RankEnt (*tab)[RDX], uint32_t *wsum)
+__device__ inline void scan_tables(RankTab<RDX> *tab, uint32_t *wsum)
 {
     static_assert(RDX <= NW * WAVE, "one thread per digit value");
     const uint32_t t = threadIdx.x;
     uint32_t tot = 0;
     if (t < (uint32_t)RDX)
-        for (int ww = 0; ww < NW; ++ww) tot += tab[ww][t].cnt;
+        for (int ww = 0; ww < NW; ++ww) tot += tab[ww].cnt[t];
     const uint32_t incl = wave_incl_scan(tot);
     if (lane_id() == WAVE - 1) wsum[wave_id()] = incl;
     __syncthreads();
@@ -216,9 +231,9 @@ __device__ inline void scan_tables(RankEnt (*tab)[RDX], uint32_t *wsum)
         uint32_t run = incl - tot;
         for (uint32_t ww = 0; ww < wave_id(); ++ww) run += wsum[ww];
         for (int ww = 0; ww < NW; ++ww) {
-            const uint32_t c = tab[ww][t].cnt;
-            tab[ww][t].off = run;
-            tab[ww][t].cnt = 0u;
+            const uint32_t c = tab[ww].cnt[t];
+            tab[ww].off[t] = run;
+            tab[ww].cnt[t] = 0u;
             run += c;
         }
     }
@@ -242,7 +257,7 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
     block_minmax<K, NW>(lo, hi, sm.red32, sm.red64);
     if (count <= 1 || !(lo < hi)) return;          // already in order (uniform branch)
     const int passes = (T::bitlen((K)(hi - lo)) + 7) / 8;
-    RankEnt *tab = sm.s.tab[wave_id()];
+    RankTab<256> &tab = sm.s.tab[wave_id()];
     uint32_t pos[IPT];
     for (int ps = 0; ps < passes; ++ps) {
         const int sh = 8 * ps;
@@ -259,7 +274,7 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
         for (int r = 0; r < IPT; ++r) {
             if (r < nrows) {
                 const uint32_t d = item_pos<NW, IPT>(r) < count ? T::digit(k[r], lo, sh) : 255u;
-                pos[r] += tab[d].off;
+                pos[r] += tab.off[d];
             }
         }
         // move keys (and values) word by word through the exchange buffer
@@ -292,7 +307,7 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
 // and buffer; no work-group barrier.  The table must be clear on entry and is
 // clear on return.
 template <int R> struct WaveSmem {
-    RankEnt tab[256];
+    RankTab<256> tab;
     uint32_t buf[R * WAVE];
 };
 
@@ -323,25 +338,19 @@ __device__ void wave_sort(K (&k)[R], uint32_t (&v)[R], uint32_t count, WaveSmem<
         wave_lds_sync();
         // exclusive scan over the 256 digit counts: lane l owns digits 4l..4l+3
         {
-            uint32_t c0 = sm.tab[4 * l].cnt, c1 = sm.tab[4 * l + 1].cnt;
-            uint32_t c2 = sm.tab[4 * l + 2].cnt, c3 = sm.tab[4 * l + 3].cnt;
-            const uint32_t s = c0 + c1 + c2 + c3;
-            uint32_t run = wave_incl_scan(s) - s;
-            sm.tab[4 * l].off = run;     run += c0;
-            sm.tab[4 * l + 1].off = run; run += c1;
-            sm.tab[4 * l + 2].off = run; run += c2;
-            sm.tab[4 * l + 3].off = run;
-            sm.tab[4 * l].cnt = 0u;
-            sm.tab[4 * l + 1].cnt = 0u;
-            sm.tab[4 * l + 2].cnt = 0u;
-            sm.tab[4 * l + 3].cnt = 0u;
+            const uint4 c = *reinterpret_cast<const uint4 *>(&sm.tab.cnt[4 * l]);
+            const uint32_t s = c.x + c.y + c.z + c.w;
+            const uint32_t run = wave_incl_scan(s) - s;
+            *reinterpret_cast<uint4 *>(&sm.tab.off[4 * l]) =
+                make_uint4(run, run + c.x, run + c.x + c.y, run + c.x + c.y + c.z);
+            *reinterpret_cast<uint4 *>(&sm.tab.cnt[4 * l]) = make_uint4(0u, 0u, 0u, 0u);
         }
         wave_lds_sync();
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if (r < nrows) {
                 const uint32_t d = r * WAVE + l < count ? T::digit(k[r], lo, sh) : 255u;
-                pos[r] += sm.tab[d].off;
+                pos[r] += sm.tab.off[d];
             }
         }
 #pragma unroll

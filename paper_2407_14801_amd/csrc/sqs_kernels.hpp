@@ -171,7 +171,7 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_sort_pivots_small(Batch<K> b)
 {
     __shared__ WaveSmem<WR> wsm[SM_NW];
     const uint32_t w = wave_id(), l = lane_id();
-    for (int i = l; i < 256; i += WAVE) wsm[w].tab[i] = RankEnt{0u, 0u, 0u, 0u};
+    wave_table_clear(wsm[w].tab);
     wave_lds_sync();
     const uint32_t slot = blockIdx.x * SM_NW + w;
     if (slot >= b.NS) return;
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
         if (t < npiv) { spiv[t] = b.piv[nd.piv + t]; sst[t] = b.strict[nd.piv + t]; }
         hist[t] = 0;
     }
-    for (int i = l; i < 256; i += WAVE) wsm[w].tab[i] = RankEnt{0u, 0u, 0u, 0u};
+    wave_table_clear(wsm[w].tab);
     __syncthreads();
 
     for (uint32_t c = w; c < ncol; c += SM_NW) {
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(1024) void k_bucket_start(Batch<K> b, unsigned long
 // column's keys of bucket j in sorted order.  Tiles larger than one chunk
 // are processed chunk by chunk in column order, which keeps that order.
 template <class K> struct TileSmem {
-    RankEnt tab[TR_NW][TB];
+    RankTab<TB> tab[TR_NW];
     uint32_t wsum[TR_NW];
     uint32_t buf[TR_CH];
     uint8_t jl[TR_CH];
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
     }
     __syncthreads();
     const uint32_t N = sm.cOff[ncol];
-    RankEnt *tab = sm.tab[wave_id()];
+    RankTab<TB> &tab = sm.tab[wave_id()];
 
     for (uint32_t q0 = 0; q0 < N; q0 += TR_CH) {
         const uint32_t chN = min((uint32_t)TR_CH, N - q0);
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
         __syncthreads();
         scan_tables<TR_NW, TB>(sm.tab, sm.wsum);
 #pragma unroll
-        for (int r = 0; r < TR_IPT; ++r) if (r < nrows) pos[r] += tab[dig[r]].off;
+        for (int r = 0; r < TR_IPT; ++r) if (r < nrows) pos[r] += tab.off[dig[r]];
 #pragma unroll
         for (int wd = 0; wd < T::WORDS; ++wd) {
 #pragma unroll
@@ -564,14 +564,14 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
             for (int r = 0; r < TR_IPT; ++r) if (r < nrows) vv[r] = sm.buf[item_pos<TR_NW, TR_IPT>(r)];
             __syncthreads();
         }
-        // digit d of this chunk starts at tab[0][d].off (wave 0, the first in order)
+        // digit d of this chunk starts at tab[0].off[d] (wave 0, the first in order)
 #pragma unroll
         for (int r = 0; r < TR_IPT; ++r) {
             if (r < nrows) {
                 const uint32_t p = item_pos<TR_NW, TR_IPT>(r);
                 if (p < chN) {
                     const uint32_t d = sm.jl[p];
-                    const uint64_t rel = (uint64_t)sm.dstb[d] + (p - sm.tab[0][d].off);
+                    const uint64_t rel = (uint64_t)sm.dstb[d] + (p - sm.tab[0].off[d]);
                     if (rel < nd.n) {                                        // guard: inside the node
                         dst[nd.off + rel] = kk[r];
                         if (HV) vdst[nd.off + rel] = vv[r];
@@ -581,8 +581,8 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
         }
         __syncthreads();
         if (tid < nb) {
-            const uint32_t end = tid + 1 < TB ? sm.tab[0][tid + 1].off : (uint32_t)TR_CH;
-            sm.dstb[tid] += min(end, chN) - min(sm.tab[0][tid].off, chN);
+            const uint32_t end = tid + 1 < TB ? sm.tab[0].off[tid + 1] : (uint32_t)TR_CH;
+            sm.dstb[tid] += min(end, chN) - min(sm.tab[0].off[tid], chN);
         }
         __syncthreads();
     }
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_bucket_small(Batch<K> b, const
 {
     __shared__ WaveSmem<WR> wsm[SM_NW];
     const uint32_t w = wave_id(), l = lane_id();
-    for (int i = l; i < 256; i += WAVE) wsm[w].tab[i] = RankEnt{0u, 0u, 0u, 0u};
+    wave_table_clear(wsm[w].tab);
     wave_lds_sync();
     const uint32_t cnt = min(b.ctr[CLS_SMALL], b.cap[CLS_SMALL]);
     for (uint32_t it = blockIdx.x * SM_NW + w; it < cnt; it += gridDim.x * SM_NW) {
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
             for (uint32_t c0 = 0; c0 < sg.size; c0 += SORT_CAP) {       // stable scatter, chunk by chunk
                 const uint32_t chN = min((uint32_t)SORT_CAP, sg.size - c0);
                 const int nrows = wave_rows<SORT_IPT>(chN);
-                RankEnt *tab = sm.s.tab[wave_id()];
+                RankTab<256> &tab = sm.s.tab[wave_id()];
                 K kk[SORT_IPT];
                 uint32_t vv[SORT_IPT], pos[SORT_IPT];
 #pragma unroll
@@ -888,7 +888,7 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
                     if (r < nrows) {
                         const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
                         const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
-                        pos[r] += tab[d].off;
+                        pos[r] += tab.off[d];
                     }
                 }
 #pragma unroll
@@ -918,7 +918,7 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
                         const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
                         if (p < chN) {
                             const uint32_t d = min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1);
-                            const uint32_t at = base[d] + run[d] + (p - sm.s.tab[0][d].off);
+                            const uint32_t at = base[d] + run[d] + (p - sm.s.tab[0].off[d]);
                             if (at < sg.size) {                                  // guard: inside the segment
                                 dstb[sb + at] = kk[r];
                                 if (HV) vdstb[sb + at] = vv[r];
@@ -928,8 +928,8 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
                 }
                 __syncthreads();
                 if (tid < nparts) {
-                    const uint32_t st0 = sm.s.tab[0][tid].off;
-                    const uint32_t en = tid + 1 < 256 ? sm.s.tab[0][tid + 1].off : chN;
+                    const uint32_t st0 = sm.s.tab[0].off[tid];
+                    const uint32_t en = tid + 1 < 256 ? sm.s.tab[0].off[tid + 1] : chN;
                     run[tid] += min(en, chN) - min(st0, chN);
                 }
                 __syncthreads();
