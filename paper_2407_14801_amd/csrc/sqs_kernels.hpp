@@ -461,17 +461,41 @@ __global__ __launch_bounds__(1024) void k_bucket_start(Batch<K> b, unsigned long
 // layout is that of Alg. 2/3: bucket j receives, column by column, the
 // column's keys of bucket j in sorted order.  Tiles larger than one chunk
 // are processed chunk by chunk in column order, which keeps that order.
+//
+// Per key, the column is read from a per-position map filled run by run, and
+// the bucket from a 256-slot table over the block's key range: slot u holds
+// the bucket of the smallest key value of the slot, so a key's bucket lies
+// between the entries of its slot and the next, and a short binary search
+// over the pivots in between (usually none or one) finishes it.
+constexpr int TR_LUT = 256;
+
 template <class K> struct TileSmem {
     RankTab<TB> tab[TR_NW];
     uint32_t wsum[TR_NW];
     uint32_t buf[TR_CH];
-    uint8_t jl[TR_CH];
+    uint8_t colOf[TR_CH];        // column of each chunk position; then the bucket of each sorted position
+    uint64_t relBase[TG];        // node-relative source index of chunk position q is relBase[c] + q
     uint32_t cOff[TG + 1];
-    uint32_t aOf[TG];
-    uint32_t dstb[TB];
+    uint32_t dstb[TB];           // node-relative destination of the bucket's next key
+    uint32_t wbase[TB];          // per chunk: destination of sorted position p is wbase[d] + p
     K piv[TB];
     uint8_t st[TB];
+    uint8_t lut[TR_LUT + 1];
 };
+
+// local bucket of x among the npv pivots of the block, given x >= lo
+template <class K>
+__device__ inline uint32_t tile_bucket(K x, K lo, int sh, const TileSmem<K> &sm)
+{
+    const K du = (K)((K)(x - lo) >> sh);
+    const uint32_t u = du < (K)(TR_LUT - 1) ? (uint32_t)du : (uint32_t)(TR_LUT - 1);
+    uint32_t a = sm.lut[u], e = sm.lut[u + 1];
+    while (a < e) {
+        const uint32_t mid = (a + e) >> 1;
+        if (le_pivot(x, sm.piv[mid], sm.st[mid] != 0)) e = mid; else a = mid + 1;
+    }
+    return a;
+}
 
 template <class K, bool HV>
 __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K *src, const uint32_t *vsrc,
@@ -488,6 +512,7 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
     const uint32_t j0 = J * TB, nb = min((uint32_t)TB, m - j0);
     const uint32_t npv = (j0 + nb <= m - 1) ? nb : nb - 1;   // real pivots of the block
     const uint32_t tid = threadIdx.x;
+    const uint32_t l = lane_id(), w = wave_id();
 
     tables_clear<TR_NW, TB>(sm.tab);
     if (tid < WAVE) {                      // one wave builds the run table
@@ -497,7 +522,10 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
             len = b.srcOff[nd.src + (uint64_t)(J + 1) * m + i0 + tid] - a;
         }
         const uint32_t incl = wave_incl_scan(len);
-        if (tid < ncol) { sm.cOff[tid] = incl - len; sm.aOf[tid] = a; }
+        if (tid < ncol) {
+            sm.cOff[tid] = incl - len;
+            sm.relBase[tid] = (uint64_t)(i0 + tid) * m + a - (incl - len);
+        }
         if (tid == ncol - 1) sm.cOff[ncol] = incl;
     }
     if (tid < nb) {
@@ -505,13 +533,37 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
         sm.dstb[tid] = b.bs[nd.bkt + j] + b.blk[nd.blk + (uint64_t)g * m + j];
         if (tid < npv) { sm.piv[tid] = b.piv[nd.piv + j]; sm.st[tid] = b.strict[nd.piv + j]; }
     }
+    // every key of the block is >= the pivot before it (or 0)
+    const K lo = j0 > 0 ? b.piv[nd.piv + j0 - 1] : (K)0;
     __syncthreads();
+    const K hi = npv > 0 ? sm.piv[npv - 1] : lo;
+    const int sh = max(0, T::bitlen((K)(hi - lo)) - 8);
+    for (uint32_t t = tid; t <= (uint32_t)TR_LUT; t += TR_NW * WAVE) {
+        uint32_t v = npv;
+        const K step = (K)((K)t << sh);
+        if (t < (uint32_t)TR_LUT && step <= (K)((K)T::MAXV - lo)) {   // t << sh cannot overflow: t < 256
+            const K x = (K)(lo + step);
+            uint32_t a = 0, e = npv;
+            while (a < e) {
+                const uint32_t mid = (a + e) >> 1;
+                if (le_pivot(x, sm.piv[mid], sm.st[mid] != 0)) e = mid; else a = mid + 1;
+            }
+            v = a;
+        }
+        sm.lut[t] = (uint8_t)v;
+    }
     const uint32_t N = sm.cOff[ncol];
-    RankTab<TB> &tab = sm.tab[wave_id()];
+    RankTab<TB> &tab = sm.tab[w];
 
     for (uint32_t q0 = 0; q0 < N; q0 += TR_CH) {
         const uint32_t chN = min((uint32_t)TR_CH, N - q0);
         const int nrows = wave_rows<TR_IPT>(chN);
+        // column map of the chunk: wave w fills the runs of columns w, w + TR_NW, ...
+        for (uint32_t c = w; c < ncol; c += TR_NW) {
+            const uint32_t s0 = max(sm.cOff[c], q0), s1 = min(sm.cOff[c + 1], q0 + chN);
+            for (uint32_t q = s0 + l; q < s1; q += WAVE) sm.colOf[q - q0] = (uint8_t)c;
+        }
+        __syncthreads();
         K kk[TR_IPT];
         uint32_t vv[TR_IPT], dig[TR_IPT], pos[TR_IPT];
 #pragma unroll
@@ -522,23 +574,26 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
                 kk[r] = (K)0;
                 vv[r] = 0;
                 if (p < chN) {
-                    const uint32_t q = q0 + p;
-                    uint32_t lo = 0, hi = ncol - 1;          // last column whose run starts at or before q
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi + 1) >> 1;
-                        if (sm.cOff[mid] <= q) lo = mid; else hi = mid - 1;
-                    }
-                    const uint64_t rel = (uint64_t)(i0 + lo) * m + sm.aOf[lo] + (q - sm.cOff[lo]);
+                    const uint32_t c = sm.colOf[p];
+                    const uint64_t rel = sm.relBase[c] + q0 + p;
                     const uint64_t at = nd.off + (rel < nd.n ? rel : 0);   // guard: inside the node
                     kk[r] = src[at];
                     if (HV) vv[r] = vsrc[at];
-                    dig[r] = bucket_search(kk[r], sm.piv, sm.st, npv);
+                    dig[r] = tile_bucket(kk[r], lo, sh, sm);
                 }
                 pos[r] = rank_row(tab, dig[r]);
             }
         }
         __syncthreads();
         scan_tables<TR_NW, TB>(sm.tab, sm.wsum);
+        // sorted chunk position p of bucket d goes to wbase[d] + p; positions
+        // past chN carry the padding digit TB - 1 and come last
+        if (tid < nb) {
+            const uint32_t s0 = min(sm.tab[0].off[tid], chN);
+            const uint32_t e0 = min(tid + 1 < TB ? sm.tab[0].off[tid + 1] : (uint32_t)TR_CH, chN);
+            sm.wbase[tid] = sm.dstb[tid] - s0;
+            sm.dstb[tid] += e0 - s0;
+        }
 #pragma unroll
         for (int r = 0; r < TR_IPT; ++r) if (r < nrows) pos[r] += tab.off[dig[r]];
 #pragma unroll
@@ -547,7 +602,7 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
             for (int r = 0; r < TR_IPT; ++r) {
                 if (r < nrows) {
                     sm.buf[pos[r]] = T::word(kk[r], wd);
-                    if (wd == 0) sm.jl[pos[r]] = (uint8_t)dig[r];
+                    if (wd == 0) sm.colOf[pos[r]] = (uint8_t)dig[r];
                 }
             }
             __syncthreads();
@@ -564,25 +619,18 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
             for (int r = 0; r < TR_IPT; ++r) if (r < nrows) vv[r] = sm.buf[item_pos<TR_NW, TR_IPT>(r)];
             __syncthreads();
         }
-        // digit d of this chunk starts at tab[0].off[d] (wave 0, the first in order)
 #pragma unroll
         for (int r = 0; r < TR_IPT; ++r) {
             if (r < nrows) {
                 const uint32_t p = item_pos<TR_NW, TR_IPT>(r);
                 if (p < chN) {
-                    const uint32_t d = sm.jl[p];
-                    const uint64_t rel = (uint64_t)sm.dstb[d] + (p - sm.tab[0].off[d]);
+                    const uint32_t rel = sm.wbase[sm.colOf[p]] + p;
                     if (rel < nd.n) {                                        // guard: inside the node
                         dst[nd.off + rel] = kk[r];
                         if (HV) vdst[nd.off + rel] = vv[r];
                     }
                 }
             }
-        }
-        __syncthreads();
-        if (tid < nb) {
-            const uint32_t end = tid + 1 < TB ? sm.tab[0].off[tid + 1] : (uint32_t)TR_CH;
-            sm.dstb[tid] += min(end, chN) - min(sm.tab[0].off[tid], chN);
         }
         __syncthreads();
     }
