@@ -56,11 +56,15 @@ struct NodeDesc {
     uint32_t pad;
 };
 constexpr uint32_t NODE_COLS_RECURSED = 1u;
+// each node's pivot slot starts at a multiple of PIV_ALIGN keys and is padded
+// to one, so a thread can load its PIV_ALIGN pivots with 16-byte loads
+constexpr uint32_t PIV_ALIGN = 16;
 
 struct BucketItem {
     uint32_t node, j, lo, size;   // lo: node-local first slot
 };
 enum { CLS_COPY = 0, CLS_SMALL = 1, CLS_MID = 2, CLS_BIG = 3, CLS_INTERNAL = 4, NCLS = 5 };
+constexpr uint32_t COPY_CH = 32768;           // keys per piece of a single-value bucket copy
 constexpr uint32_t BIG_CAP = 4 * SORT_CAP;   // largest automatic cut-off: 65536 keys
 
 template <class K> struct Batch {
@@ -134,6 +138,7 @@ __global__ void k_sample(Batch<K> b, const K *A)
     const uint32_t k = find_node(b.pivStart, b.N, item);
     const NodeDesc nd = b.nodes[k];
     const uint32_t t = item - b.pivStart[k];
+    if (t >= nd.m - 1) return;                       // padding of the node's slot
     b.piv[nd.piv + t] = A[nd.off + pivot_draw(nd.key, t, nd.n)];
 }
 
@@ -199,6 +204,19 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_sort_pivots_small(Batch<K> b)
     }
 }
 
+// pivot q of a slice held as 16-byte words
+template <class K> __device__ inline K piv_of(const uint4 *raw, int q);
+template <> __device__ inline uint32_t piv_of<uint32_t>(const uint4 *raw, int q)
+{
+    const uint4 v = raw[q >> 2];
+    return (q & 3) == 0 ? v.x : (q & 3) == 1 ? v.y : (q & 3) == 2 ? v.z : v.w;
+}
+template <> __device__ inline uint64_t piv_of<uint64_t>(const uint4 *raw, int q)
+{
+    const uint4 v = raw[q >> 1];
+    return (q & 1) == 0 ? ((uint64_t)v.y << 32 | v.x) : ((uint64_t)v.w << 32 | v.z);
+}
+
 // ------------------------------------------------------------ column phase
 __device__ inline uint32_t column_len(uint32_t i, uint32_t m, uint32_t n)
 {
@@ -223,12 +241,13 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
     const uint32_t i0 = g * TG;
     const uint32_t ncol = min((uint32_t)TG, m - i0);
     const bool recursed = nd.flags & NODE_COLS_RECURSED;
-    const uint32_t ppt = (npiv + SORT_NT - 1) / SORT_NT;   // <= SORT_IPT
-    const uint32_t t0 = threadIdx.x * ppt;
+    static_assert(PIV_ALIGN * SORT_NT >= SORT_CAP, "one pivot slice per thread covers a node");
+    constexpr int PPT = PIV_ALIGN;                       // pivots t0 .. t0 + PPT - 1 of this thread
+    const uint32_t t0 = threadIdx.x * PPT;
 
-    uint32_t P[SORT_IPT];
+    uint32_t P[PPT];
 #pragma unroll
-    for (int q = 0; q < SORT_IPT; ++q) P[q] = 0;
+    for (int q = 0; q < PPT; ++q) P[q] = 0;
 
     uint32_t total = 0;
     for (uint32_t c = 0; c < ncol; ++c) {
@@ -270,12 +289,25 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
             if (p < len) { if (sizeof(K) == 4) sm.k32[p] = (uint32_t)kk[r]; else sm.k64[p] = (uint64_t)kk[r]; }
         }
         __syncthreads();
+        // this thread's pivots and strict flags, as 16-byte loads of its
+        // aligned, padded slice (entries past npiv are not used)
+        constexpr int PV4 = PPT * (int)sizeof(K) / 16;
+        uint4 praw[PV4];
+        uint4 sraw = make_uint4(0u, 0u, 0u, 0u);
+        if (t0 < npiv) {
+            const uint4 *p4 = reinterpret_cast<const uint4 *>(b.piv + nd.piv + t0);
+#pragma unroll
+            for (int v4 = 0; v4 < PV4; ++v4) praw[v4] = p4[v4];
+            sraw = *reinterpret_cast<const uint4 *>(b.strict + nd.piv + t0);
+        }
         uint32_t prev = 0;
-        for (uint32_t q = 0; q < ppt; ++q) {
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
             const uint32_t t = t0 + q;
             if (t >= npiv) break;
-            const K pv = b.piv[nd.piv + t];
-            const bool ps = b.strict[nd.piv + t] != 0;
+            const K pv = piv_of<K>(praw, q);
+            const uint32_t sw = q < 4 ? sraw.x : q < 8 ? sraw.y : q < 12 ? sraw.z : sraw.w;
+            const bool ps = ((sw >> (8 * (q & 3))) & 255u) != 0;
             uint32_t a = prev, e = len;
             if (q > 0) {                                  // gallop from the previous answer
                 uint32_t step = 1;
@@ -294,8 +326,7 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
                 if (le_pivot(x, pv, ps)) a = mid + 1; else e = mid;
             }
             prev = a;
-#pragma unroll
-            for (int qq = 0; qq < SORT_IPT; ++qq) if (qq == (int)q) P[qq] += a;
+            P[q] += a;
             if ((t + 1) % TB == 0) b.srcOff[nd.src + (uint64_t)((t + 1) / TB) * m + i] = a;
         }
         if (threadIdx.x == 0) {
@@ -307,9 +338,9 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
     // per-bucket counts of the group from the accumulated positions
     uint32_t *Pl = sm.k32;
 #pragma unroll
-    for (int q = 0; q < SORT_IPT; ++q) {
+    for (int q = 0; q < PPT; ++q) {
         const uint32_t t = t0 + q;
-        if (q < (int)ppt && t < npiv) Pl[t] = P[q];
+        if (t < npiv) Pl[t] = P[q];
     }
     __syncthreads();
     uint32_t *blk = b.blk + nd.blk + (uint64_t)g * m;
@@ -705,8 +736,24 @@ __global__ void k_classify(Batch<K> b, uint32_t cutoff)
         }
     }
     const uint32_t l = lane_id();
+    {   // single-value buckets are copied in pieces of at most COPY_CH keys
+        const uint32_t pieces = cls == CLS_COPY ? (it.size + COPY_CH - 1) / COPY_CH : 0u;
+        const uint32_t incl = wave_incl_scan(pieces);
+        const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+        if (total > 0) {
+            uint32_t base = 0;
+            if (l == 0) base = atomicAdd(&b.ctr[CLS_COPY], total);
+            base = __shfl(base, 0, WAVE);
+            for (uint32_t q = 0; q < pieces; ++q) {
+                const uint32_t at = base + incl - pieces + q;
+                const uint32_t off = q * COPY_CH;
+                if (at < b.cap[CLS_COPY])
+                    b.list[CLS_COPY][at] = BucketItem{it.node, it.j, it.lo + off, min(COPY_CH, it.size - off)};
+            }
+        }
+    }
 #pragma unroll
-    for (int c = 0; c < NCLS; ++c) {
+    for (int c = 1; c < NCLS; ++c) {
         const unsigned long long m = __ballot(cls == c);
         if (m == 0) continue;
         uint32_t base = 0;
@@ -720,7 +767,8 @@ __global__ void k_classify(Batch<K> b, uint32_t cutoff)
     }
 }
 
-// Single-value buckets: copy A -> D (one work-group per bucket, persistent).
+// Single-value buckets: copy A -> D (one work-group per piece of at most
+// COPY_CH keys, persistent).
 template <class K, bool HV>
 __global__ __launch_bounds__(256) void k_bucket_copy(Batch<K> b, const K *A, const uint32_t *VA, K *D, uint32_t *VD)
 {

@@ -110,8 +110,9 @@ uint64_t node_meta_bytes(uint64_t n, uint64_t key_bytes)
 {
     const uint64_t m = ceil_isqrt_host(n);
     const uint64_t groups = cdiv(m, TG), nJ = cdiv(m, TB);
-    return sizeof(NodeDesc) + 7 * 4 + (m - 1) * (key_bytes + 1) + 4 * m * (nJ + 1) +
-           4 * groups * m + 4 * (m + 1) + 4 * m + 4 * sizeof(BucketItem) * m + 8;
+    return sizeof(NodeDesc) + 7 * 4 + (m - 1 + PIV_ALIGN) * (key_bytes + 1) + 4 * m * (nJ + 1) +
+           4 * groups * m + 4 * (m + 1) + 4 * m + 4 * sizeof(BucketItem) * m +
+           sizeof(BucketItem) * (n / COPY_CH + 1) + 8;
 }
 
 // Upper bound of the metadata of one batch whose nodes are disjoint ranges of
@@ -241,7 +242,7 @@ template <class K, bool HV> struct Engine {
             }
             if (d.m > (uint32_t)WCAP) { bigIdx.push_back(k); bigGrp.push_back(bigGrp.back() + d.groups); }
             else { smlIdx.push_back(k); smlGrp.push_back(smlGrp.back() + d.groups); }
-            pivS[k + 1] = pivS[k] + (d.m - 1);
+            pivS[k + 1] = pivS[k] + (uint32_t)align_up(d.m - 1, PIV_ALIGN);   // 16-key aligned slots
             tileS[k + 1] = tileS[k] + d.groups * d.nJ;
             bucS[k + 1] = bucS[k] + d.m;
             digS[k + 1] = digS[k] + cdiv(h.n, 16384);
@@ -261,7 +262,8 @@ template <class K, bool HV> struct Engine {
 
         // work-list capacities: every bucket may be small or single-valued;
         // mid buckets hold > WCAP keys and internal ones > cutoff keys
-        const uint32_t capSmall = bucS[N], capCopy = bucS[N];
+        const uint32_t capSmall = bucS[N];
+        const uint32_t capCopy = (uint32_t)std::min<uint64_t>(0xFFFFFFFFull, bucS[N] + keysTot / COPY_CH + 1);
         const uint32_t capMid = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (WCAP + 1) + 1);
         const uint32_t capBig = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (SORT_CAP + 1) + 1);
         const uint32_t capInt = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / ((uint64_t)cutoff + 1) + 1);
