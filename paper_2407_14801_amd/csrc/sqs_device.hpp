@@ -52,7 +52,6 @@ template <> struct KeyT<uint32_t> {
     __device__ static int bitlen(uint32_t x) { return x ? 32 - __clz(x) : 0; }
     __device__ static uint32_t word(uint32_t x, int) { return x; }
     __device__ static uint32_t set_word(uint32_t, int, uint32_t w) { return w; }
-    __device__ static uint32_t digit(uint32_t x, uint32_t lo, int sh) { return ((x - lo) >> sh) & 255u; }
 };
 template <> struct KeyT<uint64_t> {
     static constexpr int WORDS = 2;
@@ -63,7 +62,6 @@ template <> struct KeyT<uint64_t> {
     {
         return i == 0 ? ((x & 0xFFFFFFFF00000000ull) | w) : ((x & 0xFFFFFFFFull) | ((uint64_t)w << 32));
     }
-    __device__ static uint32_t digit(uint64_t x, uint64_t lo, int sh) { return (uint32_t)((x - lo) >> sh) & 255u; }
 };
 
 // Pivot rule: key x belongs to bucket t or an earlier one iff x <= s_t, or
@@ -240,11 +238,22 @@ __device__ inline void scan_tables(RankTab<RDX> *tab, uint32_t *wsum)
     __syncthreads();
 }
 
+// 8-bit digit at bit sh (a multiple of 8) of a key
+__device__ inline uint32_t digit8(uint32_t x, int sh) { return (x >> sh) & 255u; }
+__device__ inline uint32_t digit8(uint64_t x, int sh)
+{
+    const uint32_t w = sh < 32 ? (uint32_t)x : (uint32_t)(x >> 32);
+    return (w >> (sh & 31)) & 255u;
+}
+
 // Stable LSD radix sort of `count` keys (and values) in registers; positions
 // >= count are padding and stay at the end.  Only the bits in which the keys
 // differ are sorted: keys are offset by their minimum and ceil(bits/8) 8-bit
-// passes run.  Tables must be clear on entry (tables_clear + barrier); they
-// are clear again on return.  Ends with a barrier.
+// passes run.  Padding positions of the ranked rows hold the all-ones offset
+// key, whose digit is 255 in every pass, so they stay behind every real key
+// without a per-key test in the passes.  Tables must be clear on entry
+// (tables_clear + barrier); they are clear again on return.  Ends with a
+// barrier.  On return only positions < count hold meaningful keys.
 template <class K, bool HV, int NW, int IPT>
 __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, SortSmem<NW, IPT> &sm)
 {
@@ -257,26 +266,21 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
     block_minmax<K, NW>(lo, hi, sm.red32, sm.red64);
     if (count <= 1 || !(lo < hi)) return;          // already in order (uniform branch)
     const int passes = (T::bitlen((K)(hi - lo)) + 7) / 8;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (r < nrows) k[r] = item_pos<NW, IPT>(r) < count ? (K)(k[r] - lo) : (K)T::MAXV;
     RankTab<256> &tab = sm.s.tab[wave_id()];
     uint32_t pos[IPT];
     for (int ps = 0; ps < passes; ++ps) {
         const int sh = 8 * ps;
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            if (r < nrows) {
-                const uint32_t d = item_pos<NW, IPT>(r) < count ? T::digit(k[r], lo, sh) : 255u;
-                pos[r] = rank_row(tab, d);
-            }
-        }
+        for (int r = 0; r < IPT; ++r)
+            if (r < nrows) pos[r] = rank_row(tab, digit8(k[r], sh));
         __syncthreads();
         scan_tables<NW, 256>(sm.s.tab, sm.wsum);
 #pragma unroll
-        for (int r = 0; r < IPT; ++r) {
-            if (r < nrows) {
-                const uint32_t d = item_pos<NW, IPT>(r) < count ? T::digit(k[r], lo, sh) : 255u;
-                pos[r] += tab.off[d];
-            }
-        }
+        for (int r = 0; r < IPT; ++r)
+            if (r < nrows) pos[r] += tab.off[digit8(k[r], sh)];
         // move keys (and values) word by word through the exchange buffer
 #pragma unroll
         for (int wd = 0; wd < T::WORDS; ++wd) {
@@ -300,6 +304,9 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
             __syncthreads();
         }
     }
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (r < nrows) k[r] = (K)(k[r] + lo);
 }
 
 // ---------------------------------------------------------------- wave sort
@@ -325,16 +332,16 @@ __device__ void wave_sort(K (&k)[R], uint32_t (&v)[R], uint32_t count, WaveSmem<
     hi = wave_max(hi);
     if (count <= 1 || !(lo < hi)) return;
     const int passes = (T::bitlen((K)(hi - lo)) + 7) / 8;
+    // offset keys; padding gets the all-ones key (digit 255 in every pass)
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < nrows) k[r] = r * WAVE + l < count ? (K)(k[r] - lo) : (K)T::MAXV;
     uint32_t pos[R];
     for (int ps = 0; ps < passes; ++ps) {
         const int sh = 8 * ps;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (r < nrows) {
-                const uint32_t d = r * WAVE + l < count ? T::digit(k[r], lo, sh) : 255u;
-                pos[r] = rank_row(sm.tab, d);
-            }
-        }
+        for (int r = 0; r < R; ++r)
+            if (r < nrows) pos[r] = rank_row(sm.tab, digit8(k[r], sh));
         wave_lds_sync();
         // exclusive scan over the 256 digit counts: lane l owns digits 4l..4l+3
         {
@@ -347,12 +354,8 @@ __device__ void wave_sort(K (&k)[R], uint32_t (&v)[R], uint32_t count, WaveSmem<
         }
         wave_lds_sync();
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (r < nrows) {
-                const uint32_t d = r * WAVE + l < count ? T::digit(k[r], lo, sh) : 255u;
-                pos[r] += sm.tab.off[d];
-            }
-        }
+        for (int r = 0; r < R; ++r)
+            if (r < nrows) pos[r] += sm.tab.off[digit8(k[r], sh)];
 #pragma unroll
         for (int wd = 0; wd < T::WORDS; ++wd) {
 #pragma unroll
@@ -375,6 +378,9 @@ __device__ void wave_sort(K (&k)[R], uint32_t (&v)[R], uint32_t count, WaveSmem<
             wave_lds_sync();
         }
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < nrows) k[r] = (K)(k[r] + lo);
 }
 
 }  // namespace sqs
