@@ -180,6 +180,28 @@ __device__ inline int wave_rows(uint32_t count)
     return r < IPT ? (int)r : IPT;
 }
 
+// A block sort of `count` keys gives every wave R rows, the fewest that hold
+// them (R <= IPT), so that all waves share the work.  Row r of the calling
+// wave holds positions bpos(r, R) = (wave * R + r) * 64 + lane.
+template <int NW, int IPT>
+__device__ inline int block_rows(uint32_t count)
+{
+    const uint32_t R = (count + NW * WAVE - 1) / (NW * WAVE);
+    return R < 1u ? 1 : (R > (uint32_t)IPT ? IPT : (int)R);
+}
+__device__ inline uint32_t bpos(int r, int R)
+{
+    return (wave_id() * (uint32_t)R + (uint32_t)r) * WAVE + lane_id();
+}
+// rows of the calling wave (of R) that hold at least one of the first count positions
+__device__ inline int wave_rows_of(uint32_t count, int R)
+{
+    const int64_t left = (int64_t)count - (int64_t)wave_id() * R * WAVE;
+    if (left <= 0) return 0;
+    const int64_t r = (left + WAVE - 1) / WAVE;
+    return r < R ? (int)r : R;
+}
+
 template <int NW, int RDX>
 __device__ inline void tables_clear(RankTab<RDX> *tab)
 {
@@ -246,8 +268,9 @@ __device__ inline uint32_t digit8(uint64_t x, int sh)
     return (w >> (sh & 31)) & 255u;
 }
 
-// Stable LSD radix sort of `count` keys (and values) in registers; positions
-// >= count are padding and stay at the end.  Only the bits in which the keys
+// Stable LSD radix sort of `count` keys (and values) in registers, laid out
+// by block_rows / bpos (callers load and store with the same layout);
+// positions >= count are padding and stay at the end.  Only the bits in which the keys
 // differ are sorted: keys are offset by their minimum and ceil(bits/8) 8-bit
 // passes run.  Padding positions of the ranked rows hold the all-ones offset
 // key, whose digit is 255 in every pass, so they stay behind every real key
@@ -258,17 +281,18 @@ template <class K, bool HV, int NW, int IPT>
 __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, SortSmem<NW, IPT> &sm)
 {
     using T = KeyT<K>;
-    const int nrows = wave_rows<IPT>(count);
+    const int R = block_rows<NW, IPT>(count);
+    const int nrows = wave_rows_of(count, R);
     K lo = (K)T::MAXV, hi = (K)0;
 #pragma unroll
     for (int r = 0; r < IPT; ++r)
-        if (r < nrows && item_pos<NW, IPT>(r) < count) { lo = k[r] < lo ? k[r] : lo; hi = k[r] > hi ? k[r] : hi; }
+        if (r < nrows && bpos(r, R) < count) { lo = k[r] < lo ? k[r] : lo; hi = k[r] > hi ? k[r] : hi; }
     block_minmax<K, NW>(lo, hi, sm.red32, sm.red64);
     if (count <= 1 || !(lo < hi)) return;          // already in order (uniform branch)
     const int passes = (T::bitlen((K)(hi - lo)) + 7) / 8;
 #pragma unroll
     for (int r = 0; r < IPT; ++r)
-        if (r < nrows) k[r] = item_pos<NW, IPT>(r) < count ? (K)(k[r] - lo) : (K)T::MAXV;
+        if (r < nrows) k[r] = bpos(r, R) < count ? (K)(k[r] - lo) : (K)T::MAXV;
     RankTab<256> &tab = sm.s.tab[wave_id()];
     uint32_t pos[IPT];
     for (int ps = 0; ps < passes; ++ps) {
@@ -290,7 +314,7 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < IPT; ++r)
-                if (r < nrows) k[r] = T::set_word(k[r], wd, sm.s.buf[item_pos<NW, IPT>(r)]);
+                if (r < nrows) k[r] = T::set_word(k[r], wd, sm.s.buf[bpos(r, R)]);
             __syncthreads();
         }
         if (HV) {
@@ -300,7 +324,7 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < IPT; ++r)
-                if (r < nrows) v[r] = sm.s.buf[item_pos<NW, IPT>(r)];
+                if (r < nrows) v[r] = sm.s.buf[bpos(r, R)];
             __syncthreads();
         }
     }

@@ -88,11 +88,23 @@ template <class K> struct Batch {
     uint32_t *tot;      // [j] per node
     BucketItem *list[NCLS];
     uint32_t cap[NCLS];
-    uint32_t *ctr;      // NCLS counters
+    uint32_t *ctr;      // NCLS list sizes, then NCLS take counters (work-groups claim items)
     unsigned long long *H;
 };
 
 // largest k with prefix[k] <= item (prefix is non-decreasing, prefix[0] = 0)
+// Claims the next item of list c for the calling work-group (all threads get
+// the same index).  Items of the bucket lists differ widely in cost, so
+// work-groups take them one by one instead of in a fixed stride.
+__device__ inline uint32_t take_item(uint32_t *ctr, int c, uint32_t *slot)
+{
+    if (threadIdx.x == 0) *slot = atomicAdd(&ctr[NCLS + c], 1u);
+    __syncthreads();
+    const uint32_t it = *slot;
+    __syncthreads();
+    return it;
+}
+
 __device__ inline uint32_t find_node(const uint32_t *prefix, uint32_t N, uint32_t item)
 {
     uint32_t lo = 0, hi = N - 1;
@@ -153,17 +165,18 @@ __global__ __launch_bounds__(SORT_NT) void k_sort_pivots_big(Batch<K> b)
     K k[SORT_IPT];
     uint32_t v[SORT_IPT];
     tables_clear<SORT_NW, 256>(sm.s.tab);
+    const int R = block_rows<SORT_NW, SORT_IPT>(cnt);
 #pragma unroll
     for (int r = 0; r < SORT_IPT; ++r) {
-        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-        k[r] = p < cnt ? b.piv[nd.piv + p] : (K)0;
+        const uint32_t p = bpos(r, R);
+        k[r] = r < R && p < cnt ? b.piv[nd.piv + p] : (K)0;
     }
     __syncthreads();
     block_sort<K, false, SORT_NW, SORT_IPT>(k, v, cnt, sm);
 #pragma unroll
     for (int r = 0; r < SORT_IPT; ++r) {
-        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-        if (p < cnt) { b.piv[nd.piv + p] = k[r]; sm.k64[p] = (uint64_t)k[r]; }
+        const uint32_t p = bpos(r, R);
+        if (r < R && p < cnt) { b.piv[nd.piv + p] = k[r]; sm.k64[p] = (uint64_t)k[r]; }
     }
     __syncthreads();
     for (uint32_t t = threadIdx.x; t < cnt; t += SORT_NT)
@@ -263,10 +276,11 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
         K kk[SORT_IPT];
         uint32_t vv[SORT_IPT];
         tables_clear<SORT_NW, 256>(sm.s.tab);           // the previous search reused this LDS
+        const int R = block_rows<SORT_NW, SORT_IPT>(len);
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
-            const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-            const bool ok = p < len;
+            const uint32_t p = bpos(r, R);
+            const bool ok = r < R && p < len;
             kk[r] = ok ? (sorted ? dst[base + p] : src[base + p]) : (K)0;
             if (HV) vv[r] = ok && !sorted ? vsrc[base + p] : 0u;
         }
@@ -275,8 +289,8 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
             block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm);
 #pragma unroll
             for (int r = 0; r < SORT_IPT; ++r) {
-                const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-                if (p < len) {
+                const uint32_t p = bpos(r, R);
+                if (r < R && p < len) {
                     dst[base + p] = kk[r];
                     if (HV) vdst[base + p] = vv[r];
                 }
@@ -285,8 +299,8 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
-            const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-            if (p < len) { if (sizeof(K) == 4) sm.k32[p] = (uint32_t)kk[r]; else sm.k64[p] = (uint64_t)kk[r]; }
+            const uint32_t p = bpos(r, R);
+            if (r < R && p < len) { if (sizeof(K) == 4) sm.k32[p] = (uint32_t)kk[r]; else sm.k64[p] = (uint64_t)kk[r]; }
         }
         __syncthreads();
         // this thread's pivots and strict flags, as 16-byte loads of its
@@ -824,23 +838,25 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_mid(Batch<K> b, const K *A, 
     __shared__ SortSm sm;
     tables_clear<SORT_NW, 256>(sm.s.tab);
     __syncthreads();
+    __shared__ uint32_t take_sh;
     const uint32_t cnt = min(b.ctr[CLS_MID], b.cap[CLS_MID]);
-    for (uint32_t it = blockIdx.x; it < cnt; it += gridDim.x) {
+    for (uint32_t it = take_item(b.ctr, CLS_MID, &take_sh); it < cnt; it = take_item(b.ctr, CLS_MID, &take_sh)) {
         const BucketItem e = b.list[CLS_MID][it];
         const uint64_t base = b.nodes[e.node].off + e.lo;
         K kk[SORT_IPT];
         uint32_t vv[SORT_IPT];
+        const int R = block_rows<SORT_NW, SORT_IPT>(e.size);
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
-            const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-            kk[r] = p < e.size ? A[base + p] : (K)0;
-            if (HV) vv[r] = p < e.size ? VA[base + p] : 0u;
+            const uint32_t p = bpos(r, R);
+            kk[r] = r < R && p < e.size ? A[base + p] : (K)0;
+            if (HV) vv[r] = r < R && p < e.size ? VA[base + p] : 0u;
         }
         block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, e.size, sm);
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
-            const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-            if (p < e.size) {
+            const uint32_t p = bpos(r, R);
+            if (r < R && p < e.size) {
                 D[base + p] = kk[r];
                 if (HV) VD[base + p] = vv[r];
             }
@@ -886,8 +902,9 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
     __shared__ uint32_t hist[256], base[256], run[256];
     __shared__ uint32_t sp_sh, overflow_sh;
     const uint32_t tid = threadIdx.x;
+    __shared__ uint32_t take_sh;
     const uint32_t cnt = min(b.ctr[CLS_BIG], b.cap[CLS_BIG]);
-    for (uint32_t it = blockIdx.x; it < cnt; it += gridDim.x) {
+    for (uint32_t it = take_item(b.ctr, CLS_BIG, &take_sh); it < cnt; it = take_item(b.ctr, CLS_BIG, &take_sh)) {
         const BucketItem e = b.list[CLS_BIG][it];
         const NodeDesc nd = b.nodes[e.node];
         const uint64_t bbase = nd.off + e.lo;
@@ -919,18 +936,19 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
                     K kk[SORT_IPT];
                     uint32_t vv[SORT_IPT];
                     tables_clear<SORT_NW, 256>(sm.s.tab);
+                    const int R = block_rows<SORT_NW, SORT_IPT>(sg.size);
 #pragma unroll
                     for (int r = 0; r < SORT_IPT; ++r) {
-                        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-                        kk[r] = p < sg.size ? src[sb + p] : (K)0;
-                        if (HV) vv[r] = p < sg.size ? vsrc[sb + p] : 0u;
+                        const uint32_t p = bpos(r, R);
+                        kk[r] = r < R && p < sg.size ? src[sb + p] : (K)0;
+                        if (HV) vv[r] = r < R && p < sg.size ? vsrc[sb + p] : 0u;
                     }
                     __syncthreads();
                     block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, sg.size, sm);
 #pragma unroll
                     for (int r = 0; r < SORT_IPT; ++r) {
-                        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-                        if (p < sg.size) {
+                        const uint32_t p = bpos(r, R);
+                        if (r < R && p < sg.size) {
                             D[sb + p] = kk[r];
                             if (HV) VD[sb + p] = vv[r];
                         }
@@ -1058,18 +1076,19 @@ __global__ __launch_bounds__(SORT_NT) void k_base_sort(uint32_t n, const K *A, c
     K kk[SORT_IPT];
     uint32_t vv[SORT_IPT];
     tables_clear<SORT_NW, 256>(sm.s.tab);
+    const int R = block_rows<SORT_NW, SORT_IPT>(n);
 #pragma unroll
     for (int r = 0; r < SORT_IPT; ++r) {
-        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-        kk[r] = p < n ? A[p] : (K)0;
-        if (HV) vv[r] = p < n ? VA[p] : 0u;
+        const uint32_t p = bpos(r, R);
+        kk[r] = r < R && p < n ? A[p] : (K)0;
+        if (HV) vv[r] = r < R && p < n ? VA[p] : 0u;
     }
     __syncthreads();
     block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, n, sm);
 #pragma unroll
     for (int r = 0; r < SORT_IPT; ++r) {
-        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
-        if (p < n) {
+        const uint32_t p = bpos(r, R);
+        if (r < R && p < n) {
             D[p] = kk[r];
             if (HV) VD[p] = vv[r];
         }

@@ -285,7 +285,7 @@ template <class K, bool HV> struct Engine {
         b.list[CLS_INTERNAL] = ws.take<BucketItem>(capInt);
         b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID] = capMid;
         b.cap[CLS_BIG] = capBig; b.cap[CLS_INTERNAL] = capInt;
-        b.ctr = ws.take<uint32_t>(NCLS);
+        b.ctr = ws.take<uint32_t>(2 * NCLS);
         b.H = ws.take<unsigned long long>(N);
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         b.nodes = dDesc;
@@ -341,7 +341,7 @@ template <class K, bool HV> struct Engine {
         if (int rc = check()) return rc;
 
         // ---- buckets A -> D, by class
-        k_fill_u32<<<1, 64, 0, st>>>(b.ctr, NCLS, 0u);
+        k_fill_u32<<<1, 64, 0, st>>>(b.ctr, 2 * NCLS, 0u);
         launch("k_classify", bucS[N], [&] { k_classify<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b, cutoff); });
         launch("k_bucket_copy", keysTot, [&] { k_bucket_copy<K, HV><<<512, 256, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket_w", keysTot, [&] {
@@ -401,13 +401,13 @@ template <class K, bool HV> struct Engine {
         Batch<K> b{};
         NodeDesc *dDesc = ws.take<NodeDesc>(1);
         BucketItem *item = ws.take<BucketItem>(1);
-        uint32_t *ctr = ws.take<uint32_t>(NCLS);
+        uint32_t *ctr = ws.take<uint32_t>(2 * NCLS);
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         host_node_ = NodeDesc{};
         host_node_.n = (uint32_t)n;
         host_node_.m = 1;
         host_item_ = BucketItem{0u, 0u, 0u, (uint32_t)n};
-        for (int c = 0; c < NCLS; ++c) host_ctr_[c] = c == CLS_BIG ? 1u : 0u;
+        for (int c = 0; c < 2 * NCLS; ++c) host_ctr_[c] = c == CLS_BIG ? 1u : 0u;
         if (hipMemcpyAsync(dDesc, &host_node_, sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
             hipMemcpyAsync(item, &host_item_, sizeof(BucketItem), hipMemcpyHostToDevice, st) != hipSuccess ||
             hipMemcpyAsync(ctr, host_ctr_, sizeof(host_ctr_), hipMemcpyHostToDevice, st) != hipSuccess)
@@ -423,7 +423,7 @@ template <class K, bool HV> struct Engine {
     }
     NodeDesc host_node_{};
     BucketItem host_item_{};
-    uint32_t host_ctr_[NCLS] = {};
+    uint32_t host_ctr_[2 * NCLS] = {};
 
     int sort_root(uint64_t n, uint64_t seed)
     {
