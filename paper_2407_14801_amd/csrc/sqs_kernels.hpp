@@ -230,11 +230,23 @@ template <> __device__ inline uint64_t piv_of<uint64_t>(const uint4 *raw, int q)
     return (q & 1) == 0 ? ((uint64_t)v.y << 32 | v.x) : ((uint64_t)v.w << 32 | v.z);
 }
 
+__device__ inline bool strict_of(const uint4 &raw, int q)
+{
+    const uint32_t w = q < 4 ? raw.x : q < 8 ? raw.y : q < 12 ? raw.z : raw.w;
+    return ((w >> (8 * (q & 3))) & 255u) != 0;
+}
+
 // ------------------------------------------------------------ column phase
 __device__ inline uint32_t column_len(uint32_t i, uint32_t m, uint32_t n)
 {
     const uint64_t lo = (uint64_t)i * m;
     return lo < n ? (uint32_t)min((uint64_t)m, (uint64_t)n - lo) : 0u;
+}
+
+// key at position p of a sorted column held in LDS
+template <class K> __device__ inline K col_key(const SortSm &sm, uint32_t p)
+{
+    return sizeof(K) == 4 ? (K)sm.k32[p] : (K)sm.k64[p];
 }
 
 // Nodes with m > WCAP: one work-group per (node, column group).  Each column
@@ -314,34 +326,59 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
             for (int v4 = 0; v4 < PV4; ++v4) praw[v4] = p4[v4];
             sraw = *reinterpret_cast<const uint4 *>(b.strict + nd.piv + t0);
         }
-        uint32_t prev = 0;
+        // Each pivot's position in the sorted column (keys at or below it).
+        // The slice's first and last pivot are searched over the whole
+        // column, the others inside that bracket; the searches of one step
+        // are independent, so their LDS reads overlap.
+        const uint32_t nq = t0 < npiv ? min((uint32_t)PPT, npiv - t0) : 0u;
+        if (nq > 0) {
+            K pf = (K)0, pl = (K)0;
+            bool sf = false, sl = false;
 #pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-            const uint32_t t = t0 + q;
-            if (t >= npiv) break;
-            const K pv = piv_of<K>(praw, q);
-            const uint32_t sw = q < 4 ? sraw.x : q < 8 ? sraw.y : q < 12 ? sraw.z : sraw.w;
-            const bool ps = ((sw >> (8 * (q & 3))) & 255u) != 0;
-            uint32_t a = prev, e = len;
-            if (q > 0) {                                  // gallop from the previous answer
-                uint32_t step = 1;
-                while (true) {
-                    const uint32_t c2 = a + step - 1;
-                    if (c2 >= len) break;
-                    const K x = sizeof(K) == 4 ? (K)sm.k32[c2] : (K)sm.k64[c2];
-                    if (!le_pivot(x, pv, ps)) { e = c2; break; }
-                    a = c2 + 1;
-                    step <<= 1;
+            for (int q = 0; q < PPT; ++q) {
+                if (q == 0) { pf = piv_of<K>(praw, q); sf = strict_of(sraw, q); }
+                if (q == (int)nq - 1) { pl = piv_of<K>(praw, q); sl = strict_of(sraw, q); }
+            }
+            uint32_t af = 0, ef = len, al = 0, el = len;
+            while (af < ef || al < el) {
+                if (af < ef) {
+                    const uint32_t mid = (af + ef) >> 1;
+                    if (le_pivot(col_key<K>(sm, mid), pf, sf)) af = mid + 1; else ef = mid;
+                }
+                if (al < el) {
+                    const uint32_t mid = (al + el) >> 1;
+                    if (le_pivot(col_key<K>(sm, mid), pl, sl)) al = mid + 1; else el = mid;
                 }
             }
-            while (a < e) {
-                const uint32_t mid = (a + e) >> 1;
-                const K x = sizeof(K) == 4 ? (K)sm.k32[mid] : (K)sm.k64[mid];
-                if (le_pivot(x, pv, ps)) a = mid + 1; else e = mid;
+            uint32_t A[PPT], E[PPT];
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                const bool inner = q > 0 && q + 1 < (int)nq;
+                A[q] = inner ? af : 0u;
+                E[q] = inner ? al : 0u;
             }
-            prev = a;
-            P[q] += a;
-            if ((t + 1) % TB == 0) b.srcOff[nd.src + (uint64_t)((t + 1) / TB) * m + i] = a;
+            bool more = true;
+            while (more) {
+                more = false;
+#pragma unroll
+                for (int q = 1; q + 1 < PPT; ++q) {
+                    if (A[q] < E[q]) {
+                        const uint32_t mid = (A[q] + E[q]) >> 1;
+                        if (le_pivot(col_key<K>(sm, mid), piv_of<K>(praw, q), strict_of(sraw, q))) A[q] = mid + 1;
+                        else E[q] = mid;
+                        more |= A[q] < E[q];
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                if (q < (int)nq) {
+                    const uint32_t t = t0 + q;
+                    const uint32_t a = q == 0 ? af : (q == (int)nq - 1 ? al : A[q]);
+                    P[q] += a;
+                    if ((t + 1) % TB == 0) b.srcOff[nd.src + (uint64_t)((t + 1) / TB) * m + i] = a;
+                }
+            }
         }
         if (threadIdx.x == 0) {
             b.srcOff[nd.src + i] = 0;
