@@ -99,13 +99,17 @@ template <class T> __device__ inline T wave_max(T v)
     for (int o = WAVE / 2; o > 0; o >>= 1) { T u = __shfl_xor(v, o, WAVE); v = u > v ? u : v; }
     return v;
 }
+// Inclusive scan over the 64 lanes (all lanes active): shifts within rows of
+// 16 lanes, then the last lane of rows 0 and 2 into rows 1 and 3, then lane
+// 31 into rows 2 and 3 (DPP row_shr / row_bcast, no LDS round trips).
 __device__ inline uint32_t wave_incl_scan(uint32_t v)
 {
-    const uint32_t l = lane_id();
-    for (int o = 1; o < WAVE; o <<= 1) {
-        uint32_t u = __shfl_up(v, o, WAVE);
-        if (l >= (uint32_t)o) v += u;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return v;
 }
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v)
@@ -241,20 +245,23 @@ __device__ inline void scan_tables(RankTab<RDX> *tab, uint32_t *wsum)
 {
     static_assert(RDX <= NW * WAVE, "one thread per digit value");
     const uint32_t t = threadIdx.x;
-    uint32_t tot = 0;
-    if (t < (uint32_t)RDX)
-        for (int ww = 0; ww < NW; ++ww) tot += tab[ww].cnt[t];
+    uint32_t c[NW], tot = 0;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+        c[ww] = t < (uint32_t)RDX ? tab[ww].cnt[t] : 0u;
+        tot += c[ww];
+    }
     const uint32_t incl = wave_incl_scan(tot);
     if (lane_id() == WAVE - 1) wsum[wave_id()] = incl;
     __syncthreads();
     if (t < (uint32_t)RDX) {
         uint32_t run = incl - tot;
         for (uint32_t ww = 0; ww < wave_id(); ++ww) run += wsum[ww];
+#pragma unroll
         for (int ww = 0; ww < NW; ++ww) {
-            const uint32_t c = tab[ww].cnt[t];
             tab[ww].off[t] = run;
             tab[ww].cnt[t] = 0u;
-            run += c;
+            run += c[ww];
         }
     }
     __syncthreads();
@@ -274,20 +281,27 @@ __device__ inline uint32_t digit8(uint64_t x, int sh)
 // differ are sorted: keys are offset by their minimum and ceil(bits/8) 8-bit
 // passes run.  Padding positions of the ranked rows hold the all-ones offset
 // key, whose digit is 255 in every pass, so they stay behind every real key
-// without a per-key test in the passes.  Tables must be clear on entry
-// (tables_clear + barrier); they are clear again on return.  Ends with a
-// barrier.  On return only positions < count hold meaningful keys.
+// without a per-key test in the passes.  With `bounded`, [blo, bhi] is a
+// caller-known range of the keys and replaces the block-wide min/max.  Tables
+// must be clear on entry (tables_clear + barrier); they are clear again on
+// return.  Ends with a barrier unless it returns at once (count <= 1 or a
+// single key value).  On return only positions < count hold meaningful keys.
 template <class K, bool HV, int NW, int IPT>
-__device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, SortSmem<NW, IPT> &sm)
+__device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, SortSmem<NW, IPT> &sm,
+                           bool bounded = false, K blo = (K)0, K bhi = (K)0)
 {
     using T = KeyT<K>;
     const int R = block_rows<NW, IPT>(count);
     const int nrows = wave_rows_of(count, R);
-    K lo = (K)T::MAXV, hi = (K)0;
+    K lo = blo, hi = bhi;                          // bounded: every key lies in [blo, bhi]
+    if (!bounded) {
+        lo = (K)T::MAXV;
+        hi = (K)0;
 #pragma unroll
-    for (int r = 0; r < IPT; ++r)
-        if (r < nrows && bpos(r, R) < count) { lo = k[r] < lo ? k[r] : lo; hi = k[r] > hi ? k[r] : hi; }
-    block_minmax<K, NW>(lo, hi, sm.red32, sm.red64);
+        for (int r = 0; r < IPT; ++r)
+            if (r < nrows && bpos(r, R) < count) { lo = k[r] < lo ? k[r] : lo; hi = k[r] > hi ? k[r] : hi; }
+        block_minmax<K, NW>(lo, hi, sm.red32, sm.red64);
+    }
     if (count <= 1 || !(lo < hi)) return;          // already in order (uniform branch)
     const int passes = (T::bitlen((K)(hi - lo)) + 7) / 8;
 #pragma unroll

@@ -867,6 +867,17 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_bucket_small(Batch<K> b, const
     }
 }
 
+// Inclusive key bounds of bucket j (see single_value_bucket).
+template <class K>
+__device__ inline void bucket_bounds(const Batch<K> &b, const NodeDesc &nd, uint32_t j, K &lo, K &hi)
+{
+    const K MAXV = (K)KeyT<K>::MAXV;
+    if (j == 0) lo = 0;
+    else { const K s = b.piv[nd.piv + j - 1]; lo = b.strict[nd.piv + j - 1] ? s : (K)(s + 1); }
+    if (j == nd.m - 1) hi = MAXV;
+    else { const K s = b.piv[nd.piv + j]; hi = b.strict[nd.piv + j] ? (K)(s - 1) : s; }
+}
+
 // Buckets of WCAP+1 .. cutoff keys: one work-group per bucket (persistent).
 template <class K, bool HV>
 __global__ __launch_bounds__(SORT_NT) void k_bucket_mid(Batch<K> b, const K *A, const uint32_t *VA,
@@ -889,7 +900,9 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_mid(Batch<K> b, const K *A, 
             kk[r] = r < R && p < e.size ? A[base + p] : (K)0;
             if (HV) vv[r] = r < R && p < e.size ? VA[base + p] : 0u;
         }
-        block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, e.size, sm);
+        K blo, bhi;
+        bucket_bounds(b, b.nodes[e.node], e.j, blo, bhi);
+        block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, e.size, sm, true, blo, bhi);
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
             const uint32_t p = bpos(r, R);
@@ -902,16 +915,6 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_mid(Batch<K> b, const K *A, 
     }
 }
 
-// Inclusive key bounds of bucket j (see single_value_bucket).
-template <class K>
-__device__ inline void bucket_bounds(const Batch<K> &b, const NodeDesc &nd, uint32_t j, K &lo, K &hi)
-{
-    const K MAXV = (K)KeyT<K>::MAXV;
-    if (j == 0) lo = 0;
-    else { const K s = b.piv[nd.piv + j - 1]; lo = b.strict[nd.piv + j - 1] ? s : (K)(s + 1); }
-    if (j == nd.m - 1) hi = MAXV;
-    else { const K s = b.piv[nd.piv + j]; hi = b.strict[nd.piv + j] ? (K)(s - 1) : s; }
-}
 
 // Buckets of CAP+1 .. cutoff keys (a base case larger than one LDS sort):
 // one work-group per bucket (persistent) runs an MSD radix split through
@@ -981,7 +984,7 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
                         if (HV) vv[r] = r < R && p < sg.size ? vsrc[sb + p] : 0u;
                     }
                     __syncthreads();
-                    block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, sg.size, sm);
+                    block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, sg.size, sm, true, (K)sg.lo, (K)sg.hi);
 #pragma unroll
                     for (int r = 0; r < SORT_IPT; ++r) {
                         const uint32_t p = bpos(r, R);
