@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="u32_uniform", choices=sorted(WORKLOADS))
     ap.add_argument("--log2n", type=int, default=None, help="override the size (2^k keys)")
+    ap.add_argument("--cutoff", type=int, default=0, help="base-case cut-off (0 = the library's automatic choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
@@ -171,7 +172,7 @@ def main():
         w = 4
 
         def step(i):
-            return binding.squaresort_u32(ins[i], out, seed=seed, cutoff=0, ws=ws)
+            return binding.squaresort_u32(ins[i], out, seed=seed, cutoff=args.cutoff, ws=ws)
     else:
         bk = torch.from_numpy(host[0].view(np.int64)).to(dev)
         bv = torch.from_numpy(host[1].view(np.int32)).to(dev)
@@ -180,7 +181,7 @@ def main():
         w = 12
 
         def step(i):
-            return binding.squaresort_kv(ins[i][0], ins[i][1], ko, vo, seed=seed, cutoff=0, ws=ws)
+            return binding.squaresort_kv(ins[i][0], ins[i][1], ko, vo, seed=seed, cutoff=args.cutoff, ws=ws)
     torch.cuda.synchronize()
 
     print(f"# warmup {args.warmup}", file=sys.stderr, flush=True)

@@ -65,7 +65,7 @@ struct BucketItem {
 };
 enum { CLS_COPY = 0, CLS_SMALL = 1, CLS_MID = 2, CLS_BIG = 3, CLS_INTERNAL = 4, NCLS = 5 };
 constexpr uint32_t COPY_CH = 32768;           // keys per piece of a single-value bucket copy
-constexpr uint32_t BIG_CAP = 4 * SORT_CAP;   // largest automatic cut-off: 65536 keys
+constexpr uint32_t BIG_CAP = 8 * SORT_CAP;   // largest automatic cut-off: 131072 keys
 
 template <class K> struct Batch {
     const NodeDesc *nodes;
@@ -931,7 +931,8 @@ struct BigSeg {
     uint64_t lo, hi;             // inclusive key range of the segment
 };
 constexpr int BIG_STACK = 256;
-constexpr int SPLIT_BITS = 3;
+constexpr int SPLIT_MAX = 4;                 // at most 16 parts per split
+constexpr uint32_t SPLIT_PART = 12288;       // aimed part size (fits one LDS sort with room)
 
 template <class K, bool HV>
 __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32_t *VA, K *D, uint32_t *VD)
@@ -940,6 +941,7 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
     __shared__ SortSm sm;
     __shared__ BigSeg stack[BIG_STACK];
     __shared__ uint32_t hist[256], base[256], run[256];
+    __shared__ uint32_t whist[SORT_NW][1 << SPLIT_MAX];
     __shared__ uint32_t sp_sh, overflow_sh;
     const uint32_t tid = threadIdx.x;
     __shared__ uint32_t take_sh;
@@ -997,19 +999,37 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
                 __syncthreads();
                 continue;
             }
-            // ---- split by the top SPLIT_BITS bits of (x - lo)
+            // ---- split by the top sbits bits of (x - lo).  A range of at
+            // most SPLIT_MAX bits is split into single values (copied, not
+            // sorted); otherwise sbits is the fewest bits that give parts of
+            // about SPLIT_PART keys and the fewest 8-bit passes per part that
+            // any split of at most SPLIT_MAX bits gives
             K *dstb = sg.in_d ? A : D;
             uint32_t *vdstb = sg.in_d ? VA : VD;
             const K klo = (K)sg.lo;
             const int bits = T::bitlen((K)((K)sg.hi - klo));
-            const int sbits = bits < SPLIT_BITS ? bits : SPLIT_BITS;
+            int sbits = bits;
+            if (bits > SPLIT_MAX) {
+                const int best = (bits - SPLIT_MAX + 7) / 8;
+                sbits = min(32 - __clz((sg.size - 1) / SPLIT_PART), SPLIT_MAX);
+                while (sbits < SPLIT_MAX && (bits - sbits + 7) / 8 > best) ++sbits;
+            }
             const int shift = bits - sbits;
             const uint32_t nparts = 1u << sbits;
             if (tid < 256) { hist[tid] = 0; run[tid] = 0; }
+            if (tid < SORT_NW * (1 << SPLIT_MAX)) (&whist[0][0])[tid] = 0;
             __syncthreads();
-            for (uint32_t c0 = 0; c0 < sg.size; c0 += SORT_CAP)          // count
-                for (uint32_t p = c0 + tid; p < min(sg.size, c0 + (uint32_t)SORT_CAP); p += SORT_NT)
-                    atomicAdd(&hist[min((uint32_t)(((K)(src[sb + p] - klo)) >> shift), nparts - 1)], 1u);
+            {                                                            // count, per-wave histograms
+                uint32_t *wh = whist[wave_id()];
+                for (uint32_t p = tid; p < sg.size; p += SORT_NT)
+                    atomicAdd(&wh[min((uint32_t)(((K)(src[sb + p] - klo)) >> shift), nparts - 1)], 1u);
+            }
+            __syncthreads();
+            if (tid < nparts) {
+                uint32_t c = 0;
+                for (int w = 0; w < SORT_NW; ++w) c += whist[w][tid];
+                hist[tid] = c;
+            }
             __syncthreads();
             if (tid < WAVE) {                                            // exclusive scan of <= 256 counts
                 uint32_t c[4], t4 = 0;
@@ -1101,7 +1121,7 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
                 sp_sh = top;
             }
             __syncthreads();
-            if (overflow_sh) break;      // cannot happen: depth <= key bits / SPLIT_BITS
+            if (overflow_sh) break;      // cannot happen: a split of s <= 4 bits adds 2^s - 1 <= 3.75 s entries, s summed over the depth <= key bits
         }
         __syncthreads();
     }

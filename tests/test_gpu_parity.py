@@ -88,7 +88,9 @@ U32_CASES = [
     (16384, 0), (16385, 0), (65537, 0), (65537, 64), (1_000_003, 0),
     ((1 << 20) + 3, 0), (3_000_017, 0), (130_000, 256),
     # whole array a base case sorted with MSD splits (16384 < n <= cutoff)
-    (16_385, 0), (50_000, 0), (65_536, 0),
+    (16_385, 0), (50_000, 0), (65_536, 0), (100_000, 0), (131_072, 0),
+    # just above the automatic cut-off: one internal level with big buckets
+    (131_073, 0),
     # buckets of 16K..64K keys (MSD-split base cases inside the bucket phase)
     ((1 << 24) + 5, 0), ((1 << 22) + 1, 20_000),
 ]
@@ -185,7 +187,7 @@ def test_skew_transpose_is_root_of_sort(b, ws):
 
 # ------------------------------------------------------------------ u64, kv
 @pytest.mark.parametrize("n,cutoff", [(1, 0), (7, 4), (5000, 16), (16385, 0), (300_001, 0), (70_001, 64),
-                                      (40_000, 0), ((1 << 22) + 7, 30_000)])
+                                      (40_000, 0), (120_000, 0), ((1 << 22) + 7, 30_000)])
 def test_u64_matches_oracle(b, ws, n, cutoff):
     _say(f"u64 n={n} cutoff={cutoff}")
     x = datagen.uniform_u64(n, seed=n)
@@ -198,7 +200,7 @@ def test_u64_matches_oracle(b, ws, n, cutoff):
 
 
 @pytest.mark.parametrize("n,cutoff", [(9, 4), (5000, 16), (40_000, 64), (300_007, 0), (60_000, 0),
-                                      ((1 << 23) + 3, 0)])
+                                      (125_000, 0), ((1 << 23) + 3, 0)])
 def test_kv_matches_oracle(b, ws, n, cutoff):
     _say(f"kv n={n} cutoff={cutoff}")
     k, v = datagen.kv_mixture(n, seed=4)
