@@ -39,6 +39,9 @@ WORKLOADS = {
     "u32_dup16": dict(kind="u32", log2n=28, dist="uniform[0,2^16)", data_seed=3),
     "kv_mixture": dict(kind="kv", log2n=27, dist="80% Zipf(1.1) over 2^20 u64 / 10% constant / "
                                                   "10% sorted run with 1% swaps", data_seed=4),
+    # many independent instances in one call, against one call per instance
+    "batched_u32": dict(kind="batched", count=4096, lo=1 << 10, hi=1 << 20, dist="uniform[0,2^32)",
+                        data_seed=5),
 }
 
 
@@ -112,6 +115,115 @@ def cpu_baseline(wl, host, cutoff, seed, log2_sample):
                       f"of the same input, same seed and cut-off"}
 
 
+def roofline_of(timing, steps, w, traffic_key=None):
+    """Per-kernel shares and the dominant kernel against the HBM peak."""
+    kern = {}
+    if not timing:
+        return None, kern
+    tot = sum(v["ms"] for v in timing.values())
+    for k, v in timing.items():
+        kern[k] = {"ms_per_step": v["ms"] / steps, "launches_per_step": v["launches"] / steps,
+                   "share": v["ms"] / tot if tot else 0.0}
+    dom = max(timing, key=lambda k: timing[k]["ms"])
+    d = timing[dom]
+    avg_ms = d["ms"] / d["launches"]
+    bytes_per_launch = 2 * w * d["units"] / d["launches"]     # read + write of each key
+    ach = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    traffic = None
+    if traffic_key and os.path.exists(TRAFFIC_JSON):
+        with open(TRAFFIC_JSON) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == source_hash() and tr.get("kernel") == dom and tr.get("workload") == traffic_key:
+            traffic = int(tr["traffic_bytes_per_launch"])
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic,
+            "avg_launch_ms": round(avg_ms, 5), "alg_bytes_per_launch": int(bytes_per_launch)}
+    return roof, kern
+
+
+def bench_batched(args, wl):
+    """4096 instances, sizes log-uniform in [2^10, 2^20], one batched call per
+    step; the plain path (one call per instance, same seeds and cut-off) is
+    timed on the same data and must give the same bytes."""
+    import torch
+    from paper_2407_14801_amd import autotune, binding, datagen
+    dev = torch.device("cuda:0")
+    sizes = datagen.log_uniform_sizes(wl["count"], wl["lo"], wl["hi"], seed=wl["data_seed"])
+    total = int(sizes.sum())
+    print(f"# generating {wl['count']} instances, {total} keys", file=sys.stderr, flush=True)
+    keys = datagen.uniform_u32(total, seed=wl["data_seed"] + 1000)
+    offs = binding.batched_offsets(sizes)
+    seeds = np.arange(1, wl["count"] + 1, dtype=np.uint64)
+    ws = binding.Workspace(dev)
+    base = torch.from_numpy(keys.view(np.int32)).to(dev)
+    cutoff, tune = args.cutoff, None
+    if args.autotune:
+        print("# autotuning the cut-off", file=sys.stderr, flush=True)
+        cutoff, tune = autotune.tune_batched_cutoff(base, offs, seeds, ws=ws)
+    ins = [base.clone() for _ in range(args.warmup + args.steps)]
+    out = torch.empty_like(base)
+    for i in range(args.warmup):
+        used = binding.squaresort_batched_u32(ins[i], out, offs, seeds, cutoff=cutoff, ws=ws)
+    torch.cuda.synchronize()
+    if not args.no_timing:
+        binding.timing_enable(True)
+    print(f"# timing {args.steps} batched steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        used = binding.squaresort_batched_u32(ins[i], out, offs, seeds, cutoff=cutoff, ws=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timing = binding.timing_report() if not args.no_timing else {}
+    binding.timing_enable(False)
+    del ins
+    ms = (t1 - t0) * 1e3 / args.steps
+
+    # plain path: one call per instance on a fresh copy
+    print(f"# timing {args.plain_steps} plain steps ({wl['count']} calls each)", file=sys.stderr, flush=True)
+    plain_out = torch.empty_like(base)
+    bounds = [(int(offs[i]), int(offs[i + 1])) for i in range(wl["count"])]
+    plain_ms = []
+    for r in range(args.plain_steps + 1):            # the first is a warm-up
+        src = base.clone()
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        for i, (lo, hi) in enumerate(bounds):
+            binding.squaresort_u32(src[lo:hi], plain_out[lo:hi], seed=int(seeds[i]), cutoff=used, ws=ws)
+        torch.cuda.synchronize()
+        if r:
+            plain_ms.append((time.perf_counter() - p0) * 1e3)
+    same = bool(torch.equal(out, plain_out))
+    o = out.to(torch.int64) & 0xFFFFFFFF
+    ok = o[1:] >= o[:-1]
+    starts = torch.from_numpy(offs[1:-1].astype(np.int64) - 1).to(dev)
+    ok[starts[starts >= 0]] = True                    # instance boundaries may descend
+    sorted_ok = bool(ok.all().item())
+
+    w = 4
+    roof, kern = roofline_of(timing, args.steps, w)
+    b_alg = 6 * w * total
+    pms = float(np.median(plain_ms))
+    res = {
+        "metric": "GKeys/s", "value": round(total / (ms / 1e3) / 1e9, 4), "unit": "GKeys/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"batched_u32_{wl['count']}x_loguniform[2^10,2^20]", "instances": wl["count"],
+                   "total_keys": total, "key_dist": wl["dist"], "data_seed": wl["data_seed"],
+                   "seeds": "1..count", "cutoff": int(used), "autotune": tune},
+        "plain_per_instance": {"value": round(total / (pms / 1e3) / 1e9, 4), "unit": "GKeys/s",
+                               "ms_per_step": round(pms, 3), "calls_per_step": wl["count"]},
+        "speedup_vs_plain": round(pms / ms, 3),
+        "same_bytes_as_plain": same,
+        "roofline": roof,
+        "path_roofline": {"bytes_alg_per_level": b_alg, "levels": 1,
+                          "achieved_gbs": round(b_alg / (ms / 1e3) / 1e9, 3), "peak_gbs": HBM_PEAK_GBS,
+                          "frac": round(b_alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 5)},
+        "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in kern.items()},
+        "sorted_check": sorted_ok,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +233,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=None, help="override the size (2^k keys)")
     ap.add_argument("--cutoff", type=int, default=0, help="base-case cut-off (0 = the library's automatic choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="batched workload: pick the cut-off by timing")
+    ap.add_argument("--plain-steps", type=int, default=2, help="batched workload: timed one-call-per-instance steps")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--calib-copy", action="store_true",
@@ -156,6 +270,8 @@ def main():
     from paper_2407_14801_amd import binding
 
     wl = WORKLOADS[args.workload]
+    if wl["kind"] == "batched":
+        return bench_batched(args, wl)
     log2n = args.log2n or wl["log2n"]
     n = 1 << log2n
     dev = torch.device("cuda:0")
@@ -225,28 +341,7 @@ def main():
             "peak_gbs": HBM_PEAK_GBS}
     path["frac"] = path["achieved_gbs"] / HBM_PEAK_GBS
 
-    roof = None
-    kern = {}
-    if timing:
-        tot = sum(v["ms"] for v in timing.values())
-        for k, v in timing.items():
-            kern[k] = {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
-                       "share": v["ms"] / tot if tot else 0.0}
-        dom = max(timing, key=lambda k: timing[k]["ms"])
-        d = timing[dom]
-        avg_ms = d["ms"] / d["launches"]
-        bytes_per_launch = 2 * w * d["units"] / d["launches"]     # read + write of each key
-        ach = bytes_per_launch / (avg_ms / 1e3) / 1e9
-        traffic = None
-        if os.path.exists(TRAFFIC_JSON):
-            with open(TRAFFIC_JSON) as f:
-                tr = json.load(f)
-            if (tr.get("source_hash") == source_hash() and tr.get("kernel") == dom
-                    and tr.get("workload") == f"squaresort_{args.workload}_2^{log2n}"):
-                traffic = int(tr["traffic_bytes_per_launch"])
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "avg_launch_ms": round(avg_ms, 5), "alg_bytes_per_launch": int(bytes_per_launch)}
+    roof, kern = roofline_of(timing, args.steps, w, f"squaresort_{args.workload}_2^{log2n}")
 
     res = {
         "metric": "GKeys/s" if wl["kind"] == "u32" else "GPairs/s",

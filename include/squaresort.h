@@ -108,6 +108,24 @@ int squaresort_kv(uint64_t n, uint64_t *keys_in, uint32_t *vals_in,
 int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket_start,
                        uint64_t seed, sqs_params *params, void *stream);
 
+/* Batched form: many independent instances in one launch sequence.
+ * `count` independent uint32 instances packed back to back in
+ * in/out: instance i is [offsets[i], offsets[i+1]) (offsets: HOST array of
+ * count+1 entries, offsets[0] = 0, non-decreasing; total offsets[count] <
+ * 2^32; each instance <= sqs_max_n(SQS_KIND_U32)).  seeds: HOST array of
+ * count seeds.  Instance i ends exactly as squaresort_u32 would leave it on
+ * that range alone with seeds[i] and the same cut-off (same output, same
+ * recursion tree); with SQS_FLAG_DIGEST the call adds the sum of the
+ * instances' digests.  All instances share one launch sequence: base-case
+ * instances go straight to the base-case kernels, the others are the root
+ * nodes of one shared first recursion step.  Errors: SQS_ERR_ARG for bad
+ * offsets/seeds/pointers, SQS_ERR_UNSUPPORTED for sizes past the limits,
+ * SQS_ERR_ALIAS, SQS_ERR_WORKSPACE below squaresort_batched_workspace_bytes. */
+uint64_t squaresort_batched_workspace_bytes(uint32_t count, const uint64_t *offsets, int kind,
+                                            uint64_t cutoff);
+int squaresort_batched_u32(uint32_t count, const uint64_t *offsets, uint32_t *in, uint32_t *out,
+                           const uint64_t *seeds, sqs_params *params, void *stream);
+
 /* Measurement support (not part of the sort): while enabled, every launch is
  * bracketed by HIP events on its stream and the elapsed times are summed per
  * kernel.  sqs_timing_enable clears the table.  sqs_timing_report writes a

@@ -42,6 +42,8 @@ _SIGS = {
     "squaresort_u64": (_i, [_u64, _vp, _vp, _u64, _P, _vp]),
     "squaresort_kv": (_i, [_u64, _vp, _vp, _vp, _vp, _u64, _P, _vp]),
     "skew_transpose_u32": (_i, [_u64, _vp, _vp, _vp, _u64, _P, _vp]),
+    "squaresort_batched_workspace_bytes": (_u64, [ctypes.c_uint32, _vp, _i, _u64]),
+    "squaresort_batched_u32": (_i, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _P, _vp]),
     "sqs_status_string": (ctypes.c_char_p, [_i]),
     "sqs_timing_enable": (_i, [_i]),
     "sqs_timing_report": (ctypes.c_int64, [ctypes.c_char_p, _u64]),
@@ -159,6 +161,45 @@ def skew_transpose_u32(inp: torch.Tensor, out: torch.Tensor, bucket_start: torch
     p, _keep = _params(n, KIND_U32, 0, ws, None)
     _check(_lib.skew_transpose_u32(n, _ptr(inp), _ptr(out), _ptr(bucket_start), seed, ctypes.byref(p),
                                    _stream(inp.device)), "skew_transpose_u32")
+
+
+def batched_offsets(sizes) -> "np.ndarray":
+    """Host offsets (count+1, uint64) of instances packed back to back."""
+    import numpy as np
+    sizes = np.asarray(sizes, dtype=np.uint64)
+    offs = np.zeros(sizes.size + 1, dtype=np.uint64)
+    np.cumsum(sizes, out=offs[1:])
+    return offs
+
+
+def batched_workspace_bytes(offsets, kind: int = KIND_U32, cutoff: int = 0) -> int:
+    import numpy as np
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    return _lib.squaresort_batched_workspace_bytes(offs.size - 1, offs.ctypes.data, kind, cutoff)
+
+
+def squaresort_batched_u32(inp: torch.Tensor, out: torch.Tensor, offsets, seeds, cutoff: int = 0,
+                           ws: Workspace | None = None, digest: torch.Tensor | None = None) -> int:
+    """Sort the instances [offsets[i], offsets[i+1]) of inp (clobbered) into
+    out, instance i with seeds[i] (host arrays).  Returns the cut-off used."""
+    import numpy as np
+    _check_dev(inp, out)
+    assert inp.dtype == torch.int32 and out.dtype == torch.int32 and inp.numel() == out.numel()
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+    count = offs.size - 1
+    assert sd.size == count and int(offs[-1]) == inp.numel()
+    nbytes = batched_workspace_bytes(offs, KIND_U32, cutoff)
+    buf = (ws or Workspace(inp.device)).get(nbytes)
+    p = Params()
+    p.cutoff = cutoff
+    p.flags = FLAG_DIGEST if digest is not None else 0
+    p.workspace = buf.data_ptr()
+    p.workspace_bytes = buf.numel()
+    p.digest = None if digest is None else digest.data_ptr()
+    _check(_lib.squaresort_batched_u32(count, offs.ctypes.data, _ptr(inp), _ptr(out), sd.ctypes.data,
+                                       ctypes.byref(p), _stream(inp.device)), "squaresort_batched_u32")
+    return p.cutoff
 
 
 def timing_enable(on: bool = True) -> None:

@@ -64,6 +64,8 @@ struct BucketItem {
     uint32_t node, j, lo, size;   // lo: node-local first slot
 };
 enum { CLS_COPY = 0, CLS_SMALL = 1, CLS_MID = 2, CLS_BIG = 3, CLS_INTERNAL = 4, NCLS = 5 };
+// device counters of a batch: NCLS list sizes, NCLS take counters, NCLS key totals
+constexpr int CTR_WORDS = 3 * NCLS;
 constexpr uint32_t COPY_CH = 32768;           // keys per piece of a single-value bucket copy
 constexpr uint32_t BIG_CAP = 8 * SORT_CAP;   // largest automatic cut-off: 131072 keys
 
@@ -88,7 +90,7 @@ template <class K> struct Batch {
     uint32_t *tot;      // [j] per node
     BucketItem *list[NCLS];
     uint32_t cap[NCLS];
-    uint32_t *ctr;      // NCLS list sizes, then NCLS take counters (work-groups claim items)
+    uint32_t *ctr;      // NCLS list sizes, NCLS take counters (work-groups claim items), NCLS key totals
     unsigned long long *H;
 };
 
@@ -802,6 +804,11 @@ __global__ void k_classify(Batch<K> b, uint32_t cutoff)
                     b.list[CLS_COPY][at] = BucketItem{it.node, it.j, it.lo + off, min(COPY_CH, it.size - off)};
             }
         }
+    }
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) {                 // keys per class (measurement)
+        const unsigned long long ks = wave_sum_u64(cls == c ? it.size : 0u);
+        if (ks && l == 0) atomicAdd(&b.ctr[2 * NCLS + c], (uint32_t)ks);
     }
 #pragma unroll
     for (int c = 1; c < NCLS; ++c) {

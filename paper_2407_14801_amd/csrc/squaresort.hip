@@ -184,6 +184,16 @@ template <class K, bool HV> struct Engine {
         std::lock_guard<std::mutex> lk(g_timing.mu);
         g_timing.resolve();
     }
+    // corrects the units of this step's pending launch of a kernel
+    void set_units(const char *name0, uint64_t units)
+    {
+        if (!g_timing.on) return;
+        std::string nm = name0;
+        if (cur_depth > 0) nm += "@" + std::to_string(cur_depth);
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        for (auto it = g_timing.pending.rbegin(); it != g_timing.pending.rend(); ++it)
+            if (nm == it->name) { it->units = units; return; }
+    }
 
     static const char *intern(const std::string &s)
     {
@@ -285,7 +295,7 @@ template <class K, bool HV> struct Engine {
         b.list[CLS_INTERNAL] = ws.take<BucketItem>(capInt);
         b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID] = capMid;
         b.cap[CLS_BIG] = capBig; b.cap[CLS_INTERNAL] = capInt;
-        b.ctr = ws.take<uint32_t>(2 * NCLS);
+        b.ctr = ws.take<uint32_t>(CTR_WORDS);
         b.H = ws.take<unsigned long long>(N);
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         b.nodes = dDesc;
@@ -341,7 +351,7 @@ template <class K, bool HV> struct Engine {
         if (int rc = check()) return rc;
 
         // ---- buckets A -> D, by class
-        k_fill_u32<<<1, 64, 0, st>>>(b.ctr, 2 * NCLS, 0u);
+        k_fill_u32<<<1, 64, 0, st>>>(b.ctr, CTR_WORDS, 0u);
         launch("k_classify", bucS[N], [&] { k_classify<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b, cutoff); });
         launch("k_bucket_copy", keysTot, [&] { k_bucket_copy<K, HV><<<512, 256, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket_w", keysTot, [&] {
@@ -354,12 +364,17 @@ template <class K, bool HV> struct Engine {
         if (int rc = check()) return rc;
 
         // ---- internal buckets form the next batch
-        std::vector<uint32_t> hctr(NCLS);
+        std::vector<uint32_t> hctr(CTR_WORDS);
         std::vector<BucketItem> hint(capInt);
-        if (hipMemcpyAsync(hctr.data(), b.ctr, NCLS * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        if (hipMemcpyAsync(hctr.data(), b.ctr, CTR_WORDS * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipMemcpyAsync(hint.data(), b.list[CLS_INTERNAL], capInt * sizeof(BucketItem), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return SQS_ERR_DEVICE;
+        // the bucket kernels processed the keys of their own class only
+        set_units("k_bucket_copy", hctr[2 * NCLS + CLS_COPY]);
+        set_units("k_bucket_w", hctr[2 * NCLS + CLS_SMALL]);
+        set_units("k_bucket", hctr[2 * NCLS + CLS_MID]);
+        set_units("k_bucket_big", hctr[2 * NCLS + CLS_BIG]);
         resolve_timing();
         for (int c = 0; c < NCLS; ++c)
             if (hctr[c] > b.cap[c]) return SQS_ERR_DEVICE;   // cannot happen: capacities are bounds
@@ -401,13 +416,13 @@ template <class K, bool HV> struct Engine {
         Batch<K> b{};
         NodeDesc *dDesc = ws.take<NodeDesc>(1);
         BucketItem *item = ws.take<BucketItem>(1);
-        uint32_t *ctr = ws.take<uint32_t>(2 * NCLS);
+        uint32_t *ctr = ws.take<uint32_t>(CTR_WORDS);
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         host_node_ = NodeDesc{};
         host_node_.n = (uint32_t)n;
         host_node_.m = 1;
         host_item_ = BucketItem{0u, 0u, 0u, (uint32_t)n};
-        for (int c = 0; c < 2 * NCLS; ++c) host_ctr_[c] = c == CLS_BIG ? 1u : 0u;
+        for (int c = 0; c < CTR_WORDS; ++c) host_ctr_[c] = c == CLS_BIG ? 1u : 0u;
         if (hipMemcpyAsync(dDesc, &host_node_, sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
             hipMemcpyAsync(item, &host_item_, sizeof(BucketItem), hipMemcpyHostToDevice, st) != hipSuccess ||
             hipMemcpyAsync(ctr, host_ctr_, sizeof(host_ctr_), hipMemcpyHostToDevice, st) != hipSuccess)
@@ -423,7 +438,7 @@ template <class K, bool HV> struct Engine {
     }
     NodeDesc host_node_{};
     BucketItem host_item_{};
-    uint32_t host_ctr_[2 * NCLS] = {};
+    uint32_t host_ctr_[CTR_WORDS] = {};
 
     int sort_root(uint64_t n, uint64_t seed)
     {
@@ -437,7 +452,90 @@ template <class K, bool HV> struct Engine {
         std::vector<HostNode> root{{0, (uint32_t)n, splitmix(seed)}};
         return run_batch(root, 0);
     }
+
+    // Independent instances [offs[i], offs[i+1]) with seeds[i].  Each base-case
+    // instance becomes a one-bucket node (m = 1, so its key range is the whole
+    // type) on the bucket work lists; every other instance is a root node of
+    // one shared first batch.  Nodes never interact, so instance i gets
+    // exactly the result (and recursion tree) of sorting it alone.
+    int sort_many(uint32_t count, const uint64_t *offs, const uint64_t *seeds)
+    {
+        std::vector<HostNode> roots;
+        std::vector<NodeDesc> leaf;
+        std::vector<BucketItem> lists[NCLS];
+        for (uint32_t i = 0; i < count; ++i) {
+            const uint64_t n = offs[i + 1] - offs[i];
+            if (n == 0) continue;
+            if (n > cutoff) { roots.push_back({offs[i], (uint32_t)n, splitmix(seeds[i])}); continue; }
+            NodeDesc d{};
+            d.off = offs[i];
+            d.n = (uint32_t)n;
+            d.m = 1;
+            const int cls = n <= (uint64_t)WCAP ? CLS_SMALL : n <= (uint64_t)SORT_CAP ? CLS_MID : CLS_BIG;
+            lists[cls].push_back(BucketItem{(uint32_t)leaf.size(), 0u, 0u, (uint32_t)n});
+            leaf.push_back(d);
+        }
+        if (!leaf.empty()) {
+            const uint64_t mark = ws.top;
+            Batch<K> b{};
+            NodeDesc *dDesc = ws.take<NodeDesc>(leaf.size());
+            for (int c = CLS_SMALL; c <= CLS_BIG; ++c) {
+                b.list[c] = ws.take<BucketItem>(std::max<size_t>(lists[c].size(), 1));
+                b.cap[c] = (uint32_t)lists[c].size();
+            }
+            uint32_t *ctr = ws.take<uint32_t>(CTR_WORDS);
+            if (ws.overflow) return SQS_ERR_WORKSPACE;
+            uint32_t hctr[CTR_WORDS] = {};
+            for (int c = CLS_SMALL; c <= CLS_BIG; ++c) hctr[c] = (uint32_t)lists[c].size();
+            if (hipMemcpyAsync(dDesc, leaf.data(), leaf.size() * sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(ctr, hctr, sizeof hctr, hipMemcpyHostToDevice, st) != hipSuccess)
+                return SQS_ERR_DEVICE;
+            for (int c = CLS_SMALL; c <= CLS_BIG; ++c)
+                if (!lists[c].empty() &&
+                    hipMemcpyAsync(b.list[c], lists[c].data(), lists[c].size() * sizeof(BucketItem),
+                                   hipMemcpyHostToDevice, st) != hipSuccess)
+                    return SQS_ERR_DEVICE;
+            b.nodes = dDesc;
+            b.N = (uint32_t)leaf.size();
+            b.ctr = ctr;
+            uint64_t keys[NCLS] = {};
+            for (int c = CLS_SMALL; c <= CLS_BIG; ++c)
+                for (const BucketItem &e : lists[c]) keys[c] += e.size;
+            if (!lists[CLS_SMALL].empty())
+                launch("k_bucket_w", keys[CLS_SMALL], [&] {
+                    k_bucket_small<K, HV><<<std::min<uint32_t>(cdiv(b.cap[CLS_SMALL], SM_NW), 2048), SM_NW * WAVE, 0, st>>>(
+                        b, A, VA, D, VD); });
+            if (!lists[CLS_MID].empty())
+                launch("k_bucket", keys[CLS_MID], [&] {
+                    k_bucket_mid<K, HV><<<std::min<uint32_t>(b.cap[CLS_MID], 512), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
+            if (!lists[CLS_BIG].empty())
+                launch("k_bucket_big", keys[CLS_BIG], [&] {
+                    k_bucket_big<K, HV><<<std::min<uint32_t>(b.cap[CLS_BIG], 256), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
+            if (int rc = check()) return rc;
+            if (hipStreamSynchronize(st) != hipSuccess) return SQS_ERR_DEVICE;   // host lists outlive the uploads
+            resolve_timing();
+            ws.top = mark;
+        }
+        if (!roots.empty()) return run_batch(roots, 0);
+        return SQS_OK;
+    }
 };
+
+// Workspace of a batched call: the base-case lists, then (after they are
+// released) the shared first batch of the other instances and its recursion.
+uint64_t batched_workspace_bound(uint32_t count, const uint64_t *offs, uint64_t C, uint64_t key_bytes)
+{
+    uint64_t S = 0, big = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        const uint64_t n = offs[i + 1] - offs[i];
+        if (n > C) { S += n; big = std::max(big, n); }
+    }
+    const uint64_t leaves = (uint64_t)count * (sizeof(NodeDesc) + 3 * sizeof(BucketItem)) + 8 * 256;
+    if (S == 0) return leaves;
+    uint64_t chain = 1;
+    for (uint64_t s = ceil_isqrt_host(big); s > C && chain < 8; s = ceil_isqrt_host(s)) ++chain;
+    return std::max(leaves, chain * batch_bound(S, C, key_bytes) + (1 << 20));
+}
 
 constexpr uint64_t key_bytes_of(int kind) { return kind == SQS_KIND_U32 ? 4 : 8; }
 
@@ -559,6 +657,46 @@ int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket
     e.skew_bs = reinterpret_cast<unsigned long long *>(bucket_start);
     std::vector<HostNode> root{{0, (uint32_t)n, splitmix(seed)}};
     return e.run_batch(root, 0);
+}
+
+uint64_t squaresort_batched_workspace_bytes(uint32_t count, const uint64_t *offsets, int kind, uint64_t cutoff)
+{
+    if (kind != SQS_KIND_U32 || !offsets) return 0;
+    if (cutoff == 0) cutoff = max_cutoff_of(kind);
+    if (cutoff < 4) cutoff = 4;
+    for (uint32_t i = 0; i < count; ++i) if (offsets[i + 1] < offsets[i]) return 0;
+    return batched_workspace_bound(count, offsets, cutoff, 4);
+}
+
+int squaresort_batched_u32(uint32_t count, const uint64_t *offsets, uint32_t *in, uint32_t *out,
+                           const uint64_t *seeds, sqs_params *params, void *stream)
+{
+    uint32_t C;
+    if (int rc = resolve_cutoff(SQS_KIND_U32, params, &C)) return rc;
+    if (count == 0) return SQS_OK;
+    if (!offsets || !seeds || offsets[0] != 0) return SQS_ERR_ARG;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (offsets[i + 1] < offsets[i]) return SQS_ERR_ARG;
+        if (offsets[i + 1] - offsets[i] > max_n_of(SQS_KIND_U32)) return SQS_ERR_UNSUPPORTED;
+    }
+    const uint64_t total = offsets[count];
+    if (total == 0) return SQS_OK;
+    if (total > 0xFFFFFFFFull) return SQS_ERR_UNSUPPORTED;
+    if (!in || !out) return SQS_ERR_ARG;
+    if (overlap(in, total * 4, out, total * 4)) return SQS_ERR_ALIAS;
+    const uint64_t need = batched_workspace_bound(count, offsets, C, 4);
+    if (!params || !params->workspace || params->workspace_bytes < need) return SQS_ERR_WORKSPACE;
+    const bool dig = params->flags & SQS_FLAG_DIGEST;
+    if (dig && !params->digest) return SQS_ERR_ARG;
+    Engine<uint32_t, false> e;
+    e.A = in; e.VA = nullptr; e.D = out; e.VD = nullptr;
+    e.cutoff = C;
+    e.st = (hipStream_t)stream;
+    e.ws.base = static_cast<char *>(params->workspace);
+    e.ws.size = params->workspace_bytes;
+    e.digest = dig;
+    e.digest_ptr = dig ? reinterpret_cast<unsigned long long *>(params->digest) : nullptr;
+    return e.sort_many(count, offsets, seeds);
 }
 
 int sqs_timing_enable(int on)

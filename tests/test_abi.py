@@ -79,3 +79,35 @@ def test_argument_errors_before_gpu_work(b):
     # skew transpose needs n >= 2
     assert b.lib.skew_transpose_u32(1, fake_in, fake_out, None, 1, ctypes.byref(_params()), None) == -1
     assert b.lib.sqs_status_string(-3) == b"workspace missing or too small"
+
+
+def test_batched_argument_errors_before_gpu_work(b):
+    import numpy as np
+    fake_in, fake_out = 0x10000000, 0x40000000
+
+    def call(offs, seeds, inp=fake_in, out=fake_out, p=None):
+        offs = np.ascontiguousarray(offs, dtype=np.uint64)
+        seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
+        p = p or _params()
+        return b.lib.squaresort_batched_u32(offs.size - 1, offs.ctypes.data, inp, out,
+                                            seeds.ctypes.data, ctypes.byref(p), None)
+
+    # zero instances, or instances of total size 0, are no-ops
+    assert b.lib.squaresort_batched_u32(0, None, None, None, None, ctypes.byref(_params()), None) == 0
+    assert call([0, 0, 0], [1, 2], None, None) == 0
+    # offsets must start at 0 and not decrease
+    assert call([1, 5], [1]) == -1
+    assert call([0, 9, 5], [1, 2]) == -1
+    # one instance past the size limit, or a total of 2^32 keys or more
+    assert call([0, b.max_n(0) + 1], [1]) == -7
+    assert call([k << 28 for k in range(17)] + [(16 << 28) + 1], [1] * 17) == -7
+    # overlapping input and output
+    assert call([0, 100], [1], fake_in, fake_in + 64) == -2
+    # workspace missing or too small; the size query agrees
+    offs = np.array([0, 10, 200_000, 200_010], dtype=np.uint64)
+    need = b.batched_workspace_bytes(offs)
+    assert need > 0
+    assert call(offs, [1, 2, 3]) == -3
+    assert call(offs, [1, 2, 3], p=_params(ws=0x50000000, nbytes=need - 1)) == -3
+    # base cases only: a list workspace, no batch metadata
+    assert 0 < b.batched_workspace_bytes(np.array([0, 10, 20], dtype=np.uint64)) < need
