@@ -42,6 +42,8 @@ WORKLOADS = {
     # many independent instances in one call, against one call per instance
     "batched_u32": dict(kind="batched", count=4096, lo=1 << 10, hi=1 << 20, dist="uniform[0,2^32)",
                         data_seed=5),
+    # Poisson request stream served with admission and continuous batching
+    "served": dict(kind="served", lo=1 << 12, hi=1 << 24, data_seed=6, budget_gb=64),
 }
 
 
@@ -224,6 +226,89 @@ def bench_batched(args, wl):
     print(json.dumps(res), flush=True)
 
 
+def bench_served(args, wl):
+    """A Poisson stream of mixed requests (sizes log-uniform in [2^12, 2^24];
+    70% u32, 30% key/value; keys uniform or Zipf(1.1)).  The plain path's
+    capacity is measured first (each request alone, one call at a time); the
+    stream then arrives at --serve-load times that capacity and is served
+    twice at the same arrival times: plain (FIFO, one call per request) and
+    served (admission by a 64 GB budget, continuous batching per kind, the
+    two kinds overlapping on separate streams).  Every served result must
+    equal the request's result alone."""
+    import torch
+    from paper_2407_14801_amd import datagen
+    from paper_2407_14801_amd.serve import GpuExecutor, PlainExecutor, Request, Server, percentiles, replay
+    dev = torch.device("cuda:0")
+    count = args.serve_count
+    print(f"# generating {count} requests", file=sys.stderr, flush=True)
+    specs = datagen.serve_requests(count, wl["data_seed"], lo=wl["lo"], hi=wl["hi"])
+    staged = []
+    for s in specs:
+        if s["kind"] == "u32":
+            staged.append((torch.from_numpy(s["keys"].view(np.int32)).to(dev), None))
+        else:
+            staged.append((torch.from_numpy(s["keys"].view(np.int64)).to(dev),
+                           torch.from_numpy(s["vals"].view(np.int32)).to(dev)))
+    total = sum(s["n"] for s in specs)
+
+    def fresh():
+        return [Request(id=s["id"], kind=s["kind"], n=s["n"], seed=s["seed"], keys=k, vals=v)
+                for s, (k, v) in zip(specs, staged)]
+
+    # capacity of the plain path: every request alone (after one warm-up pass)
+    plain = PlainExecutor(dev, args.cutoff)
+    print("# alone (capacity)", file=sys.stderr, flush=True)
+    for r in fresh()[: min(16, count)]:
+        plain(r.kind, [r])
+    alone = fresh()
+    svc = []
+    for r in alone:
+        t0 = time.perf_counter()
+        plain(r.kind, [r])
+        svc.append(time.perf_counter() - t0)
+    cap = 1.0 / float(np.mean(svc))                       # requests per second
+    rate = args.serve_load * cap
+    g = np.random.Generator(np.random.PCG64(wl["data_seed"] + 7))
+    arrivals = np.cumsum(g.exponential(1.0 / rate, size=count))
+    arrivals -= arrivals[0]
+
+    def run(server, label):
+        reqs = fresh()
+        print(f"# {label} stream at {rate:.1f} req/s", file=sys.stderr, flush=True)
+        server.start()
+        t0 = replay(server, reqs, arrivals)
+        server.drain(count)
+        span = max(r.done for r in reqs) - t0
+        lat = [r.latency * 1e3 for r in reqs]
+        return reqs, {"keys_per_s_G": round(total / span / 1e9, 4), "span_s": round(span, 4),
+                      **{k + "_ms": round(v, 3) for k, v in percentiles(lat).items()},
+                      "mean_ms": round(float(np.mean(lat)), 3)}
+
+    _, plain_stats = run(Server(PlainExecutor(dev, args.cutoff), max_batch_keys=0, lanes=("all",),
+                                lane_of=lambda r: "all", budget_bytes=wl["budget_gb"] << 30), "plain")
+    srv = Server(GpuExecutor(dev, args.cutoff), budget_bytes=wl["budget_gb"] << 30)
+    served, served_stats = run(srv, "served")
+    same = all(torch.equal(a.out_keys, b.out_keys) and (a.out_vals is None or torch.equal(a.out_vals, b.out_vals))
+               for a, b in zip(alone, served))
+    batches = len({r.batch for r in served})
+    res = {
+        "metric": "GKeys/s", "value": served_stats["keys_per_s_G"], "unit": "GKeys/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(served_stats["span_s"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32 | u64+u32",
+        "data": "synthetic",
+        "config": {"workload": "served_poisson_mixed", "requests": count, "total_keys": total,
+                   "sizes": "log-uniform [2^12, 2^24]", "mix": "70% u32 / 30% u64+u32; uniform or Zipf(1.1) 1/2 each",
+                   "budget_gb": wl["budget_gb"], "arrival_rate_req_s": round(rate, 2),
+                   "load_vs_plain_capacity": args.serve_load, "plain_capacity_req_s": round(cap, 2)},
+        "served": {**served_stats, "batches": batches, "peak_admitted_gb": round(srv.peak_used / 2**30, 3)},
+        "plain_one_call_per_request": plain_stats,
+        "alone_service_ms": {"mean": round(float(np.mean(svc)) * 1e3, 3),
+                             **{k: round(v * 1e3, 3) for k, v in percentiles(svc).items()}},
+        "same_results_alone_and_in_mix": bool(same),
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +320,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="batched workload: pick the cut-off by timing")
     ap.add_argument("--plain-steps", type=int, default=2, help="batched workload: timed one-call-per-instance steps")
+    ap.add_argument("--serve-count", type=int, default=256, help="served workload: requests in the stream")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="served workload: arrival rate as a fraction of the plain path's capacity")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
     ap.add_argument("--calib-copy", action="store_true",
@@ -272,6 +360,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if wl["kind"] == "batched":
         return bench_batched(args, wl)
+    if wl["kind"] == "served":
+        return bench_served(args, wl)
     log2n = args.log2n or wl["log2n"]
     n = 1 << log2n
     dev = torch.device("cuda:0")

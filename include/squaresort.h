@@ -126,6 +126,14 @@ uint64_t squaresort_batched_workspace_bytes(uint32_t count, const uint64_t *offs
 int squaresort_batched_u32(uint32_t count, const uint64_t *offsets, uint32_t *in, uint32_t *out,
                            const uint64_t *seeds, sqs_params *params, void *stream);
 
+/* Batched key/value form: the same contract as squaresort_batched_u32 for
+ * (uint64 key, uint32 value) instances, each ordered by (key, original index
+ * within its instance) exactly as squaresort_kv leaves it.  kind for the
+ * workspace query: SQS_KIND_KV. */
+int squaresort_batched_kv(uint32_t count, const uint64_t *offsets, uint64_t *keys_in, uint32_t *vals_in,
+                          uint64_t *keys_out, uint32_t *vals_out, const uint64_t *seeds,
+                          sqs_params *params, void *stream);
+
 /* Measurement support (not part of the sort): while enabled, every launch is
  * bracketed by HIP events on its stream and the elapsed times are summed per
  * kernel.  sqs_timing_enable clears the table.  sqs_timing_report writes a

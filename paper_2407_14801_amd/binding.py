@@ -44,6 +44,7 @@ _SIGS = {
     "skew_transpose_u32": (_i, [_u64, _vp, _vp, _vp, _u64, _P, _vp]),
     "squaresort_batched_workspace_bytes": (_u64, [ctypes.c_uint32, _vp, _i, _u64]),
     "squaresort_batched_u32": (_i, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _P, _vp]),
+    "squaresort_batched_kv": (_i, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _P, _vp]),
     "sqs_status_string": (ctypes.c_char_p, [_i]),
     "sqs_timing_enable": (_i, [_i]),
     "sqs_timing_report": (ctypes.c_int64, [ctypes.c_char_p, _u64]),
@@ -199,6 +200,31 @@ def squaresort_batched_u32(inp: torch.Tensor, out: torch.Tensor, offsets, seeds,
     p.digest = None if digest is None else digest.data_ptr()
     _check(_lib.squaresort_batched_u32(count, offs.ctypes.data, _ptr(inp), _ptr(out), sd.ctypes.data,
                                        ctypes.byref(p), _stream(inp.device)), "squaresort_batched_u32")
+    return p.cutoff
+
+
+def squaresort_batched_kv(keys_in, vals_in, keys_out, vals_out, offsets, seeds, cutoff: int = 0,
+                          ws: Workspace | None = None, digest: torch.Tensor | None = None) -> int:
+    """Key/value batched form (uint64 keys in int64 tensors, uint32 values in
+    int32 tensors).  Returns the cut-off used."""
+    import numpy as np
+    _check_dev(keys_in, vals_in, keys_out, vals_out)
+    assert keys_in.dtype == torch.int64 and vals_in.dtype == torch.int32
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+    count = offs.size - 1
+    assert sd.size == count and int(offs[-1]) == keys_in.numel()
+    nbytes = batched_workspace_bytes(offs, KIND_KV, cutoff)
+    buf = (ws or Workspace(keys_in.device)).get(nbytes)
+    p = Params()
+    p.cutoff = cutoff
+    p.flags = FLAG_DIGEST if digest is not None else 0
+    p.workspace = buf.data_ptr()
+    p.workspace_bytes = buf.numel()
+    p.digest = None if digest is None else digest.data_ptr()
+    _check(_lib.squaresort_batched_kv(count, offs.ctypes.data, _ptr(keys_in), _ptr(vals_in), _ptr(keys_out),
+                                      _ptr(vals_out), sd.ctypes.data, ctypes.byref(p), _stream(keys_in.device)),
+           "squaresort_batched_kv")
     return p.cutoff
 
 

@@ -661,35 +661,44 @@ int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket
 
 uint64_t squaresort_batched_workspace_bytes(uint32_t count, const uint64_t *offsets, int kind, uint64_t cutoff)
 {
-    if (kind != SQS_KIND_U32 || !offsets) return 0;
+    if ((kind != SQS_KIND_U32 && kind != SQS_KIND_KV) || !offsets) return 0;
     if (cutoff == 0) cutoff = max_cutoff_of(kind);
     if (cutoff < 4) cutoff = 4;
     for (uint32_t i = 0; i < count; ++i) if (offsets[i + 1] < offsets[i]) return 0;
-    return batched_workspace_bound(count, offsets, cutoff, 4);
+    return batched_workspace_bound(count, offsets, cutoff, key_bytes_of(kind) + (kind == SQS_KIND_KV ? 4 : 0));
 }
 
-int squaresort_batched_u32(uint32_t count, const uint64_t *offsets, uint32_t *in, uint32_t *out,
-                           const uint64_t *seeds, sqs_params *params, void *stream)
+}  // extern "C"
+
+namespace sqs {
+namespace {
+template <class K, bool HV>
+int run_batched(uint32_t count, const uint64_t *offsets, K *in, uint32_t *vin, K *out, uint32_t *vout,
+                const uint64_t *seeds, sqs_params *params, void *stream, int kind)
 {
     uint32_t C;
-    if (int rc = resolve_cutoff(SQS_KIND_U32, params, &C)) return rc;
+    if (int rc = resolve_cutoff(kind, params, &C)) return rc;
     if (count == 0) return SQS_OK;
     if (!offsets || !seeds || offsets[0] != 0) return SQS_ERR_ARG;
     for (uint32_t i = 0; i < count; ++i) {
         if (offsets[i + 1] < offsets[i]) return SQS_ERR_ARG;
-        if (offsets[i + 1] - offsets[i] > max_n_of(SQS_KIND_U32)) return SQS_ERR_UNSUPPORTED;
+        if (offsets[i + 1] - offsets[i] > max_n_of(kind)) return SQS_ERR_UNSUPPORTED;
     }
     const uint64_t total = offsets[count];
     if (total == 0) return SQS_OK;
     if (total > 0xFFFFFFFFull) return SQS_ERR_UNSUPPORTED;
-    if (!in || !out) return SQS_ERR_ARG;
-    if (overlap(in, total * 4, out, total * 4)) return SQS_ERR_ALIAS;
-    const uint64_t need = batched_workspace_bound(count, offsets, C, 4);
+    if (!in || !out || (HV && (!vin || !vout))) return SQS_ERR_ARG;
+    const uint64_t kb = total * sizeof(K), vb = total * 4;
+    if (overlap(in, kb, out, kb)) return SQS_ERR_ALIAS;
+    if (HV && (overlap(vin, vb, vout, vb) || overlap(vin, vb, in, kb) || overlap(vin, vb, out, kb) ||
+               overlap(vout, vb, in, kb) || overlap(vout, vb, out, kb)))
+        return SQS_ERR_ALIAS;
+    const uint64_t need = batched_workspace_bound(count, offsets, C, sizeof(K) + (HV ? 4 : 0));
     if (!params || !params->workspace || params->workspace_bytes < need) return SQS_ERR_WORKSPACE;
     const bool dig = params->flags & SQS_FLAG_DIGEST;
     if (dig && !params->digest) return SQS_ERR_ARG;
-    Engine<uint32_t, false> e;
-    e.A = in; e.VA = nullptr; e.D = out; e.VD = nullptr;
+    Engine<K, HV> e;
+    e.A = in; e.VA = vin; e.D = out; e.VD = vout;
     e.cutoff = C;
     e.st = (hipStream_t)stream;
     e.ws.base = static_cast<char *>(params->workspace);
@@ -697,6 +706,25 @@ int squaresort_batched_u32(uint32_t count, const uint64_t *offsets, uint32_t *in
     e.digest = dig;
     e.digest_ptr = dig ? reinterpret_cast<unsigned long long *>(params->digest) : nullptr;
     return e.sort_many(count, offsets, seeds);
+}
+}  // namespace
+}  // namespace sqs
+
+extern "C" {
+
+int squaresort_batched_u32(uint32_t count, const uint64_t *offsets, uint32_t *in, uint32_t *out,
+                           const uint64_t *seeds, sqs_params *params, void *stream)
+{
+    return run_batched<uint32_t, false>(count, offsets, in, nullptr, out, nullptr, seeds, params, stream,
+                                        SQS_KIND_U32);
+}
+
+int squaresort_batched_kv(uint32_t count, const uint64_t *offsets, uint64_t *keys_in, uint32_t *vals_in,
+                          uint64_t *keys_out, uint32_t *vals_out, const uint64_t *seeds, sqs_params *params,
+                          void *stream)
+{
+    return run_batched<uint64_t, true>(count, offsets, keys_in, vals_in, keys_out, vals_out, seeds, params,
+                                       stream, SQS_KIND_KV);
 }
 
 int sqs_timing_enable(int on)

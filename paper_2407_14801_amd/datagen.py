@@ -87,3 +87,37 @@ def log_uniform_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
     g = _rng(seed)
     e = g.uniform(math.log(lo), math.log(hi), size=count)
     return np.clip(np.exp(e).astype(np.int64), lo, hi)
+
+
+def zipf_keys(n: int, seed: int, bits: int = 32, num_values: int = 1 << 20, s: float = 1.1) -> np.ndarray:
+    """n keys drawn Zipf(s) over num_values distinct random values of `bits`
+    bits (rank r with probability proportional to r^-s)."""
+    g = _rng(seed)
+    distinct = g.integers(0, 1 << bits, size=num_values, dtype=np.uint64)
+    ranks = np.minimum(np.searchsorted(zipf_table(num_values, s), g.random(n), side="right"), num_values - 1)
+    keys = distinct[ranks]
+    return keys.astype(np.uint32) if bits == 32 else keys
+
+
+def serve_requests(count: int, seed: int, lo: int = 1 << 12, hi: int = 1 << 24):
+    """Request mix of the served form: sizes log-uniform in [lo, hi]; 70%
+    uint32 keys, 30% (uint64 key, uint32 value = index) pairs; keys uniform or
+    Zipf(1.1) over 2^20 values with probability 1/2 each.  Returns a list of
+    dicts (kind, n, dist, data_seed, seed) and the keys/values of each."""
+    g = _rng(seed)
+    sizes = log_uniform_sizes(count, lo, hi, seed + 1)
+    kinds = np.where(g.random(count) < 0.7, "u32", "kv")
+    dists = np.where(g.random(count) < 0.5, "uniform", "zipf")
+    reqs = []
+    for i in range(count):
+        n, kind, dist = int(sizes[i]), str(kinds[i]), str(dists[i])
+        ds = seed * 100_003 + i
+        if kind == "u32":
+            keys = uniform_u32(n, ds) if dist == "uniform" else zipf_keys(n, ds, 32)
+            vals = None
+        else:
+            keys = uniform_u64(n, ds) if dist == "uniform" else zipf_keys(n, ds, 64)
+            vals = np.arange(n, dtype=np.uint32)
+        reqs.append({"id": i, "kind": kind, "n": n, "dist": dist, "data_seed": ds, "seed": i + 1,
+                     "keys": keys, "vals": vals})
+    return reqs

@@ -1,0 +1,49 @@
+"""Served form on the GPU: every request's result is the same alone and in
+the mix (same seed, so bit-identical), and it is the sort of its input."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2407_14801_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def _requests(count, seed):
+    from paper_2407_14801_amd.serve import Request
+    specs = datagen.serve_requests(count, seed, lo=1 << 6, hi=1 << 18)
+    reqs = []
+    for s in specs:
+        if s["kind"] == "u32":
+            k = torch.from_numpy(s["keys"].view(np.int32)).to(DEV)
+            v = None
+        else:
+            k = torch.from_numpy(s["keys"].view(np.int64)).to(DEV)
+            v = torch.from_numpy(s["vals"].view(np.int32)).to(DEV)
+        reqs.append(Request(id=s["id"], kind=s["kind"], n=s["n"], seed=s["seed"], keys=k, vals=v))
+    return specs, reqs
+
+
+def test_served_results_identical_alone_and_in_the_mix():
+    assert torch.cuda.is_available()
+    from paper_2407_14801_amd.serve import GpuExecutor, PlainExecutor, Request, Server, replay
+    print("served: 48 mixed requests", flush=True)
+    specs, reqs = _requests(48, seed=21)
+    srv = Server(GpuExecutor(DEV)).start()
+    replay(srv, reqs, [0.0005 * i for i in range(len(reqs))])      # arrive while others run
+    srv.drain(len(reqs))
+    assert len({r.batch for r in reqs}) < len(reqs)                # some requests shared a batch
+    alone = PlainExecutor(DEV)
+    for s, r in zip(specs, reqs):
+        a = Request(id=r.id, kind=r.kind, n=r.n, seed=r.seed, keys=r.keys, vals=r.vals)
+        alone(a.kind, [a])
+        assert torch.equal(a.out_keys, r.out_keys), f"request {r.id}"
+        if r.kind == "u32":
+            assert np.array_equal(r.out_keys.cpu().numpy().view(np.uint32), np.sort(s["keys"]))
+        else:
+            assert torch.equal(a.out_vals, r.out_vals), f"request {r.id}"
+            order = np.argsort(s["keys"], kind="stable")
+            assert np.array_equal(r.out_keys.cpu().numpy().view(np.uint64), s["keys"][order])
+            assert np.array_equal(r.out_vals.cpu().numpy().view(np.uint32), s["vals"][order])
