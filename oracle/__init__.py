@@ -37,6 +37,10 @@ def _load():
         "orc_root_key": (u64, [u64]),
         "orc_child_key": (u64, [u64, u32, u64]),
         "orc_draw_pos": (u64, [u64, u64, u64]),
+        "orc_draw_pos_alg1": (u64, [u64, u64, u64, u64]),
+        "orc_squaresort_rule": (ctypes.c_int, [u64, vp, vp, vp, vp, u64, u64, u64, ctypes.c_int, vp, vp]),
+        "orc_root_pivots_alg1": (ctypes.c_int, [u64, vp, u64, vp, vp, vp]),
+        "orc_tree_stats_rule": (ctypes.c_int, [u64, vp, u64, u64, ctypes.c_int, u64, vp, vp, vp]),
         "orc_ceil_isqrt": (u64, [u64]),
         "orc_squaresort": (ctypes.c_int, [u64, vp, vp, vp, vp, u64, u64, vp, vp]),
         "orc_squaresort_u32": (ctypes.c_int, [u64, vp, vp, u64, u64, vp, vp]),
@@ -88,8 +92,32 @@ def ceil_isqrt(n: int) -> int:
     return _load().orc_ceil_isqrt(n)
 
 
+def draw_pos_alg1(K: int, a: int, t: int, n: int) -> int:
+    return _load().orc_draw_pos_alg1(K, a, t, n)
+
+
+RULES = {"replacement": 0, "alg1": 1}
+ALG1_ATTEMPTS = 64
+
+
+def _sort_rule(keys, vals, seed, cutoff, key_max, rule):
+    k = np.array(keys, dtype=np.uint64)
+    v = None if vals is None else np.array(vals, dtype=np.uint32)
+    ko = np.empty_like(k)
+    vo = None if v is None else np.empty_like(v)
+    dg, nd = u64(0), u64(0)
+    rc = _load().orc_squaresort_rule(k.size, _p(k), _p(v), _p(ko), _p(vo), seed, cutoff, key_max,
+                                     RULES[rule], ctypes.addressof(dg), ctypes.addressof(nd))
+    _check(rc, f"squaresort ({rule} pivots)")
+    return ko, vo, dg.value, nd.value
+
+
 # ---- sorts --------------------------------------------------------------
-def squaresort_u32(x: np.ndarray, seed: int, cutoff: int, want_digest=False):
+def squaresort_u32(x: np.ndarray, seed: int, cutoff: int, want_digest=False, rule="replacement"):
+    if rule != "replacement":
+        ko, _, dg, nd = _sort_rule(np.asarray(x, dtype=np.uint32), None, seed, cutoff, 2**32 - 1, rule)
+        out = ko.astype(np.uint32)
+        return (out, dg, nd) if want_digest else out
     x = np.ascontiguousarray(x, dtype=np.uint32)
     out = np.empty_like(x)
     dg, nd = u64(0), u64(0)
@@ -99,7 +127,10 @@ def squaresort_u32(x: np.ndarray, seed: int, cutoff: int, want_digest=False):
     return (out, dg.value, nd.value) if want_digest else out
 
 
-def squaresort_u64(x: np.ndarray, seed: int, cutoff: int, want_digest=False):
+def squaresort_u64(x: np.ndarray, seed: int, cutoff: int, want_digest=False, rule="replacement"):
+    if rule != "replacement":
+        ko, _, dg, nd = _sort_rule(x, None, seed, cutoff, 2**64 - 1, rule)
+        return (ko, dg, nd) if want_digest else ko
     x = np.ascontiguousarray(x, dtype=np.uint64)
     out = np.empty_like(x)
     dg, nd = u64(0), u64(0)
@@ -110,7 +141,10 @@ def squaresort_u64(x: np.ndarray, seed: int, cutoff: int, want_digest=False):
 
 
 def squaresort_kv(keys: np.ndarray, vals: np.ndarray, seed: int, cutoff: int,
-                  want_digest=False):
+                  want_digest=False, rule="replacement"):
+    if rule != "replacement":
+        ko, vo, dg, nd = _sort_rule(keys, vals, seed, cutoff, 2**64 - 1, rule)
+        return (ko, vo, dg, nd) if want_digest else (ko, vo)
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
     vals = np.ascontiguousarray(vals, dtype=np.uint32)
     ko, vo = np.empty_like(keys), np.empty_like(vals)
@@ -136,6 +170,18 @@ def root_pivots(keys: np.ndarray, seed: int):
     strict = np.empty(m - 1, np.uint8)
     _check(_load().orc_root_pivots(keys.size, _p(keys), seed, _p(piv), _p(strict)), "root_pivots")
     return piv, strict
+
+
+def root_pivots_alg1(keys: np.ndarray, seed: int):
+    """Root pivots under the Alg. 1 rule: (pivots, strict flags, attempts)."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    m = ceil_isqrt(keys.size)
+    piv = np.empty(m - 1, np.uint64)
+    strict = np.empty(m - 1, np.uint8)
+    att = u64(0)
+    _check(_load().orc_root_pivots_alg1(keys.size, _p(keys), seed, _p(piv), _p(strict), ctypes.addressof(att)),
+           "root_pivots_alg1")
+    return piv, strict, att.value
 
 
 def bucket_of(x: int, piv: np.ndarray, strict: np.ndarray) -> int:
@@ -175,13 +221,13 @@ def root_intermediate(keys, seed, vals=None):
     return (ko, bs) if v is None else (ko, vo, bs)
 
 
-def tree_stats(keys, seed, cutoff, max_depth=16):
+def tree_stats(keys, seed, cutoff, max_depth=16, rule="replacement"):
     k = np.ascontiguousarray(keys, dtype=np.uint64)
     cnt = np.zeros(max_depth, np.uint64)
     ssum = np.zeros(max_depth, np.uint64)
     depth = u64(0)
-    _check(_load().orc_tree_stats(k.size, _p(k), seed, cutoff, max_depth, _p(cnt), _p(ssum),
-                                  ctypes.addressof(depth)), "tree_stats")
+    _check(_load().orc_tree_stats_rule(k.size, _p(k), seed, cutoff, RULES[rule], max_depth, _p(cnt),
+                                       _p(ssum), ctypes.addressof(depth)), "tree_stats")
     return cnt, ssum, depth.value
 
 

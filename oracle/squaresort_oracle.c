@@ -40,6 +40,16 @@ uint64_t orc_draw_pos(uint64_t K, uint64_t t, uint64_t n)
     return (uint64_t)(((unsigned __int128)u * n) >> 64);
 }
 
+/* Draw t of attempt a under the Alg. 1 pivot rule: its own counter range
+ * (bits 63 and 62 set, attempt in bits 32..61), so attempts never reuse a
+ * draw of the other rule or of another attempt. */
+uint64_t orc_draw_pos_alg1(uint64_t K, uint64_t a, uint64_t t, uint64_t n)
+{
+    uint64_t c = (3ull << 62) | ((a & 0x3FFFFFFFull) << 32) | (t & 0xFFFFFFFFull);
+    uint64_t u = orc_sm64(K ^ orc_sm64(c));
+    return (uint64_t)(((unsigned __int128)u * n) >> 64);
+}
+
 /* m = ceil(sqrt(n)) exactly (Alg. 1, "m = ceil(sqrt n)").  Bit-by-bit
  * integer square root: no floating point decides m. */
 uint64_t orc_ceil_isqrt(uint64_t n)
@@ -222,12 +232,54 @@ static int choose_pivots(uint64_t K, uint64_t n, uint64_t m, const uint64_t *a_k
     return 0;
 }
 
+/* The pivot rule of Alg. 1: m-1 pivots, pairwise distinct and none equal
+ * to the node's minimum; a sample that breaks either condition is thrown
+ * away whole and drawn again.  Buckets are [p_{j-1}, p_j): with every
+ * pivot marked strict the bucket rule above counts the pivots <= x, which
+ * is exactly that half-open rule (keys equal to a pivot go right).  Inputs
+ * with too few distinct keys never yield such a sample; after
+ * ORC_ALG1_ATTEMPTS draws the oracle gives up with -4.                    */
+static int choose_pivots_alg1(uint64_t K, uint64_t n, uint64_t m, const uint64_t *a_keys,
+                              uint64_t *piv, uint8_t *strict, uint64_t *attempts)
+{
+    uint64_t lo = a_keys[0];
+    for (uint64_t r = 1; r < n; ++r) if (a_keys[r] < lo) lo = a_keys[r];
+    for (uint64_t a = 0; a < ORC_ALG1_ATTEMPTS; ++a) {
+        for (uint64_t t = 0; t + 1 < m; ++t) piv[t] = a_keys[orc_draw_pos_alg1(K, a, t, n)];
+        int rc = orc_stable_sort(m - 1, piv, NULL);
+        if (rc) return rc;
+        int ok = m < 2 || piv[0] != lo;
+        for (uint64_t t = 0; ok && t + 2 < m; ++t) ok = piv[t] != piv[t + 1];
+        if (ok) {
+            for (uint64_t t = 0; t + 1 < m; ++t) strict[t] = 1;
+            if (attempts) *attempts = a + 1;
+            return 0;
+        }
+    }
+    return -4;
+}
+
+static int choose_pivots_rule(int rule, uint64_t K, uint64_t n, uint64_t m, const uint64_t *a_keys,
+                              uint64_t *piv, uint8_t *strict)
+{
+    if (rule == ORC_RULE_ALG1) return choose_pivots_alg1(K, n, m, a_keys, piv, strict, NULL);
+    return choose_pivots(K, n, m, a_keys, piv, strict);
+}
+
 int orc_root_pivots(uint64_t n, const uint64_t *keys_in, uint64_t seed,
                     uint64_t *pivots, uint8_t *strict)
 {
     if (n < 2 || !keys_in || !pivots || !strict) return -1;
     uint64_t m = orc_ceil_isqrt(n);
     return choose_pivots(orc_root_key(seed), n, m, keys_in, pivots, strict);
+}
+
+int orc_root_pivots_alg1(uint64_t n, const uint64_t *keys_in, uint64_t seed,
+                         uint64_t *pivots, uint8_t *strict, uint64_t *attempts)
+{
+    if (n < 2 || !keys_in || !pivots || !strict) return -1;
+    uint64_t m = orc_ceil_isqrt(n);
+    return choose_pivots_alg1(orc_root_key(seed), n, m, keys_in, pivots, strict, attempts);
 }
 
 /* A non-empty bucket j admits exactly one key value.  Inclusive bounds:
@@ -272,6 +324,7 @@ typedef struct {
     /* tree statistics (optional) */
     uint64_t max_depth, *node_count, *size_sum, depth_reached;
     int err;
+    int rule;          /* ORC_RULE_REPLACEMENT or ORC_RULE_ALG1 */
 } sqs_ctx;
 
 static uint64_t elem_hash_x(uint64_t key, const uint32_t *vals, uint64_t r)
@@ -303,7 +356,7 @@ static void squaresort_rec(sqs_ctx *g, uint64_t K, uint64_t n,
     if (!piv || !strict || !bs) { g->err = -2; goto out; }
 
     /* pivots come from the node input before the column children clobber it */
-    int rc = choose_pivots(K, n, m, ak, piv, strict);
+    int rc = choose_pivots_rule(g->rule, K, n, m, ak, piv, strict);
     if (rc) { g->err = rc; goto out; }
 
     /* sort each column of A into the same position of D */
@@ -344,13 +397,26 @@ out:
     free(piv); free(strict); free(bs);
 }
 
+static int run_squaresort_rule(uint64_t n, uint64_t *ak, uint32_t *av, uint64_t *dk, uint32_t *dv,
+                               uint64_t seed, uint64_t cutoff, uint64_t key_max, int rule,
+                               uint64_t *digest, uint64_t *nodes)
+{
+    if (cutoff < 4 || (rule != ORC_RULE_REPLACEMENT && rule != ORC_RULE_ALG1)) return -1;
+    if (n > 0 && (!ak || !dk)) return -1;
+    sqs_ctx g = { cutoff, key_max, 0, 0, 0, NULL, NULL, 0, 0, rule };
+    squaresort_rec(&g, orc_root_key(seed), n, ak, av, dk, dv, 0);
+    if (digest) *digest = g.digest;
+    if (nodes) *nodes = g.nodes;
+    return g.err;
+}
+
 static int run_squaresort(uint64_t n, uint64_t *ak, uint32_t *av, uint64_t *dk, uint32_t *dv,
                           uint64_t seed, uint64_t cutoff, uint64_t key_max,
                           uint64_t *digest, uint64_t *nodes)
 {
     if (cutoff < 4) return -1;
     if (n > 0 && (!ak || !dk)) return -1;
-    sqs_ctx g = { cutoff, key_max, 0, 0, 0, NULL, NULL, 0, 0 };
+    sqs_ctx g = { cutoff, key_max, 0, 0, 0, NULL, NULL, 0, 0, ORC_RULE_REPLACEMENT };
     squaresort_rec(&g, orc_root_key(seed), n, ak, av, dk, dv, 0);
     if (digest) *digest = g.digest;
     if (nodes) *nodes = g.nodes;
@@ -364,6 +430,15 @@ int orc_squaresort(uint64_t n, uint64_t *keys_a, uint32_t *vals_a,
     if ((vals_a == NULL) != (vals_d == NULL)) return -1;
     return run_squaresort(n, keys_a, vals_a, keys_d, vals_d, seed, cutoff, UINT64_MAX,
                           digest, nodes);
+}
+
+int orc_squaresort_rule(uint64_t n, uint64_t *keys_a, uint32_t *vals_a,
+                        uint64_t *keys_d, uint32_t *vals_d, uint64_t seed, uint64_t cutoff,
+                        uint64_t key_max, int rule, uint64_t *digest, uint64_t *nodes)
+{
+    if ((vals_a == NULL) != (vals_d == NULL)) return -1;
+    return run_squaresort_rule(n, keys_a, vals_a, keys_d, vals_d, seed, cutoff, key_max, rule,
+                               digest, nodes);
 }
 
 int orc_squaresort_u32(uint64_t n, const uint32_t *in, uint32_t *out,
@@ -439,21 +514,30 @@ out:
     return rc;
 }
 
-int orc_tree_stats(uint64_t n, const uint64_t *keys_in, uint64_t seed, uint64_t cutoff,
-                   uint64_t max_depth, uint64_t *node_count, uint64_t *size_sum,
-                   uint64_t *depth)
+int orc_tree_stats_rule(uint64_t n, const uint64_t *keys_in, uint64_t seed, uint64_t cutoff,
+                        int rule, uint64_t max_depth, uint64_t *node_count, uint64_t *size_sum,
+                        uint64_t *depth)
 {
     if (cutoff < 4 || (n > 0 && !keys_in) || !node_count || !size_sum) return -1;
+    if (rule != ORC_RULE_REPLACEMENT && rule != ORC_RULE_ALG1) return -1;
     uint64_t *a = malloc((n ? n : 1) * sizeof *a), *d = malloc((n ? n : 1) * sizeof *d);
     if (!a || !d) { free(a); free(d); return -2; }
     if (n) memcpy(a, keys_in, n * sizeof *a);
     memset(node_count, 0, max_depth * sizeof *node_count);
     memset(size_sum, 0, max_depth * sizeof *size_sum);
-    sqs_ctx g = { cutoff, UINT64_MAX, 0, 0, max_depth, node_count, size_sum, 0, 0 };
+    sqs_ctx g = { cutoff, UINT64_MAX, 0, 0, max_depth, node_count, size_sum, 0, 0, rule };
     squaresort_rec(&g, orc_root_key(seed), n, a, NULL, d, NULL, 0);
     if (depth) *depth = g.depth_reached;
     free(a); free(d);
     return g.err;
+}
+
+int orc_tree_stats(uint64_t n, const uint64_t *keys_in, uint64_t seed, uint64_t cutoff,
+                   uint64_t max_depth, uint64_t *node_count, uint64_t *size_sum,
+                   uint64_t *depth)
+{
+    return orc_tree_stats_rule(n, keys_in, seed, cutoff, ORC_RULE_REPLACEMENT, max_depth,
+                               node_count, size_sum, depth);
 }
 
 /* ------------------------------------------------------------------ */

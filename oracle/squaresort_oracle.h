@@ -31,8 +31,14 @@
  *     recursed into (Section 2.1, last paragraph).
  *   - base case: n <= C (cut-off C >= 4) sorts directly (Alg. 1 first step).
  *
+ * A second pivot rule follows Alg. 1 literally (for inputs of distinct
+ * keys): m-1 pivots that are pairwise distinct and differ from the node's
+ * minimum, a failing sample redrawn whole, buckets [p_{j-1}, p_j).  Its
+ * draws use their own counter range (orc_draw_pos_alg1).
+ *
  * Status codes: 0 ok, -1 bad argument (C < 4, null pointer with n > 0),
- * -2 out of memory.
+ * -2 out of memory, -4 the Alg. 1 rule found no valid sample in
+ * ORC_ALG1_ATTEMPTS draws (the input lacks distinct keys).
  */
 #ifndef SQUARESORT_ORACLE_H
 #define SQUARESORT_ORACLE_H
@@ -48,6 +54,11 @@ uint64_t orc_sm64(uint64_t state);                 /* first SplitMix64 output fr
 uint64_t orc_root_key(uint64_t seed);              /* sm64(seed)                           */
 uint64_t orc_child_key(uint64_t K, uint32_t phase, uint64_t i); /* phase 0 column, 1 bucket */
 uint64_t orc_draw_pos(uint64_t K, uint64_t t, uint64_t n);      /* floor(draw * n / 2^64)   */
+/* draw t of attempt a under the Alg. 1 rule: counter 3*2^62 | a*2^32 | t   */
+uint64_t orc_draw_pos_alg1(uint64_t K, uint64_t a, uint64_t t, uint64_t n);
+
+enum { ORC_RULE_REPLACEMENT = 0, ORC_RULE_ALG1 = 1 };
+#define ORC_ALG1_ATTEMPTS 64
 uint64_t orc_ceil_isqrt(uint64_t n);
 
 /* ---- full SquareSort (Alg. 1).  A is clobbered; D receives the sorted
@@ -70,9 +81,19 @@ int orc_squaresort_kv(uint64_t n, const uint64_t *keys_in, const uint32_t *vals_
                       uint64_t *keys_out, uint32_t *vals_out,
                       uint64_t seed, uint64_t cutoff, uint64_t *digest, uint64_t *nodes);
 
+/* SquareSort under either pivot rule; key_max is the largest key of the key
+ * type (UINT32_MAX or UINT64_MAX), used by the single-value bucket test. */
+int orc_squaresort_rule(uint64_t n, uint64_t *keys_a, uint32_t *vals_a,
+                        uint64_t *keys_d, uint32_t *vals_d, uint64_t seed, uint64_t cutoff,
+                        uint64_t key_max, int rule, uint64_t *digest, uint64_t *nodes);
+
 /* ---- the root node's pivots: m-1 sorted samples and strict flags ---- */
 int orc_root_pivots(uint64_t n, const uint64_t *keys_in, uint64_t seed,
                     uint64_t *pivots /* m-1 */, uint8_t *strict /* m-1 */);
+/* the same under the Alg. 1 rule; attempts (nullable) receives the number
+ * of samples drawn (1 = the first was valid) */
+int orc_root_pivots_alg1(uint64_t n, const uint64_t *keys_in, uint64_t seed,
+                         uint64_t *pivots, uint8_t *strict, uint64_t *attempts);
 
 /* bucket index of key x against sorted pivots s[0..npiv) with strict flags */
 uint64_t orc_bucket_of(uint64_t x, const uint64_t *s, const uint8_t *strict, uint64_t npiv);
@@ -113,6 +134,9 @@ int orc_root_buckets(uint64_t n, const uint64_t *keys_in, uint64_t seed,
 int orc_tree_stats(uint64_t n, const uint64_t *keys_in, uint64_t seed, uint64_t cutoff,
                    uint64_t max_depth, uint64_t *node_count, uint64_t *size_sum,
                    uint64_t *depth);
+int orc_tree_stats_rule(uint64_t n, const uint64_t *keys_in, uint64_t seed, uint64_t cutoff,
+                        int rule, uint64_t max_depth, uint64_t *node_count, uint64_t *size_sum,
+                        uint64_t *depth);
 
 /* ---- a plain stable merge sort by key (the base case "simple_sort") ---- */
 int orc_stable_sort(uint64_t n, uint64_t *keys, uint32_t *vals);

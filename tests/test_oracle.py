@@ -308,3 +308,100 @@ def test_root_buckets_match_full_intermediate(orc):
     assert np.array_equal(bounds[:, 1], bs[sel.astype(np.int64) + 1])
     want = np.concatenate([full[int(bs[j]):int(bs[j + 1])] for j in sel])
     assert np.array_equal(keys, want)
+
+
+# --------------------------------------------- the Alg. 1 pivot rule (a mode)
+def test_alg1_every_permutation_small(orc):
+    """Brute force: every permutation of 0..n-1, n <= 8, at cut-off 4."""
+    for n in range(5, 9):
+        for p in itertools.permutations(range(n)):
+            x = np.array(p, dtype=np.uint32)
+            assert np.array_equal(orc.squaresort_u32(x, 1, 4, rule="alg1"), np.arange(n, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("n,cutoff", [(26, 4), (100, 4), (1000, 16), (4096, 64), (4097, 64), (65535, 64),
+                                      (200_003, 1000)])
+def test_alg1_distinct_keys_match_numpy(orc, n, cutoff):
+    x = (np.random.default_rng(n).permutation(n) * 7 + 3).astype(np.uint32)
+    assert np.array_equal(orc.squaresort_u32(x, 5, cutoff, rule="alg1"), np.sort(x))
+    y = datagen.uniform_u64(n, seed=n)            # 64-bit random keys: distinct with overwhelming probability
+    assert np.unique(y).size == n
+    assert np.array_equal(orc.squaresort_u64(y, 6, cutoff, rule="alg1"), np.sort(y))
+    ko, vo = orc.squaresort_kv(y, np.arange(n, dtype=np.uint32), 7, cutoff, rule="alg1")
+    order = np.argsort(y, kind="stable")
+    assert np.array_equal(ko, y[order]) and np.array_equal(vo, order.astype(np.uint32))
+
+
+def test_alg1_pivots_are_distinct_keys_above_the_minimum(orc):
+    x = (np.random.default_rng(3).permutation(40_000) + 11).astype(np.uint64)
+    piv, strict, attempts = orc.root_pivots_alg1(x, seed=9)
+    assert piv.size == orc.ceil_isqrt(x.size) - 1 and attempts >= 1
+    assert np.all(np.diff(piv.astype(np.int64)) > 0)          # sorted, pairwise distinct
+    assert piv[0] > x.min() and np.all(np.isin(piv, x))
+    assert np.all(strict == 1)
+    # bucket rule [p_{j-1}, p_j): bucket(x) = number of pivots <= x
+    probe = np.concatenate([x[:500], piv, piv - 1, piv + 1, [x.min(), x.max()]])
+    for v in probe.tolist():
+        assert orc.bucket_of(v, piv, strict) == int(np.searchsorted(piv, v, side="right"))
+
+
+def test_alg1_resamples_the_whole_set(orc):
+    """A sample with a repeated position or the minimum is redrawn whole: the
+    chosen pivots are the first attempt (in draw order) whose sorted draws
+    are distinct and above the minimum, and every earlier attempt failed."""
+    n = 50                                   # m - 1 = 7 draws of 50: repeats are common
+    x = (np.random.default_rng(1).permutation(n) + 100).astype(np.uint64)
+    seen_retry = 0
+    for seed in range(1, 60):
+        K = orc.root_key(seed)
+        piv, _, attempts = orc.root_pivots_alg1(x, seed)
+        for a in range(attempts):
+            draws = np.sort(x[[orc.draw_pos_alg1(K, a, t, n) for t in range(7)]])
+            valid = np.unique(draws).size == 7 and draws[0] != x.min()
+            assert valid == (a == attempts - 1), (seed, a)
+        assert np.array_equal(piv, draws)
+        seen_retry += attempts > 1
+    assert seen_retry >= 5
+
+
+def test_alg1_rejects_inputs_without_distinct_samples(orc):
+    with pytest.raises(RuntimeError):
+        orc.squaresort_u32(np.full(1000, 5, np.uint32), 1, 4, rule="alg1")
+    with pytest.raises(RuntimeError):
+        orc.squaresort_u32(np.arange(1000, dtype=np.uint32) % 3, 1, 4, rule="alg1")
+
+
+def _root_bucket_sizes_alg1(orc, n, seed):
+    x = (np.random.default_rng(seed).permutation(n) + 1).astype(np.uint64)
+    piv, _, _ = orc.root_pivots_alg1(x, seed)
+    # [p_{j-1}, p_j) buckets from the closed form
+    return np.bincount(np.searchsorted(piv, x, side="right"), minlength=piv.size + 1)
+
+
+def test_alg1_bucket_size_tails(orc):
+    """The Section 3.2 bounds are proved for this rule (distinct pivots other
+    than the minimum): upper tail Pr[n_i >= t sqrt n] <= e^{-0.9t+0.1}, lower
+    tail Pr[n_1 <= s] <= e^2 s / sqrt n, E[sum n_i log n_i] <= n log n / 2 +
+    4 e n; every bucket is non-empty (each pivot opens its bucket)."""
+    n = 10000
+    sizes = [_root_bucket_sizes_alg1(orc, n, s) for s in range(1, 81)]
+    allsz = np.concatenate(sizes)
+    assert allsz.min() >= 1
+    for t in (1, 2, 3, 4):
+        freq = float(np.mean(allsz >= t * math.sqrt(n)))
+        assert freq <= math.exp(-0.9 * t + 0.1) + 0.01, (t, freq)
+    first = np.array([s[0] for s in sizes])
+    for s in (2, 10, 30):
+        assert float(np.mean(first <= s)) <= math.e ** 2 * s / math.sqrt(n) + 0.05
+    ent = [float(np.sum(s * np.log2(s))) for s in sizes]
+    assert np.mean(ent) <= 0.5 * n * math.log2(n) + 4 * math.e * n
+
+
+def test_alg1_tree_shape(orc):
+    n = 1 << 16
+    x = (np.random.default_rng(5).permutation(n)).astype(np.uint64)
+    cnt, ssum, depth = orc.tree_stats(x, seed=1, cutoff=16, rule="alg1")
+    assert cnt[0] == 1 and ssum[0] == n
+    for d in range(depth):
+        assert ssum[d] <= (2 ** d) * n
+    assert 2 <= depth <= 8
