@@ -44,6 +44,8 @@ WORKLOADS = {
                         data_seed=5),
     # Poisson request stream served with admission and continuous batching
     "served": dict(kind="served", lo=1 << 12, hi=1 << 24, data_seed=6, budget_gb=64),
+    # distinct keys under the Alg. 1 pivot rule, against the default rule
+    "u32_perm_alg1": dict(kind="alg1", log2n=28, dist="permutation of 0..n-1 times an odd constant", data_seed=8),
 }
 
 
@@ -309,6 +311,72 @@ def bench_served(args, wl):
     print(json.dumps(res), flush=True)
 
 
+def bench_alg1(args, wl):
+    """n = 2^28 distinct u32 keys (a permutation, spread by an odd
+    multiplier) sorted under the Alg. 1 pivot rule and under the default
+    rule; the root's bucket sizes (Alg. 1 rule) against the Section 3.2
+    bounds: Pr[n_i >= t sqrt n] <= e^{-0.9t+0.1}, Pr[n_1 <= s] <= e^2 s /
+    sqrt n, sum n_i log n_i <= n log n / 2 + 4 e n (in expectation)."""
+    import math
+    import torch
+    from paper_2407_14801_amd import binding
+    dev = torch.device("cuda:0")
+    log2n = args.log2n or wl["log2n"]
+    n = 1 << log2n
+    print(f"# generating a permutation of 2^{log2n}", file=sys.stderr, flush=True)
+    g = np.random.Generator(np.random.PCG64(wl["data_seed"]))
+    x = (g.permutation(n).astype(np.uint64) * 2654435761 % (1 << 32)).astype(np.uint32)
+    base = torch.from_numpy(x.view(np.int32)).to(dev)
+    out = torch.empty_like(base)
+    ws = binding.Workspace(dev)
+    res_rules = {}
+    for rule in ("alg1", "replacement"):
+        ins = [base.clone() for _ in range(args.warmup + args.steps)]
+        for i in range(args.warmup):
+            used = binding.squaresort_u32(ins[i], out, seed=1, cutoff=args.cutoff, ws=ws, pivot_rule=rule)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.warmup, args.warmup + args.steps):
+            used = binding.squaresort_u32(ins[i], out, seed=1, cutoff=args.cutoff, ws=ws, pivot_rule=rule)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        o = out.to(torch.int64) & 0xFFFFFFFF
+        res_rules[rule] = {"ms_per_step": round(ms, 4), "GKeys_s": round(n / ms / 1e6, 4), "cutoff": int(used),
+                           "sorted_check": bool((o[1:] > o[:-1]).all().item())}
+        del ins
+    # root bucket sizes under the Alg. 1 rule, several seeds
+    m = int(math.isqrt(n - 1)) + 1
+    sizes = []
+    for seed in range(1, 5):
+        bs = torch.empty(m + 1, dtype=torch.int64, device=dev)
+        src = base.clone()
+        binding.skew_transpose_u32(src, out, bs, seed=seed, ws=ws, pivot_rule="alg1")
+        torch.cuda.synchronize()
+        sizes.append(np.diff(bs.cpu().numpy()))
+        del src
+    allsz = np.concatenate(sizes)
+    rn = math.sqrt(n)
+    tails = {str(t): {"measured": round(float(np.mean(allsz >= t * rn)), 6), "bound": round(math.exp(-0.9 * t + 0.1), 6)}
+             for t in (1, 2, 3, 4, 6)}
+    first = np.array([s[0] for s in sizes])
+    ent = float(np.mean([np.sum(s * np.log2(s)) for s in sizes]))
+    res = {
+        "metric": "GKeys/s", "value": res_rules["alg1"]["GKeys_s"], "unit": "GKeys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res_rules["alg1"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"squaresort_u32_perm_alg1_2^{log2n}", "n": n, "key_dist": wl["dist"],
+                   "data_seed": wl["data_seed"], "seed": 1, "pivot_rule": "alg1"},
+        "rules": res_rules,
+        "root_buckets_alg1": {"seeds": 4, "m": m, "min_size": int(allsz.min()), "max_size": int(allsz.max()),
+                              "upper_tail": tails,
+                              "first_bucket_le_s": {str(s): {"measured": round(float(np.mean(first <= s)), 4),
+                                                             "bound": round(math.e ** 2 * s / rn, 6)} for s in (2, 10, 30)},
+                              "sum_ni_log2_ni": {"measured": round(ent, 1),
+                                                 "bound": round(0.5 * n * math.log2(n) + 4 * math.e * n, 1)}},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,6 +430,8 @@ def main():
         return bench_batched(args, wl)
     if wl["kind"] == "served":
         return bench_served(args, wl)
+    if wl["kind"] == "alg1":
+        return bench_alg1(args, wl)
     log2n = args.log2n or wl["log2n"]
     n = 1 << log2n
     dev = torch.device("cuda:0")

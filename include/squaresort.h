@@ -34,6 +34,9 @@ typedef enum {
     SQS_ERR_ALIAS = -2,        /* in and out overlap                                   */
     SQS_ERR_WORKSPACE = -3,    /* workspace missing or smaller than needed            */
     SQS_ERR_DEVICE = -4,       /* a HIP launch or copy failed                         */
+    SQS_ERR_PRECOND = -5,      /* SQS_FLAG_ALG1_PIVOTS: some node found no sample of
+                                  distinct pivots in 64 draws (the input lacks
+                                  distinct keys); the output is undefined          */
     SQS_ERR_DEPTH = -6,        /* recursion deeper than SQS_MAX_DEPTH levels          */
     SQS_ERR_UNSUPPORTED = -7   /* n beyond the supported range (see sqs_max_n)        */
 } sqs_status;
@@ -41,7 +44,15 @@ typedef enum {
 enum { SQS_KIND_U32 = 0, SQS_KIND_U64 = 1, SQS_KIND_KV = 2 };
 
 enum {
-    SQS_FLAG_DIGEST = 1u       /* accumulate the recursion-tree digest into *digest    */
+    SQS_FLAG_DIGEST = 1u,      /* accumulate the recursion-tree digest into *digest    */
+    /* Pivot rule of Alg. 1 as a mode, for inputs of distinct keys: each
+     * node's m-1 pivots are pairwise distinct and differ from the node's
+     * smallest key; a sample that is not is drawn again whole (attempt a,
+     * draw t at position floor(sm64(K ^ sm64(3*2^62 | a*2^32 | t)) * n /
+     * 2^64), up to 64 attempts, else SQS_ERR_PRECOND); buckets are
+     * [p_{j-1}, p_j).  Without the flag pivots are drawn with replacement
+     * and a run of equal pivots yields a single-value bucket. */
+    SQS_FLAG_ALG1_PIVOTS = 2u
 };
 
 #define SQS_MAX_DEPTH 64

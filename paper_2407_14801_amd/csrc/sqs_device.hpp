@@ -43,6 +43,14 @@ __device__ inline uint32_t pivot_draw(uint64_t K, uint64_t t, uint32_t n)
     uint64_t u = splitmix(K ^ splitmix((1ull << 63) | t));
     return (uint32_t)__umul64hi(u, (uint64_t)n);
 }
+// draw t of sample attempt a under the Alg. 1 pivot rule (its own counter
+// range: bits 63 and 62 set, the attempt in bits 32..61)
+__device__ inline uint32_t pivot_draw_alg1(uint64_t K, uint32_t a, uint64_t t, uint32_t n)
+{
+    const uint64_t c = (3ull << 62) | ((uint64_t)(a & 0x3FFFFFFFu) << 32) | (t & 0xFFFFFFFFull);
+    uint64_t u = splitmix(K ^ splitmix(c));
+    return (uint32_t)__umul64hi(u, (uint64_t)n);
+}
 
 // ---------------------------------------------------------------- keys
 template <class K> struct KeyT;

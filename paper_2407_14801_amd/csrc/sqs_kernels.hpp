@@ -64,8 +64,12 @@ struct BucketItem {
     uint32_t node, j, lo, size;   // lo: node-local first slot
 };
 enum { CLS_COPY = 0, CLS_SMALL = 1, CLS_MID = 2, CLS_BIG = 3, CLS_INTERNAL = 4, NCLS = 5 };
-// device counters of a batch: NCLS list sizes, NCLS take counters, NCLS key totals
-constexpr int CTR_WORDS = 3 * NCLS;
+// device counters of a batch: NCLS list sizes, NCLS take counters, NCLS key
+// totals, then a flag set when the Alg. 1 pivot rule found no valid sample
+constexpr int CTR_FAIL = 3 * NCLS;
+constexpr int CTR_WORDS = 3 * NCLS + 1;
+// sample attempts of the Alg. 1 pivot rule before a node gives up
+constexpr uint32_t ALG1_ATTEMPTS = 64;
 constexpr uint32_t COPY_CH = 32768;           // keys per piece of a single-value bucket copy
 constexpr uint32_t BIG_CAP = 8 * SORT_CAP;   // largest automatic cut-off: 131072 keys
 
@@ -90,7 +94,9 @@ template <class K> struct Batch {
     uint32_t *tot;      // [j] per node
     BucketItem *list[NCLS];
     uint32_t cap[NCLS];
-    uint32_t *ctr;      // NCLS list sizes, NCLS take counters (work-groups claim items), NCLS key totals
+    uint32_t *ctr;      // NCLS list sizes, NCLS take counters (work-groups claim items), NCLS key totals, fail flag
+    K *nmin;            // per node: smallest key of its input (Alg. 1 pivot rule)
+    uint32_t alg1;      // 1: Alg. 1 pivot rule (distinct, above the minimum, resampled; [ ) buckets)
     unsigned long long *H;
 };
 
@@ -153,41 +159,84 @@ __global__ void k_sample(Batch<K> b, const K *A)
     const NodeDesc nd = b.nodes[k];
     const uint32_t t = item - b.pivStart[k];
     if (t >= nd.m - 1) return;                       // padding of the node's slot
-    b.piv[nd.piv + t] = A[nd.off + pivot_draw(nd.key, t, nd.n)];
+    const uint32_t pos = b.alg1 ? pivot_draw_alg1(nd.key, 0, t, nd.n) : pivot_draw(nd.key, t, nd.n);
+    b.piv[nd.piv + t] = A[nd.off + pos];
+}
+
+// Smallest key of every node's input (the Alg. 1 rule excludes it as a
+// pivot): one block per 16384-key chunk, an atomic min per node.
+template <class K>
+__global__ void k_node_min(Batch<K> b, const K *A)
+{
+    constexpr uint32_t CHUNK = 16384;
+    __shared__ K wmin[4];
+    const uint32_t k = find_node(b.digStart, b.N, blockIdx.x);
+    const NodeDesc nd = b.nodes[k];
+    const uint32_t r0 = (blockIdx.x - b.digStart[k]) * CHUNK, r1 = min(nd.n, r0 + CHUNK);
+    K mn = (K)KeyT<K>::MAXV;
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) { const K x = A[nd.off + r]; mn = x < mn ? x : mn; }
+    mn = wave_min(mn);
+    if (lane_id() == 0) wmin[wave_id()] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t w = 1; w < blockDim.x / WAVE; ++w) mn = wmin[w] < mn ? wmin[w] : mn;
+        if (sizeof(K) == 4) atomicMin(reinterpret_cast<unsigned int *>(&b.nmin[k]), (unsigned int)mn);
+        else atomicMin(reinterpret_cast<unsigned long long *>(&b.nmin[k]), (unsigned long long)mn);
+    }
 }
 
 // Sort the samples of one node (any correct sort; the paper uses MergeSort):
 // one work-group per node with more than WCAP pivots ...
+// Under the Alg. 1 rule a sorted sample with a repeated value or the node's
+// minimum is drawn again whole (attempt a+1, read from the node input A) up
+// to ALG1_ATTEMPTS times; every pivot is then strict ([ ) buckets).
 template <class K>
-__global__ __launch_bounds__(SORT_NT) void k_sort_pivots_big(Batch<K> b)
+__global__ __launch_bounds__(SORT_NT) void k_sort_pivots_big(Batch<K> b, const K *A)
 {
     __shared__ SortSm sm;
-    const NodeDesc nd = b.nodes[b.bigIdx[blockIdx.x]];
+    const uint32_t node = b.bigIdx[blockIdx.x];
+    const NodeDesc nd = b.nodes[node];
     const uint32_t cnt = nd.m - 1;
     K k[SORT_IPT];
     uint32_t v[SORT_IPT];
-    tables_clear<SORT_NW, 256>(sm.s.tab);
     const int R = block_rows<SORT_NW, SORT_IPT>(cnt);
+    for (uint32_t a = 0;; ++a) {
+        tables_clear<SORT_NW, 256>(sm.s.tab);          // sm.k64 below reuses the tables
+#pragma unroll
+        for (int r = 0; r < SORT_IPT; ++r) {
+            const uint32_t p = bpos(r, R);
+            k[r] = (K)0;
+            if (r < R && p < cnt) k[r] = a == 0 ? b.piv[nd.piv + p] : A[nd.off + pivot_draw_alg1(nd.key, a, p, nd.n)];
+        }
+        __syncthreads();
+        block_sort<K, false, SORT_NW, SORT_IPT>(k, v, cnt, sm);
+#pragma unroll
+        for (int r = 0; r < SORT_IPT; ++r) {
+            const uint32_t p = bpos(r, R);
+            if (r < R && p < cnt) sm.k64[p] = (uint64_t)k[r];
+        }
+        __syncthreads();
+        if (!b.alg1) break;
+        bool bad = threadIdx.x == 0 && sm.k64[0] == (uint64_t)b.nmin[node];
+        for (uint32_t t = threadIdx.x; t + 1 < cnt; t += SORT_NT) bad |= sm.k64[t] == sm.k64[t + 1];
+        if (!__syncthreads_or(bad)) break;
+        if (a + 1 == ALG1_ATTEMPTS) {
+            if (threadIdx.x == 0) atomicOr(&b.ctr[CTR_FAIL], 1u);
+            break;
+        }
+    }
 #pragma unroll
     for (int r = 0; r < SORT_IPT; ++r) {
         const uint32_t p = bpos(r, R);
-        k[r] = r < R && p < cnt ? b.piv[nd.piv + p] : (K)0;
+        if (r < R && p < cnt) b.piv[nd.piv + p] = k[r];
     }
-    __syncthreads();
-    block_sort<K, false, SORT_NW, SORT_IPT>(k, v, cnt, sm);
-#pragma unroll
-    for (int r = 0; r < SORT_IPT; ++r) {
-        const uint32_t p = bpos(r, R);
-        if (r < R && p < cnt) { b.piv[nd.piv + p] = k[r]; sm.k64[p] = (uint64_t)k[r]; }
-    }
-    __syncthreads();
     for (uint32_t t = threadIdx.x; t < cnt; t += SORT_NT)
-        b.strict[nd.piv + t] = (t + 1 < cnt && sm.k64[t] == sm.k64[t + 1]) ? 1 : 0;
+        b.strict[nd.piv + t] = b.alg1 ? 1 : ((t + 1 < cnt && sm.k64[t] == sm.k64[t + 1]) ? 1 : 0);
 }
 
 // ... and one wave per node with at most WCAP pivots.
 template <class K>
-__global__ __launch_bounds__(SM_NW * WAVE) void k_sort_pivots_small(Batch<K> b)
+__global__ __launch_bounds__(SM_NW * WAVE) void k_sort_pivots_small(Batch<K> b, const K *A)
 {
     __shared__ WaveSmem<WR> wsm[SM_NW];
     const uint32_t w = wave_id(), l = lane_id();
@@ -195,26 +244,43 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_sort_pivots_small(Batch<K> b)
     wave_lds_sync();
     const uint32_t slot = blockIdx.x * SM_NW + w;
     if (slot >= b.NS) return;
-    const NodeDesc nd = b.nodes[b.smlIdx[slot]];
+    const uint32_t node = b.smlIdx[slot];
+    const NodeDesc nd = b.nodes[node];
     const uint32_t cnt = nd.m - 1;
-    K k[WR];
+    K k[WR], nx[WR];
     uint32_t v[WR];
+    for (uint32_t a = 0;; ++a) {
 #pragma unroll
-    for (int r = 0; r < WR; ++r) {
-        const uint32_t p = r * WAVE + l;
-        k[r] = p < cnt ? b.piv[nd.piv + p] : (K)0;
+        for (int r = 0; r < WR; ++r) {
+            const uint32_t p = r * WAVE + l;
+            k[r] = (K)0;
+            if (p < cnt) k[r] = a == 0 ? b.piv[nd.piv + p] : A[nd.off + pivot_draw_alg1(nd.key, a, p, nd.n)];
+        }
+        wave_sort<K, false, WR>(k, v, cnt, wsm[w]);
+        // the next pivot in order (lane l+1, or lane 0 of the next row)
+        bool bad = false;
+#pragma unroll
+        for (int r = 0; r < WR; ++r) {
+            const uint32_t p = r * WAVE + l;
+            nx[r] = __shfl_down(k[r], 1, WAVE);
+            const K first_next = __shfl(k[r + 1 < WR ? r + 1 : r], 0, WAVE);
+            if (l == WAVE - 1) nx[r] = first_next;
+            bad |= p + 1 < cnt && nx[r] == k[r];
+        }
+        if (!b.alg1) break;
+        bad |= l == 0 && cnt > 0 && k[0] == b.nmin[node];
+        if (__ballot(bad) == 0) break;
+        if (a + 1 == ALG1_ATTEMPTS) {
+            if (l == 0) atomicOr(&b.ctr[CTR_FAIL], 1u);
+            break;
+        }
     }
-    wave_sort<K, false, WR>(k, v, cnt, wsm[w]);
-    // strict: the next pivot (lane l+1, or lane 0 of the next row) is equal
 #pragma unroll
     for (int r = 0; r < WR; ++r) {
         const uint32_t p = r * WAVE + l;
-        K nx = __shfl_down(k[r], 1, WAVE);
-        const K first_next = __shfl(k[r + 1 < WR ? r + 1 : r], 0, WAVE);
-        if (l == WAVE - 1) nx = first_next;
         if (p < cnt) {
             b.piv[nd.piv + p] = k[r];
-            b.strict[nd.piv + p] = (p + 1 < cnt && nx == k[r]) ? 1 : 0;
+            b.strict[nd.piv + p] = b.alg1 ? 1 : ((p + 1 < cnt && nx[r] == k[r]) ? 1 : 0);
         }
     }
 }

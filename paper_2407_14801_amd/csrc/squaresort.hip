@@ -110,7 +110,7 @@ uint64_t node_meta_bytes(uint64_t n, uint64_t key_bytes)
 {
     const uint64_t m = ceil_isqrt_host(n);
     const uint64_t groups = cdiv(m, TG), nJ = cdiv(m, TB);
-    return sizeof(NodeDesc) + 7 * 4 + (m - 1 + PIV_ALIGN) * (key_bytes + 1) + 4 * m * (nJ + 1) +
+    return sizeof(NodeDesc) + 7 * 4 + 8 + (m - 1 + PIV_ALIGN) * (key_bytes + 1) + 4 * m * (nJ + 1) +
            4 * groups * m + 4 * (m + 1) + 4 * m + 4 * sizeof(BucketItem) * m +
            sizeof(BucketItem) * (n / COPY_CH + 1) + 8;
 }
@@ -153,6 +153,7 @@ template <class K, bool HV> struct Engine {
     Workspace ws;
     bool digest;
     unsigned long long *digest_ptr;
+    bool alg1 = false;     // the Alg. 1 pivot rule
     // skew-transpose mode: only the root's columns and transpose, columns
     // sorted in place in A, transpose A -> out
     bool skew_only = false;
@@ -296,6 +297,8 @@ template <class K, bool HV> struct Engine {
         b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID] = capMid;
         b.cap[CLS_BIG] = capBig; b.cap[CLS_INTERNAL] = capInt;
         b.ctr = ws.take<uint32_t>(CTR_WORDS);
+        b.nmin = ws.take<K>(N);
+        b.alg1 = alg1 ? 1u : 0u;
         b.H = ws.take<unsigned long long>(N);
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         b.nodes = dDesc;
@@ -312,9 +315,16 @@ template <class K, bool HV> struct Engine {
             return SQS_ERR_DEVICE;
 
         // ---- pivots (drawn from the node inputs before any child clobbers them)
+        // counters (list sizes, take counters, key totals, the pivot-rule flag)
+        k_fill_u32<<<1, 64, 0, st>>>(b.ctr, CTR_WORDS, 0u);
+        if (alg1) {                                   // node minima for the Alg. 1 pivot rule
+            if (sizeof(K) == 4) k_fill_u32<<<cdiv(N, 256), 256, 0, st>>>(reinterpret_cast<uint32_t *>(b.nmin), N, 0xFFFFFFFFu);
+            else k_fill_u64<<<cdiv(N, 256), 256, 0, st>>>(reinterpret_cast<unsigned long long *>(b.nmin), N, ~0ull);
+            launch("k_node_min", keysTot, [&] { k_node_min<K><<<digS[N], 256, 0, st>>>(b, A); });
+        }
         if (pivS[N] > 0) launch("k_sample", pivS[N], [&] { k_sample<K><<<cdiv(pivS[N], 256), 256, 0, st>>>(b, A); });
-        if (NB) launch("k_sort_pivots", pivS[N], [&] { k_sort_pivots_big<K><<<NB, SORT_NT, 0, st>>>(b); });
-        if (NS) launch("k_sort_pivots_w", pivS[N], [&] { k_sort_pivots_small<K><<<cdiv(NS, SM_NW), SM_NW * WAVE, 0, st>>>(b); });
+        if (NB) launch("k_sort_pivots", pivS[N], [&] { k_sort_pivots_big<K><<<NB, SORT_NT, 0, st>>>(b, A); });
+        if (NS) launch("k_sort_pivots_w", pivS[N], [&] { k_sort_pivots_small<K><<<cdiv(NS, SM_NW), SM_NW * WAVE, 0, st>>>(b, A); });
         if (int rc = check()) return rc;
 
         // ---- columns: internal column children first, then sort/count
@@ -351,7 +361,6 @@ template <class K, bool HV> struct Engine {
         if (int rc = check()) return rc;
 
         // ---- buckets A -> D, by class
-        k_fill_u32<<<1, 64, 0, st>>>(b.ctr, CTR_WORDS, 0u);
         launch("k_classify", bucS[N], [&] { k_classify<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b, cutoff); });
         launch("k_bucket_copy", keysTot, [&] { k_bucket_copy<K, HV><<<512, 256, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket_w", keysTot, [&] {
@@ -376,6 +385,7 @@ template <class K, bool HV> struct Engine {
         set_units("k_bucket", hctr[2 * NCLS + CLS_MID]);
         set_units("k_bucket_big", hctr[2 * NCLS + CLS_BIG]);
         resolve_timing();
+        if (alg1 && hctr[CTR_FAIL]) return SQS_ERR_PRECOND;  // no valid Alg. 1 sample for some node
         for (int c = 0; c < NCLS; ++c)
             if (hctr[c] > b.cap[c]) return SQS_ERR_DEVICE;   // cannot happen: capacities are bounds
         if (debug_on()) {
@@ -593,6 +603,7 @@ int run_sort(uint64_t n, K *in, uint32_t *vin, K *out, uint32_t *vout, uint64_t 
     e.ws.size = p ? p->workspace_bytes : 0;
     e.digest = dig;
     e.digest_ptr = dig ? reinterpret_cast<unsigned long long *>(p->digest) : nullptr;
+    e.alg1 = p && (p->flags & SQS_FLAG_ALG1_PIVOTS);
     return e.sort_root(n, seed);
 }
 
@@ -653,6 +664,7 @@ int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket
     e.digest = false;
     e.digest_ptr = nullptr;
     e.skew_only = true;
+    e.alg1 = params->flags & SQS_FLAG_ALG1_PIVOTS;
     e.skew_out = out;
     e.skew_bs = reinterpret_cast<unsigned long long *>(bucket_start);
     std::vector<HostNode> root{{0, (uint32_t)n, splitmix(seed)}};
@@ -705,6 +717,7 @@ int run_batched(uint32_t count, const uint64_t *offsets, K *in, uint32_t *vin, K
     e.ws.size = params->workspace_bytes;
     e.digest = dig;
     e.digest_ptr = dig ? reinterpret_cast<unsigned long long *>(params->digest) : nullptr;
+    e.alg1 = params->flags & SQS_FLAG_ALG1_PIVOTS;
     return e.sort_many(count, offsets, seeds);
 }
 }  // namespace
@@ -766,6 +779,7 @@ const char *sqs_status_string(int s)
     case SQS_ERR_ALIAS: return "input and output overlap";
     case SQS_ERR_WORKSPACE: return "workspace missing or too small";
     case SQS_ERR_DEVICE: return "HIP launch or copy failed";
+    case SQS_ERR_PRECOND: return "Alg. 1 pivot rule: no sample of distinct pivots (input lacks distinct keys)";
     case SQS_ERR_DEPTH: return "recursion too deep";
     case SQS_ERR_UNSUPPORTED: return "size not supported";
     default: return "unknown status";
