@@ -56,6 +56,10 @@ struct NodeDesc {
     uint32_t pad;
 };
 constexpr uint32_t NODE_COLS_RECURSED = 1u;
+// m > SORT_CAP: a column does not fit one LDS sort.  Its columns are sorted
+// into D before the count (by the base-case kernels or by recursion), and the
+// count runs through HBM (k_blockoff, k_tilecount) instead of in LDS.
+constexpr uint32_t NODE_HUGE = 2u;
 // each node's pivot slot starts at a multiple of PIV_ALIGN keys and is padded
 // to one, so a thread can load its PIV_ALIGN pivots with 16-byte loads
 constexpr uint32_t PIV_ALIGN = 16;
@@ -784,6 +788,121 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
         }
         __syncthreads();
     }
+}
+
+// ------------------------------------------------------------ nodes with m > SORT_CAP
+// Strict flags of sorted pivots (one work-group per listed node).
+template <class K>
+__global__ void k_strict_flags(Batch<K> b, const uint32_t *nodeList)
+{
+    const NodeDesc nd = b.nodes[nodeList[blockIdx.x]];
+    const uint32_t cnt = nd.m - 1;
+    for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x)
+        b.strict[nd.piv + t] = b.alg1 ? 1 : ((t + 1 < cnt && b.piv[nd.piv + t] == b.piv[nd.piv + t + 1]) ? 1 : 0);
+}
+
+// Bucket-block offsets of a sorted column in D: srcOff[J][i] = number of keys
+// of column i at or below pivot 64J - 1 (binary search in HBM), J = 0..nJ.
+// One work-group per (node, column); colStart is the prefix of the listed
+// nodes' column counts.
+template <class K>
+__global__ void k_blockoff(Batch<K> b, const K *D, const uint32_t *nodeList, const uint32_t *colStart,
+                           uint32_t nList)
+{
+    const uint32_t q = find_node(colStart, nList, blockIdx.x);
+    const NodeDesc nd = b.nodes[nodeList[q]];
+    const uint32_t i = blockIdx.x - colStart[q];
+    const uint32_t len = column_len(i, nd.m, nd.n);
+    const K *col = D + nd.off + (uint64_t)i * nd.m;
+    for (uint32_t J = threadIdx.x; J <= nd.nJ; J += blockDim.x) {
+        uint32_t a = 0;
+        if (J == nd.nJ) a = len;
+        else if (J > 0) {
+            const uint32_t t = J * TB - 1;
+            const K pv = b.piv[nd.piv + t];
+            const bool ps = b.strict[nd.piv + t] != 0;
+            uint32_t e = len;
+            while (a < e) {
+                const uint32_t mid = (a + e) >> 1;
+                if (le_pivot(col[mid], pv, ps)) a = mid + 1; else e = mid;
+            }
+        }
+        b.srcOff[nd.src + (uint64_t)J * nd.m + i] = a;
+    }
+}
+
+// Per (column group, bucket) counts of a node whose columns are sorted in D,
+// one work-group per SkewTranspose tile (g, J): the tile's keys are read as
+// in k_transpose, each key's bucket found the same way, and the 64 bucket
+// counts are LDS atomic adds (commutative: the counts do not depend on
+// order).  Tiles of other nodes return at once.
+template <class K>
+__global__ __launch_bounds__(TR_NW * WAVE) void k_tilecount(Batch<K> b, const K *src)
+{
+    __shared__ TileSmem<K> sm;
+    __shared__ uint32_t hist[TB];
+    using T = KeyT<K>;
+    const uint32_t k = find_node(b.tileStart, b.N, blockIdx.x);
+    const NodeDesc nd = b.nodes[k];
+    if (!(nd.flags & NODE_HUGE)) return;
+    const uint32_t tix = blockIdx.x - b.tileStart[k];
+    const uint32_t g = tix / nd.nJ, J = tix % nd.nJ;
+    const uint32_t m = nd.m;
+    const uint32_t i0 = g * TG, ncol = min((uint32_t)TG, m - i0);
+    const uint32_t j0 = J * TB, nb = min((uint32_t)TB, m - j0);
+    const uint32_t npv = (j0 + nb <= m - 1) ? nb : nb - 1;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t l = lane_id(), w = wave_id();
+    if (tid < WAVE) {
+        uint32_t a = 0, len = 0;
+        if (tid < ncol) {
+            a = b.srcOff[nd.src + (uint64_t)J * m + i0 + tid];
+            len = b.srcOff[nd.src + (uint64_t)(J + 1) * m + i0 + tid] - a;
+        }
+        const uint32_t incl = wave_incl_scan(len);
+        if (tid < ncol) {
+            sm.cOff[tid] = incl - len;
+            sm.relBase[tid] = (uint64_t)(i0 + tid) * m + a - (incl - len);
+        }
+        if (tid == ncol - 1) sm.cOff[ncol] = incl;
+    }
+    if (tid < TB) hist[tid] = 0;
+    if (tid < npv) { sm.piv[tid] = b.piv[nd.piv + j0 + tid]; sm.st[tid] = b.strict[nd.piv + j0 + tid]; }
+    const K lo = j0 > 0 ? b.piv[nd.piv + j0 - 1] : (K)0;
+    __syncthreads();
+    const K hi = npv > 0 ? sm.piv[npv - 1] : lo;
+    const int sh = max(0, T::bitlen((K)(hi - lo)) - 8);
+    for (uint32_t t = tid; t <= (uint32_t)TR_LUT; t += TR_NW * WAVE) {
+        uint32_t v = npv;
+        const K step = (K)((K)t << sh);
+        if (t < (uint32_t)TR_LUT && step <= (K)((K)T::MAXV - lo)) {
+            const K x = (K)(lo + step);
+            uint32_t a = 0, e = npv;
+            while (a < e) {
+                const uint32_t mid = (a + e) >> 1;
+                if (le_pivot(x, sm.piv[mid], sm.st[mid] != 0)) e = mid; else a = mid + 1;
+            }
+            v = a;
+        }
+        sm.lut[t] = (uint8_t)v;
+    }
+    const uint32_t N = sm.cOff[ncol];
+    for (uint32_t q0 = 0; q0 < N; q0 += TR_CH) {
+        const uint32_t chN = min((uint32_t)TR_CH, N - q0);
+        for (uint32_t c = w; c < ncol; c += TR_NW) {
+            const uint32_t s0 = max(sm.cOff[c], q0), s1 = min(sm.cOff[c + 1], q0 + chN);
+            for (uint32_t q = s0 + l; q < s1; q += WAVE) sm.colOf[q - q0] = (uint8_t)c;
+        }
+        __syncthreads();
+        for (uint32_t p = tid; p < chN; p += TR_NW * WAVE) {
+            const uint32_t c = sm.colOf[p];
+            const uint64_t rel = sm.relBase[c] + q0 + p;
+            const K x = src[nd.off + (rel < nd.n ? rel : 0)];      // guard: inside the node
+            atomicAdd(&hist[tile_bucket(x, lo, sh, sm)], 1u);
+        }
+        __syncthreads();
+    }
+    if (tid < nb) b.blk[nd.blk + (uint64_t)g * m + j0 + tid] = hist[tid];
 }
 
 // ------------------------------------------------------------ digest

@@ -222,6 +222,11 @@ template <class K, bool HV> struct Engine {
         uint64_t srcTot = 0, blkTot = 0, keysTot = 0;
         uint32_t bktTot = 0;
         std::vector<HostNode> col_kids;
+        // nodes with m > SORT_CAP: their pivots and base-case columns are sorted
+        // as segments (one-bucket nodes) before the count
+        std::vector<uint32_t> hugeIdx, hugeCol{0};
+        std::vector<NodeDesc> pivSeg, colSeg;
+        std::vector<BucketItem> pivLists[NCLS], colLists[NCLS];
         for (uint32_t k = 0; k < N; ++k) {
             const HostNode &h = nodes[k];
             NodeDesc &d = desc[k];
@@ -237,11 +242,35 @@ template <class K, bool HV> struct Engine {
             d.blk = blkTot;
             d.flags = 0;
             d.pad = 0;
-            if (d.m > (uint32_t)SORT_CAP) {                                 // a column is sorted by one work-group
-                if (debug_on()) fprintf(stderr, "[sqs] depth %d node %u: n=%u m=%u unsupported\n", depth, k, h.n, d.m);
-                return SQS_ERR_UNSUPPORTED;
-            }
-            if (!skew_only && d.m > cutoff) {
+            const bool huge = d.m > (uint32_t)SORT_CAP;
+            if (huge) {
+                // columns do not fit one LDS sort: sorted into D first (the
+                // Alg. 1 rule and the skew entry point keep the LDS-sized limit)
+                if (skew_only || alg1) return SQS_ERR_UNSUPPORTED;
+                d.flags |= NODE_HUGE | NODE_COLS_RECURSED;
+                hugeIdx.push_back(k);
+                hugeCol.push_back(hugeCol.back() + d.m);
+                NodeDesc pn{};
+                pn.off = d.piv;
+                pn.n = d.m - 1;
+                pn.m = 1;
+                pivLists[CLS_BIG].push_back(BucketItem{(uint32_t)pivSeg.size(), 0u, 0u, d.m - 1});
+                pivSeg.push_back(pn);
+                NodeDesc cn{};
+                cn.off = d.off;
+                cn.n = d.n;
+                cn.m = 1;
+                const uint32_t cnode = (uint32_t)colSeg.size();
+                colSeg.push_back(cn);
+                for (uint32_t i = 0; i < d.m; ++i) {
+                    const uint64_t lo = (uint64_t)i * d.m;
+                    if (lo >= h.n) break;
+                    const uint32_t len = (uint32_t)std::min<uint64_t>(d.m, h.n - lo);
+                    if (len > cutoff) { col_kids.push_back({h.off + lo, len, node_child_key(h.key, 0, i)}); continue; }
+                    const int cls = len <= (uint32_t)WCAP ? CLS_SMALL : len <= (uint32_t)SORT_CAP ? CLS_MID : CLS_BIG;
+                    colLists[cls].push_back(BucketItem{cnode, 0u, (uint32_t)lo, len});
+                }
+            } else if (!skew_only && d.m > cutoff) {
                 d.flags |= NODE_COLS_RECURSED;
                 for (uint32_t i = 0; i < d.m; ++i) {
                     const uint64_t lo = (uint64_t)i * d.m;
@@ -251,7 +280,8 @@ template <class K, bool HV> struct Engine {
                     if (len > cutoff) col_kids.push_back({h.off + lo, len, node_child_key(h.key, 0, i)});
                 }
             }
-            if (d.m > (uint32_t)WCAP) { bigIdx.push_back(k); bigGrp.push_back(bigGrp.back() + d.groups); }
+            if (huge) {
+            } else if (d.m > (uint32_t)WCAP) { bigIdx.push_back(k); bigGrp.push_back(bigGrp.back() + d.groups); }
             else { smlIdx.push_back(k); smlGrp.push_back(smlGrp.back() + d.groups); }
             pivS[k + 1] = pivS[k] + (uint32_t)align_up(d.m - 1, PIV_ALIGN);   // 16-key aligned slots
             tileS[k + 1] = tileS[k] + d.groups * d.nJ;
@@ -270,6 +300,9 @@ template <class K, bool HV> struct Engine {
         const size_t oBigGrp = idx.size(); idx.insert(idx.end(), bigGrp.begin(), bigGrp.end());
         const size_t oSmlIdx = idx.size(); idx.insert(idx.end(), smlIdx.begin(), smlIdx.end());
         const size_t oSmlGrp = idx.size(); idx.insert(idx.end(), smlGrp.begin(), smlGrp.end());
+        const uint32_t NH = (uint32_t)hugeIdx.size();
+        const size_t oHugeIdx = idx.size(); idx.insert(idx.end(), hugeIdx.begin(), hugeIdx.end());
+        const size_t oHugeCol = idx.size(); idx.insert(idx.end(), hugeCol.begin(), hugeCol.end());
 
         // work-list capacities: every bucket may be small or single-valued;
         // mid buckets hold > WCAP keys and internal ones > cutoff keys
@@ -300,6 +333,7 @@ template <class K, bool HV> struct Engine {
         b.nmin = ws.take<K>(N);
         b.alg1 = alg1 ? 1u : 0u;
         b.H = ws.take<unsigned long long>(N);
+        K *pivScratch = NH ? ws.take<K>(std::max<uint32_t>(pivS[N], 1)) : nullptr;
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         b.nodes = dDesc;
         b.N = N;
@@ -326,6 +360,18 @@ template <class K, bool HV> struct Engine {
         if (NB) launch("k_sort_pivots", pivS[N], [&] { k_sort_pivots_big<K><<<NB, SORT_NT, 0, st>>>(b, A); });
         if (NS) launch("k_sort_pivots_w", pivS[N], [&] { k_sort_pivots_small<K><<<cdiv(NS, SM_NW), SM_NW * WAVE, 0, st>>>(b, A); });
         if (int rc = check()) return rc;
+        const uint32_t *dHugeIdx = dIdx + oHugeIdx, *dHugeCol = dIdx + oHugeCol;
+        if (NH) {                                     // pivots of m > SORT_CAP nodes: MSD-split sorts, then flags
+            if (int rc = sort_segments<false>(b.piv, nullptr, pivScratch, nullptr, pivSeg, pivLists)) return rc;
+            for (uint32_t q = 0; q < NH; ++q) {
+                const NodeDesc &d = desc[hugeIdx[q]];
+                if (hipMemcpyAsync(b.piv + d.piv, pivScratch + d.piv, (uint64_t)(d.m - 1) * sizeof(K),
+                                   hipMemcpyDeviceToDevice, st) != hipSuccess)
+                    return SQS_ERR_DEVICE;
+            }
+            k_strict_flags<K><<<NH, 256, 0, st>>>(b, dHugeIdx);
+            if (int rc = check()) return rc;
+        }
 
         // ---- columns: internal column children first, then sort/count
         if (!col_kids.empty()) {
@@ -334,6 +380,13 @@ template <class K, bool HV> struct Engine {
         }
         K *cdst = skew_only ? A : D;
         uint32_t *vcdst = skew_only ? VA : VD;
+        if (NH) {                                     // m > SORT_CAP: base-case columns A -> D, then the HBM count
+            if (int rc = sort_segments<HV>(A, VA, D, VD, colSeg, colLists)) return rc;
+            launch("k_blockoff", keysTot, [&] {
+                k_blockoff<K><<<hugeCol.back(), 256, 0, st>>>(b, D, dHugeIdx, dHugeCol, NH); });
+            launch("k_tilecount", keysTot, [&] { k_tilecount<K><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, D); });
+            if (int rc = check()) return rc;
+        }
         if (NB) launch("k_colsort", keysTot, [&] {
             k_colsort_big<K, HV><<<bigGrp.back(), SORT_NT, 0, st>>>(b, A, VA, cdst, vcdst, cutoff); });
         if (NS) launch("k_colsort_w", keysTot, [&] {
@@ -379,6 +432,7 @@ template <class K, bool HV> struct Engine {
             hipMemcpyAsync(hint.data(), b.list[CLS_INTERNAL], capInt * sizeof(BucketItem), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return SQS_ERR_DEVICE;
+        keep_.clear();                                   // the stream has run every upload
         // the bucket kernels processed the keys of their own class only
         set_units("k_bucket_copy", hctr[2 * NCLS + CLS_COPY]);
         set_units("k_bucket_w", hctr[2 * NCLS + CLS_SMALL]);
@@ -463,6 +517,54 @@ template <class K, bool HV> struct Engine {
         return run_batch(root, 0);
     }
 
+    // Sorts independent segments src -> dst with the base-case kernels.  pn
+    // are one-bucket nodes (m = 1, so a segment's key range is the whole
+    // type) giving each segment's base; lists hold the segments by class
+    // (small, mid, big).  Takes workspace; the caller keeps pn and lists
+    // alive until the stream has run the uploads.
+    template <bool HV2>
+    int sort_segments(K *sA, uint32_t *sVA, K *sD, uint32_t *sVD, const std::vector<NodeDesc> &pn,
+                      std::vector<BucketItem> (&lists)[NCLS])
+    {
+        Batch<K> b{};
+        NodeDesc *dDesc = ws.take<NodeDesc>(pn.size());
+        for (int c = CLS_SMALL; c <= CLS_BIG; ++c) {
+            b.list[c] = ws.take<BucketItem>(std::max<size_t>(lists[c].size(), 1));
+            b.cap[c] = (uint32_t)lists[c].size();
+        }
+        uint32_t *ctr = ws.take<uint32_t>(CTR_WORDS);
+        if (ws.overflow) return SQS_ERR_WORKSPACE;
+        keep_.emplace_back(CTR_WORDS * 4, 0);
+        uint32_t *hctr = reinterpret_cast<uint32_t *>(keep_.back().data());
+        for (int c = CLS_SMALL; c <= CLS_BIG; ++c) hctr[c] = (uint32_t)lists[c].size();
+        if (hipMemcpyAsync(dDesc, pn.data(), pn.size() * sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(ctr, hctr, CTR_WORDS * 4, hipMemcpyHostToDevice, st) != hipSuccess)
+            return SQS_ERR_DEVICE;
+        for (int c = CLS_SMALL; c <= CLS_BIG; ++c)
+            if (!lists[c].empty() &&
+                hipMemcpyAsync(b.list[c], lists[c].data(), lists[c].size() * sizeof(BucketItem),
+                               hipMemcpyHostToDevice, st) != hipSuccess)
+                return SQS_ERR_DEVICE;
+        b.nodes = dDesc;
+        b.N = (uint32_t)pn.size();
+        b.ctr = ctr;
+        uint64_t keys[NCLS] = {};
+        for (int c = CLS_SMALL; c <= CLS_BIG; ++c)
+            for (const BucketItem &e : lists[c]) keys[c] += e.size;
+        if (!lists[CLS_SMALL].empty())
+            launch("k_bucket_w", keys[CLS_SMALL], [&] {
+                k_bucket_small<K, HV2><<<std::min<uint32_t>(cdiv(b.cap[CLS_SMALL], SM_NW), 2048), SM_NW * WAVE, 0, st>>>(
+                    b, sA, sVA, sD, sVD); });
+        if (!lists[CLS_MID].empty())
+            launch("k_bucket", keys[CLS_MID], [&] {
+                k_bucket_mid<K, HV2><<<std::min<uint32_t>(b.cap[CLS_MID], 512), SORT_NT, 0, st>>>(b, sA, sVA, sD, sVD); });
+        if (!lists[CLS_BIG].empty())
+            launch("k_bucket_big", keys[CLS_BIG], [&] {
+                k_bucket_big<K, HV2><<<std::min<uint32_t>(b.cap[CLS_BIG], 256), SORT_NT, 0, st>>>(b, sA, sVA, sD, sVD); });
+        return check();
+    }
+    std::vector<std::vector<char>> keep_;      // host copies that async uploads read
+
     // Independent instances [offs[i], offs[i+1]) with seeds[i].  Each base-case
     // instance becomes a one-bucket node (m = 1, so its key range is the whole
     // type) on the bucket work lists; every other instance is a root node of
@@ -487,41 +589,7 @@ template <class K, bool HV> struct Engine {
         }
         if (!leaf.empty()) {
             const uint64_t mark = ws.top;
-            Batch<K> b{};
-            NodeDesc *dDesc = ws.take<NodeDesc>(leaf.size());
-            for (int c = CLS_SMALL; c <= CLS_BIG; ++c) {
-                b.list[c] = ws.take<BucketItem>(std::max<size_t>(lists[c].size(), 1));
-                b.cap[c] = (uint32_t)lists[c].size();
-            }
-            uint32_t *ctr = ws.take<uint32_t>(CTR_WORDS);
-            if (ws.overflow) return SQS_ERR_WORKSPACE;
-            uint32_t hctr[CTR_WORDS] = {};
-            for (int c = CLS_SMALL; c <= CLS_BIG; ++c) hctr[c] = (uint32_t)lists[c].size();
-            if (hipMemcpyAsync(dDesc, leaf.data(), leaf.size() * sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
-                hipMemcpyAsync(ctr, hctr, sizeof hctr, hipMemcpyHostToDevice, st) != hipSuccess)
-                return SQS_ERR_DEVICE;
-            for (int c = CLS_SMALL; c <= CLS_BIG; ++c)
-                if (!lists[c].empty() &&
-                    hipMemcpyAsync(b.list[c], lists[c].data(), lists[c].size() * sizeof(BucketItem),
-                                   hipMemcpyHostToDevice, st) != hipSuccess)
-                    return SQS_ERR_DEVICE;
-            b.nodes = dDesc;
-            b.N = (uint32_t)leaf.size();
-            b.ctr = ctr;
-            uint64_t keys[NCLS] = {};
-            for (int c = CLS_SMALL; c <= CLS_BIG; ++c)
-                for (const BucketItem &e : lists[c]) keys[c] += e.size;
-            if (!lists[CLS_SMALL].empty())
-                launch("k_bucket_w", keys[CLS_SMALL], [&] {
-                    k_bucket_small<K, HV><<<std::min<uint32_t>(cdiv(b.cap[CLS_SMALL], SM_NW), 2048), SM_NW * WAVE, 0, st>>>(
-                        b, A, VA, D, VD); });
-            if (!lists[CLS_MID].empty())
-                launch("k_bucket", keys[CLS_MID], [&] {
-                    k_bucket_mid<K, HV><<<std::min<uint32_t>(b.cap[CLS_MID], 512), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
-            if (!lists[CLS_BIG].empty())
-                launch("k_bucket_big", keys[CLS_BIG], [&] {
-                    k_bucket_big<K, HV><<<std::min<uint32_t>(b.cap[CLS_BIG], 256), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
-            if (int rc = check()) return rc;
+            if (int rc = sort_segments<HV>(A, VA, D, VD, leaf, lists)) return rc;
             if (hipStreamSynchronize(st) != hipSuccess) return SQS_ERR_DEVICE;   // host lists outlive the uploads
             resolve_timing();
             ws.top = mark;
@@ -556,9 +624,16 @@ uint64_t max_cutoff_of(int kind) { return (kind >= SQS_KIND_U32 && kind <= SQS_K
 uint64_t max_n_of(int kind)
 {
     if (kind < SQS_KIND_U32 || kind > SQS_KIND_KV) return 0;
-    // the root's columns (and its m-1 pivots) are sorted by one work-group each
-    const uint64_t mm = (uint64_t)SORT_CAP;
-    return std::min<uint64_t>(mm * mm, 0xFFFFFFFFull);
+    // 32-bit positions inside a node; columns longer than one LDS sort are
+    // sorted through HBM (NODE_HUGE)
+    return 0xFFFFFFFFull;
+}
+
+// the skew entry point and the Alg. 1 pivot rule keep columns within one LDS sort
+uint64_t max_n_lds(int kind)
+{
+    if (kind < SQS_KIND_U32 || kind > SQS_KIND_KV) return 0;
+    return (uint64_t)SORT_CAP * SORT_CAP;
 }
 
 int resolve_cutoff(int kind, sqs_params *p, uint32_t *out)
@@ -647,7 +722,7 @@ int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket
     uint32_t C;
     if (int rc = resolve_cutoff(SQS_KIND_U32, params, &C)) return rc;
     if (n < 2 || !in || !out) return SQS_ERR_ARG;
-    if (n > max_n_of(SQS_KIND_U32)) return SQS_ERR_UNSUPPORTED;
+    if (n > max_n_lds(SQS_KIND_U32)) return SQS_ERR_UNSUPPORTED;
     if (overlap(in, n * 4, out, n * 4)) return SQS_ERR_ALIAS;
     const uint64_t m = ceil_isqrt_host(n);
     if (bucket_start && (overlap(bucket_start, (m + 1) * 8, in, n * 4) || overlap(bucket_start, (m + 1) * 8, out, n * 4)))
