@@ -1122,18 +1122,26 @@ struct BigSeg {
     uint32_t pad;
     uint64_t lo, hi;             // inclusive key range of the segment
 };
+// The MSD-split kernel runs half-size work-groups (8 waves, 8192-key LDS
+// sorts, about 76 KB of LDS) so that two share a CU and one's global-memory
+// phases overlap the other's LDS work.
+constexpr int BK_NW = 8;
+constexpr int BK_IPT = 16;
+constexpr int BK_NT = BK_NW * WAVE;
+constexpr int BK_CAP = BK_NT * BK_IPT;          // 8192 keys per LDS sort
+using BigSm = SortSmem<BK_NW, BK_IPT>;
 constexpr int BIG_STACK = 256;
 constexpr int SPLIT_MAX = 4;                 // at most 16 parts per split
-constexpr uint32_t SPLIT_PART = 12288;       // aimed part size (fits one LDS sort with room)
+constexpr uint32_t SPLIT_PART = 6144;        // aimed part size (fits one LDS sort with room)
 
 template <class K, bool HV>
-__global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32_t *VA, K *D, uint32_t *VD)
+__global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint32_t *VA, K *D, uint32_t *VD)
 {
     using T = KeyT<K>;
-    __shared__ SortSm sm;
+    __shared__ BigSm sm;
     __shared__ BigSeg stack[BIG_STACK];
     __shared__ uint32_t hist[256], base[256], run[256];
-    __shared__ uint32_t whist[SORT_NW][1 << SPLIT_MAX];
+    __shared__ uint32_t whist[BK_NW][1 << SPLIT_MAX];
     __shared__ uint32_t sp_sh, overflow_sh;
     const uint32_t tid = threadIdx.x;
     __shared__ uint32_t take_sh;
@@ -1159,28 +1167,28 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
             K *src = sg.in_d ? D : A;
             uint32_t *vsrc = sg.in_d ? VD : VA;
             const uint64_t sb = bbase + sg.off;
-            if (sg.size <= (uint32_t)SORT_CAP || sg.lo == sg.hi) {
+            if (sg.size <= (uint32_t)BK_CAP || sg.lo == sg.hi) {
                 if (sg.lo == sg.hi) {                       // one key value: already in order
                     if (!sg.in_d)
-                        for (uint32_t p = tid; p < sg.size; p += SORT_NT) {
+                        for (uint32_t p = tid; p < sg.size; p += BK_NT) {
                             D[sb + p] = A[sb + p];
                             if (HV) VD[sb + p] = VA[sb + p];
                         }
                 } else {
-                    K kk[SORT_IPT];
-                    uint32_t vv[SORT_IPT];
-                    tables_clear<SORT_NW, 256>(sm.s.tab);
-                    const int R = block_rows<SORT_NW, SORT_IPT>(sg.size);
+                    K kk[BK_IPT];
+                    uint32_t vv[BK_IPT];
+                    tables_clear<BK_NW, 256>(sm.s.tab);
+                    const int R = block_rows<BK_NW, BK_IPT>(sg.size);
 #pragma unroll
-                    for (int r = 0; r < SORT_IPT; ++r) {
+                    for (int r = 0; r < BK_IPT; ++r) {
                         const uint32_t p = bpos(r, R);
                         kk[r] = r < R && p < sg.size ? src[sb + p] : (K)0;
                         if (HV) vv[r] = r < R && p < sg.size ? vsrc[sb + p] : 0u;
                     }
                     __syncthreads();
-                    block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, sg.size, sm, true, (K)sg.lo, (K)sg.hi);
+                    block_sort<K, HV, BK_NW, BK_IPT>(kk, vv, sg.size, sm, true, (K)sg.lo, (K)sg.hi);
 #pragma unroll
-                    for (int r = 0; r < SORT_IPT; ++r) {
+                    for (int r = 0; r < BK_IPT; ++r) {
                         const uint32_t p = bpos(r, R);
                         if (r < R && p < sg.size) {
                             D[sb + p] = kk[r];
@@ -1209,17 +1217,17 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
             const int shift = bits - sbits;
             const uint32_t nparts = 1u << sbits;
             if (tid < 256) { hist[tid] = 0; run[tid] = 0; }
-            if (tid < SORT_NW * (1 << SPLIT_MAX)) (&whist[0][0])[tid] = 0;
+            if (tid < BK_NW * (1 << SPLIT_MAX)) (&whist[0][0])[tid] = 0;
             __syncthreads();
             {                                                            // count, per-wave histograms
                 uint32_t *wh = whist[wave_id()];
-                for (uint32_t p = tid; p < sg.size; p += SORT_NT)
+                for (uint32_t p = tid; p < sg.size; p += BK_NT)
                     atomicAdd(&wh[min((uint32_t)(((K)(src[sb + p] - klo)) >> shift), nparts - 1)], 1u);
             }
             __syncthreads();
             if (tid < nparts) {
                 uint32_t c = 0;
-                for (int w = 0; w < SORT_NW; ++w) c += whist[w][tid];
+                for (int w = 0; w < BK_NW; ++w) c += whist[w][tid];
                 hist[tid] = c;
             }
             __syncthreads();
@@ -1229,18 +1237,18 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
                 uint32_t r0 = wave_incl_scan(t4) - t4;
                 for (int q = 0; q < 4; ++q) { if (4 * tid + q < 256) base[4 * tid + q] = r0; r0 += c[q]; }
             }
-            tables_clear<SORT_NW, 256>(sm.s.tab);
+            tables_clear<BK_NW, 256>(sm.s.tab);
             __syncthreads();
-            for (uint32_t c0 = 0; c0 < sg.size; c0 += SORT_CAP) {       // stable scatter, chunk by chunk
-                const uint32_t chN = min((uint32_t)SORT_CAP, sg.size - c0);
-                const int nrows = wave_rows<SORT_IPT>(chN);
+            for (uint32_t c0 = 0; c0 < sg.size; c0 += BK_CAP) {       // stable scatter, chunk by chunk
+                const uint32_t chN = min((uint32_t)BK_CAP, sg.size - c0);
+                const int nrows = wave_rows<BK_IPT>(chN);
                 RankTab<256> &tab = sm.s.tab[wave_id()];
-                K kk[SORT_IPT];
-                uint32_t vv[SORT_IPT], pos[SORT_IPT];
+                K kk[BK_IPT];
+                uint32_t vv[BK_IPT], pos[BK_IPT];
 #pragma unroll
-                for (int r = 0; r < SORT_IPT; ++r) {
+                for (int r = 0; r < BK_IPT; ++r) {
                     if (r < nrows) {
-                        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
+                        const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
                         kk[r] = p < chN ? src[sb + c0 + p] : (K)0;
                         if (HV) vv[r] = p < chN ? vsrc[sb + c0 + p] : 0u;
                         const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
@@ -1248,11 +1256,11 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
                     }
                 }
                 __syncthreads();
-                scan_tables<SORT_NW, 256>(sm.s.tab, sm.wsum);
+                scan_tables<BK_NW, 256>(sm.s.tab, sm.wsum);
 #pragma unroll
-                for (int r = 0; r < SORT_IPT; ++r) {
+                for (int r = 0; r < BK_IPT; ++r) {
                     if (r < nrows) {
-                        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
+                        const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
                         const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
                         pos[r] += tab.off[d];
                     }
@@ -1260,28 +1268,28 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_big(Batch<K> b, K *A, uint32
 #pragma unroll
                 for (int wd = 0; wd < T::WORDS; ++wd) {
 #pragma unroll
-                    for (int r = 0; r < SORT_IPT; ++r)
+                    for (int r = 0; r < BK_IPT; ++r)
                         if (r < nrows) sm.s.buf[pos[r]] = T::word(kk[r], wd);
                     __syncthreads();
 #pragma unroll
-                    for (int r = 0; r < SORT_IPT; ++r)
-                        if (r < nrows) kk[r] = T::set_word(kk[r], wd, sm.s.buf[item_pos<SORT_NW, SORT_IPT>(r)]);
+                    for (int r = 0; r < BK_IPT; ++r)
+                        if (r < nrows) kk[r] = T::set_word(kk[r], wd, sm.s.buf[item_pos<BK_NW, BK_IPT>(r)]);
                     __syncthreads();
                 }
                 if (HV) {
 #pragma unroll
-                    for (int r = 0; r < SORT_IPT; ++r) if (r < nrows) sm.s.buf[pos[r]] = vv[r];
+                    for (int r = 0; r < BK_IPT; ++r) if (r < nrows) sm.s.buf[pos[r]] = vv[r];
                     __syncthreads();
 #pragma unroll
-                    for (int r = 0; r < SORT_IPT; ++r) if (r < nrows) vv[r] = sm.s.buf[item_pos<SORT_NW, SORT_IPT>(r)];
+                    for (int r = 0; r < BK_IPT; ++r) if (r < nrows) vv[r] = sm.s.buf[item_pos<BK_NW, BK_IPT>(r)];
                     __syncthreads();
                 }
                 // element at chunk position p has digit d (recomputed from its key);
                 // it goes to base[d] + run[d] + (p - start of d in this chunk)
 #pragma unroll
-                for (int r = 0; r < SORT_IPT; ++r) {
+                for (int r = 0; r < BK_IPT; ++r) {
                     if (r < nrows) {
-                        const uint32_t p = item_pos<SORT_NW, SORT_IPT>(r);
+                        const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
                         if (p < chN) {
                             const uint32_t d = min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1);
                             const uint32_t at = base[d] + run[d] + (p - sm.s.tab[0].off[d]);

@@ -422,7 +422,7 @@ template <class K, bool HV> struct Engine {
             k_bucket_mid<K, HV><<<std::min<uint32_t>(capMid, 512), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
         if (cutoff > (uint32_t)SORT_CAP)
             launch("k_bucket_big", keysTot, [&] {
-                k_bucket_big<K, HV><<<std::min<uint32_t>(capBig, 256), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
+                k_bucket_big<K, HV><<<std::min<uint32_t>(capBig, 512), BK_NT, 0, st>>>(b, A, VA, D, VD); });
         if (int rc = check()) return rc;
 
         // ---- internal buckets form the next batch
@@ -493,7 +493,7 @@ template <class K, bool HV> struct Engine {
             return SQS_ERR_DEVICE;
         b.nodes = dDesc; b.N = 1; b.ctr = ctr;
         b.list[CLS_BIG] = item; b.cap[CLS_BIG] = 1;
-        launch("k_bucket_big", n, [&] { k_bucket_big<K, HV><<<1, SORT_NT, 0, st>>>(b, A, VA, D, VD); });
+        launch("k_bucket_big", n, [&] { k_bucket_big<K, HV><<<1, BK_NT, 0, st>>>(b, A, VA, D, VD); });
         if (int rc = check()) return rc;
         if (hipStreamSynchronize(st) != hipSuccess) return SQS_ERR_DEVICE;   // host copies outlive the upload
         resolve_timing();
@@ -560,7 +560,7 @@ template <class K, bool HV> struct Engine {
                 k_bucket_mid<K, HV2><<<std::min<uint32_t>(b.cap[CLS_MID], 512), SORT_NT, 0, st>>>(b, sA, sVA, sD, sVD); });
         if (!lists[CLS_BIG].empty())
             launch("k_bucket_big", keys[CLS_BIG], [&] {
-                k_bucket_big<K, HV2><<<std::min<uint32_t>(b.cap[CLS_BIG], 256), SORT_NT, 0, st>>>(b, sA, sVA, sD, sVD); });
+                k_bucket_big<K, HV2><<<std::min<uint32_t>(b.cap[CLS_BIG], 512), BK_NT, 0, st>>>(b, sA, sVA, sD, sVD); });
         return check();
     }
     std::vector<std::vector<char>> keep_;      // host copies that async uploads read
