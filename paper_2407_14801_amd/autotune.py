@@ -12,7 +12,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-DEFAULT_CANDIDATES = (1024, 4096, 16384, 65536, 131072)
+DEFAULT_CANDIDATES = (4096, 16384, 65536, 131072, 262144)
 
 
 def tune_batched_cutoff(pristine: torch.Tensor, offsets, seeds, candidates=DEFAULT_CANDIDATES,

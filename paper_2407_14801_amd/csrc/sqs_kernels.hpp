@@ -75,7 +75,7 @@ constexpr int CTR_WORDS = 3 * NCLS + 1;
 // sample attempts of the Alg. 1 pivot rule before a node gives up
 constexpr uint32_t ALG1_ATTEMPTS = 64;
 constexpr uint32_t COPY_CH = 32768;           // keys per piece of a single-value bucket copy
-constexpr uint32_t BIG_CAP = 8 * SORT_CAP;   // largest automatic cut-off: 131072 keys
+constexpr uint32_t BIG_CAP = 16 * SORT_CAP;  // largest automatic cut-off: 262144 keys
 
 template <class K> struct Batch {
     const NodeDesc *nodes;

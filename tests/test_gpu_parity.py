@@ -89,8 +89,9 @@ U32_CASES = [
     ((1 << 20) + 3, 0), (3_000_017, 0), (130_000, 256),
     # whole array a base case sorted with MSD splits (16384 < n <= cutoff)
     (16_385, 0), (50_000, 0), (65_536, 0), (100_000, 0), (131_072, 0),
+    (131_073, 0), (262_144, 0),
     # just above the automatic cut-off: one internal level with big buckets
-    (131_073, 0),
+    (262_145, 0),
     # buckets of 16K..64K keys (MSD-split base cases inside the bucket phase)
     ((1 << 24) + 5, 0), ((1 << 22) + 1, 20_000),
 ]
