@@ -418,7 +418,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: this benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU exchange is a design note only)", file=sys.stderr)
         sys.exit(2)
 
