@@ -98,6 +98,7 @@ template <class K> struct Batch {
     uint32_t *tot;      // [j] per node
     BucketItem *list[NCLS];
     uint32_t cap[NCLS];
+    const uint32_t *order[NCLS];   // claim order of a list (largest items first), or null: list order
     uint32_t *ctr;      // NCLS list sizes, NCLS take counters (work-groups claim items), NCLS key totals, fail flag
     K *nmin;            // per node: smallest key of its input (Alg. 1 pivot rule)
     uint32_t alg1;      // 1: Alg. 1 pivot rule (distinct, above the minimum, resampled; [ ) buckets)
@@ -1070,6 +1071,41 @@ __device__ inline void bucket_bounds(const Batch<K> &b, const NodeDesc &nd, uint
     else { const K s = b.piv[nd.piv + j]; hi = b.strict[nd.piv + j] ? (K)(s - 1) : s; }
 }
 
+// Claim order of the mid (block 0) and big (block 1) bucket lists: largest
+// items first.  Work-groups take items one at a time, so taking them in
+// decreasing size (longest-processing-time order) makes the work-groups that
+// take the last items finish close together; in list order a large bucket
+// taken late sets the end of the whole kernel.  Sizes are counting-sorted
+// into 256 bins of 2^shift keys; the order inside a bin is whatever the
+// atomics give, and no output depends on it.
+template <class K>
+__global__ __launch_bounds__(1024) void k_order_lists(Batch<K> b, uint32_t *ordMid, uint32_t *ordBig,
+                                                      uint32_t shiftMid, uint32_t shiftBig)
+{
+    __shared__ uint32_t at[256];
+    const int c = blockIdx.x == 0 ? CLS_MID : CLS_BIG;
+    uint32_t *ord = blockIdx.x == 0 ? ordMid : ordBig;
+    const uint32_t shift = blockIdx.x == 0 ? shiftMid : shiftBig;
+    if (!ord) return;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t cnt = min(b.ctr[c], b.cap[c]);
+    const BucketItem *lst = b.list[c];
+    if (tid < 256) at[tid] = 0;
+    __syncthreads();
+    for (uint32_t i = tid; i < cnt; i += blockDim.x)                  // bin 0 holds the largest sizes
+        atomicAdd(&at[255u - min((lst[i].size - 1u) >> shift, 255u)], 1u);
+    __syncthreads();
+    if (tid < WAVE) {                                                  // exclusive scan, 4 bins a lane
+        uint32_t v[4], t4 = 0;
+        for (int q = 0; q < 4; ++q) { v[q] = at[4 * tid + q]; t4 += v[q]; }
+        uint32_t r0 = wave_incl_scan(t4) - t4;
+        for (int q = 0; q < 4; ++q) { at[4 * tid + q] = r0; r0 += v[q]; }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < cnt; i += blockDim.x)
+        ord[atomicAdd(&at[255u - min((lst[i].size - 1u) >> shift, 255u)], 1u)] = i;
+}
+
 // Buckets of WCAP+1 .. cutoff keys: one work-group per bucket (persistent).
 template <class K, bool HV>
 __global__ __launch_bounds__(SORT_NT) void k_bucket_mid(Batch<K> b, const K *A, const uint32_t *VA,
@@ -1081,7 +1117,7 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_mid(Batch<K> b, const K *A, 
     __shared__ uint32_t take_sh;
     const uint32_t cnt = min(b.ctr[CLS_MID], b.cap[CLS_MID]);
     for (uint32_t it = take_item(b.ctr, CLS_MID, &take_sh); it < cnt; it = take_item(b.ctr, CLS_MID, &take_sh)) {
-        const BucketItem e = b.list[CLS_MID][it];
+        const BucketItem e = b.list[CLS_MID][b.order[CLS_MID] ? b.order[CLS_MID][it] : it];
         const uint64_t base = b.nodes[e.node].off + e.lo;
         K kk[SORT_IPT];
         uint32_t vv[SORT_IPT];
@@ -1147,7 +1183,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
     __shared__ uint32_t take_sh;
     const uint32_t cnt = min(b.ctr[CLS_BIG], b.cap[CLS_BIG]);
     for (uint32_t it = take_item(b.ctr, CLS_BIG, &take_sh); it < cnt; it = take_item(b.ctr, CLS_BIG, &take_sh)) {
-        const BucketItem e = b.list[CLS_BIG][it];
+        const BucketItem e = b.list[CLS_BIG][b.order[CLS_BIG] ? b.order[CLS_BIG][it] : it];
         const NodeDesc nd = b.nodes[e.node];
         const uint64_t bbase = nd.off + e.lo;
         if (tid == 0) {

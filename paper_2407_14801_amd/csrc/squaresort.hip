@@ -83,6 +83,13 @@ bool debug_on()
     return on;
 }
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+// shift that puts item sizes 1..cap into 256 bins (k_order_lists)
+inline uint32_t shift_of(uint32_t cap)
+{
+    uint32_t bits = 0;
+    while (bits < 32 && ((uint64_t)1 << bits) < cap) ++bits;     // 2^bits >= cap
+    return bits > 8 ? bits - 8 : 0u;
+}
 
 struct HostNode {
     uint64_t off;
@@ -111,7 +118,7 @@ uint64_t node_meta_bytes(uint64_t n, uint64_t key_bytes)
     const uint64_t m = ceil_isqrt_host(n);
     const uint64_t groups = cdiv(m, TG), nJ = cdiv(m, TB);
     return sizeof(NodeDesc) + 7 * 4 + 8 + (m - 1 + PIV_ALIGN) * (key_bytes + 1) + 4 * m * (nJ + 1) +
-           4 * groups * m + 4 * (m + 1) + 4 * m + 4 * sizeof(BucketItem) * m +
+           4 * groups * m + 4 * (m + 1) + 4 * m + 4 * sizeof(BucketItem) * m + 2 * 4 * m +
            sizeof(BucketItem) * (n / COPY_CH + 1) + 8;
 }
 
@@ -126,7 +133,7 @@ uint64_t batch_bound(uint64_t S, uint64_t C, uint64_t key_bytes)
     const uint64_t big = node_meta_bytes(S, key_bytes);
     const uint64_t nodes = S / (C + 1) + 1;
     const uint64_t sq = ceil_isqrt_host(C + 1);
-    const uint64_t per_m = key_bytes + 1 + 4 * 2 + 4 + 4 + 4 + 4 * sizeof(BucketItem) + 8;   // generous
+    const uint64_t per_m = key_bytes + 1 + 4 * 2 + 4 + 4 + 4 + 4 * sizeof(BucketItem) + 2 * 4 + 8;   // generous
     return big + nodes * (sizeof(NodeDesc) + 64 + 4 * per_m) + (S / sq + nodes) * per_m * 2 +
            S / 8 + 32 * 256;
 }
@@ -329,6 +336,10 @@ template <class K, bool HV> struct Engine {
         b.list[CLS_INTERNAL] = ws.take<BucketItem>(capInt);
         b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID] = capMid;
         b.cap[CLS_BIG] = capBig; b.cap[CLS_INTERNAL] = capInt;
+        for (int c = 0; c < NCLS; ++c) b.order[c] = nullptr;
+        uint32_t *ordMid = ws.take<uint32_t>(capMid);
+        uint32_t *ordBig = cutoff > (uint32_t)SORT_CAP ? ws.take<uint32_t>(capBig) : nullptr;
+        b.order[CLS_MID] = ordMid; b.order[CLS_BIG] = ordBig;
         b.ctr = ws.take<uint32_t>(CTR_WORDS);
         b.nmin = ws.take<K>(N);
         b.alg1 = alg1 ? 1u : 0u;
@@ -415,6 +426,8 @@ template <class K, bool HV> struct Engine {
 
         // ---- buckets A -> D, by class
         launch("k_classify", bucS[N], [&] { k_classify<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b, cutoff); });
+        launch("k_order_lists", bucS[N], [&] {
+            k_order_lists<K><<<2, 1024, 0, st>>>(b, ordMid, ordBig, shift_of(SORT_CAP), shift_of(cutoff)); });
         launch("k_bucket_copy", keysTot, [&] { k_bucket_copy<K, HV><<<512, 256, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket_w", keysTot, [&] {
             k_bucket_small<K, HV><<<std::min<uint32_t>(cdiv(capSmall, SM_NW), 2048), SM_NW * WAVE, 0, st>>>(b, A, VA, D, VD); });
@@ -527,6 +540,9 @@ template <class K, bool HV> struct Engine {
                       std::vector<BucketItem> (&lists)[NCLS])
     {
         Batch<K> b{};
+        for (int c = CLS_MID; c <= CLS_BIG; ++c)      // largest first, as k_order_lists orders device lists
+            std::stable_sort(lists[c].begin(), lists[c].end(),
+                             [](const BucketItem &x, const BucketItem &y) { return x.size > y.size; });
         NodeDesc *dDesc = ws.take<NodeDesc>(pn.size());
         for (int c = CLS_SMALL; c <= CLS_BIG; ++c) {
             b.list[c] = ws.take<BucketItem>(std::max<size_t>(lists[c].size(), 1));
