@@ -53,7 +53,8 @@ struct NodeDesc {
     uint64_t src;      // first slot of the column/bucket-block offsets ((nJ+1)*m)
     uint64_t blk;      // first slot of the group/bucket counts (groups*m)
     uint32_t flags;    // NODE_COLS_RECURSED: columns > cut-off come sorted in D
-    uint32_t pad;
+    uint32_t sub;      // work-groups per column group (a power of two <= TG): each takes TG/sub
+                       // columns; with sub > 1 they add their bucket counts into the group's
 };
 constexpr uint32_t NODE_COLS_RECURSED = 1u;
 // m > SORT_CAP: a column does not fit one LDS sort.  Its columns are sorted
@@ -102,6 +103,7 @@ template <class K> struct Batch {
     uint32_t *ctr;      // NCLS list sizes, NCLS take counters (work-groups claim items), NCLS key totals, fail flag
     K *nmin;            // per node: smallest key of its input (Alg. 1 pivot rule)
     uint32_t alg1;      // 1: Alg. 1 pivot rule (distinct, above the minimum, resampled; [ ) buckets)
+    uint32_t bigInD;    // 1: the big-list items start in D (else in A)
     unsigned long long *H;
 };
 
@@ -334,10 +336,12 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
     __shared__ SortSm sm;
     const uint32_t bi = find_node(b.bigGrp, b.NB, blockIdx.x);
     const NodeDesc nd = b.nodes[b.bigIdx[bi]];
-    const uint32_t g = blockIdx.x - b.bigGrp[bi];
+    const uint32_t wi = blockIdx.x - b.bigGrp[bi];
+    const uint32_t S = nd.sub, g = wi / S, cps = TG / S;
     const uint32_t m = nd.m, n = nd.n, npiv = m - 1;
-    const uint32_t i0 = g * TG;
-    const uint32_t ncol = min((uint32_t)TG, m - i0);
+    const uint32_t i0 = g * TG + (wi % S) * cps;
+    if (i0 >= m) return;                                 // a sub-group past the last column
+    const uint32_t ncol = min(cps, m - i0);
     const bool recursed = nd.flags & NODE_COLS_RECURSED;
     static_assert(PIV_ALIGN * SORT_NT >= SORT_CAP, "one pivot slice per thread covers a node");
     constexpr int PPT = PIV_ALIGN;                       // pivots t0 .. t0 + PPT - 1 of this thread
@@ -468,8 +472,16 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
     }
     __syncthreads();
     uint32_t *blk = b.blk + nd.blk + (uint64_t)g * m;
-    for (uint32_t t = threadIdx.x; t < npiv; t += SORT_NT) blk[t] = Pl[t] - (t > 0 ? Pl[t - 1] : 0u);
-    if (threadIdx.x == 0) blk[m - 1] = total - (npiv > 0 ? Pl[npiv - 1] : 0u);
+    if (S == 1) {
+        for (uint32_t t = threadIdx.x; t < npiv; t += SORT_NT) blk[t] = Pl[t] - (t > 0 ? Pl[t - 1] : 0u);
+        if (threadIdx.x == 0) blk[m - 1] = total - (npiv > 0 ? Pl[npiv - 1] : 0u);
+    } else {                                             // the group's counts start at zero
+        for (uint32_t t = threadIdx.x; t < npiv; t += SORT_NT) {
+            const uint32_t c = Pl[t] - (t > 0 ? Pl[t - 1] : 0u);
+            if (c) atomicAdd(&blk[t], c);
+        }
+        if (threadIdx.x == 0) atomicAdd(&blk[m - 1], total - (npiv > 0 ? Pl[npiv - 1] : 0u));
+    }
 }
 
 // Nodes with m <= WCAP: one work-group of SM_NW waves per (node, column
@@ -487,9 +499,12 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
     __shared__ uint32_t hist[WCAP];
     const uint32_t si = find_node(b.smlGrp, b.NS, blockIdx.x);
     const NodeDesc nd = b.nodes[b.smlIdx[si]];
-    const uint32_t g = blockIdx.x - b.smlGrp[si];
+    const uint32_t wi = blockIdx.x - b.smlGrp[si];
+    const uint32_t S = nd.sub, g = wi / S, cps = TG / S;
     const uint32_t m = nd.m, n = nd.n, npiv = m - 1, nJ = nd.nJ;
-    const uint32_t i0 = g * TG, ncol = min((uint32_t)TG, m - i0);
+    const uint32_t i0 = g * TG + (wi % S) * cps;
+    if (i0 >= m) return;                                 // a sub-group past the last column
+    const uint32_t ncol = min(cps, m - i0);
     const bool recursed = nd.flags & NODE_COLS_RECURSED;
     const uint32_t w = wave_id(), l = lane_id();
 
@@ -556,7 +571,11 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
     }
     __syncthreads();
     uint32_t *blk = b.blk + nd.blk + (uint64_t)g * m;
-    for (uint32_t t = threadIdx.x; t < m; t += SM_NW * WAVE) blk[t] = hist[t];
+    if (S == 1)
+        for (uint32_t t = threadIdx.x; t < m; t += SM_NW * WAVE) blk[t] = hist[t];
+    else                                                 // the group's counts start at zero
+        for (uint32_t t = threadIdx.x; t < m; t += SM_NW * WAVE)
+            if (hist[t]) atomicAdd(&blk[t], hist[t]);
 }
 
 // Per node and bucket j: exclusive prefix of the group counts over groups
@@ -1189,7 +1208,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
         if (tid == 0) {
             K lo, hi;
             bucket_bounds(b, nd, e.j, lo, hi);
-            stack[0] = BigSeg{0u, e.size, 0u, 0u, (uint64_t)lo, (uint64_t)hi};
+            stack[0] = BigSeg{0u, e.size, b.bigInD, 0u, (uint64_t)lo, (uint64_t)hi};
             sp_sh = 1;
             overflow_sh = 0;
         }
@@ -1360,6 +1379,236 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
             if (overflow_sh) break;      // cannot happen: a split of s <= 4 bits adds 2^s - 1 <= 3.75 s entries, s summed over the depth <= key bits
         }
         __syncthreads();
+    }
+}
+
+// ---- A whole array that is a base case larger than one LDS sort, on the
+// whole grid.  One MSD split by the top 8 bits of x - min runs over all
+// work-groups (chunk ranges, per-chunk digit counts, one scan, a stable
+// scatter into D); the parts are then items of the MSD-split kernel, which
+// reads them from D.  A pseudo node with one bucket per part carries the part
+// bounds as strict pivots: its bucket j holds min + j*2^shift ..
+// min + (j+1)*2^shift - 1 (the first and last buckets open towards 0 and
+// the largest key of the type).
+constexpr int BS_NW = 4;
+constexpr int BS_IPT = 16;
+constexpr int BS_NT = BS_NW * WAVE;
+constexpr uint32_t BS_CH = BS_NT * BS_IPT;          // 4096 keys a chunk
+constexpr uint32_t BS_MAXG = BIG_CAP / BS_CH;       // chunks of the largest base case
+static_assert(BS_MAXG <= (uint32_t)WAVE, "one lane per chunk in split_range");
+using BsSm = SortSmem<BS_NW, BS_IPT>;
+
+template <class K> struct BaseSplit {
+    K *mm;               // [g][2]: smallest and largest key of chunk g
+    uint32_t *cnt;       // [d][g]: keys of chunk g with digit d; after the scan their first slot
+    NodeDesc *node;      // the pseudo node
+    K *piv;              // its pivots (255 slots)
+    uint8_t *strict;
+    BucketItem *items;   // its non-empty parts, largest first (<= 256)
+    uint32_t *ctr;       // the counters of the part sort
+    uint32_t n, G;
+};
+
+// smallest key of the array and the split shift (all threads)
+template <class K>
+__device__ inline void split_range(const BaseSplit<K> &s, K &lo, K &hi, int &shift, K *sh)
+{
+    using T = KeyT<K>;
+    if (threadIdx.x < WAVE) {
+        const uint32_t l = lane_id();
+        K a = l < s.G ? s.mm[2 * l] : (K)T::MAXV;
+        K c = l < s.G ? s.mm[2 * l + 1] : (K)0;
+        a = wave_min(a);
+        c = wave_max(c);
+        if (l == 0) { sh[0] = a; sh[1] = c; }
+    }
+    __syncthreads();
+    lo = sh[0];
+    hi = sh[1];
+    const int bits = T::bitlen((K)(hi - lo));
+    shift = bits > 8 ? bits - 8 : 0;
+}
+
+template <class K>
+__global__ __launch_bounds__(BS_NT) void k_base_range(const K *A, BaseSplit<K> s)
+{
+    using T = KeyT<K>;
+    __shared__ uint32_t red32[2 * BS_NW];
+    __shared__ unsigned long long red64[2 * BS_NW];
+    const uint32_t g = blockIdx.x;
+    K lo = (K)T::MAXV, hi = (K)0;
+    for (uint32_t i = 0; i < (uint32_t)BS_IPT; ++i) {
+        const uint32_t p = g * BS_CH + i * BS_NT + threadIdx.x;
+        if (p < s.n) { const K x = A[p]; lo = x < lo ? x : lo; hi = x > hi ? x : hi; }
+    }
+    block_minmax<K, BS_NW>(lo, hi, red32, red64);
+    if (threadIdx.x == 0) { s.mm[2 * g] = lo; s.mm[2 * g + 1] = hi; }
+}
+
+template <class K>
+__global__ __launch_bounds__(BS_NT) void k_base_count(const K *A, BaseSplit<K> s)
+{
+    __shared__ uint32_t h[BS_NW][256];
+    __shared__ K sh[2];
+    const uint32_t g = blockIdx.x, tid = threadIdx.x;
+    K lo, hi;
+    int shift;
+    split_range(s, lo, hi, shift, sh);
+    for (uint32_t i = tid; i < BS_NW * 256; i += BS_NT) (&h[0][0])[i] = 0;
+    __syncthreads();
+    uint32_t *wh = h[wave_id()];
+    for (uint32_t i = 0; i < (uint32_t)BS_IPT; ++i) {
+        const uint32_t p = g * BS_CH + i * BS_NT + tid;
+        if (p < s.n) atomicAdd(&wh[(uint32_t)((K)(A[p] - lo) >> shift)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t d = tid; d < 256; d += BS_NT) {
+        uint32_t c = 0;
+        for (int w = 0; w < BS_NW; ++w) c += h[w][d];
+        s.cnt[d * s.G + g] = c;
+    }
+}
+
+// One work-group: exclusive scan of the [d][g] counts (digit-major, so the
+// chunks of a digit follow each other: the scatter is stable), then the
+// pseudo node, its pivots, its parts (largest first) and the part-sort
+// counters.  With shift 0 every part holds one key value and is final after
+// the scatter: no items.
+template <class K>
+__global__ __launch_bounds__(1024) void k_base_scan(BaseSplit<K> s)
+{
+    __shared__ uint32_t v[256 * BS_MAXG];
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t sz[256], st0[256];
+    __shared__ K sh[2];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t E = 256 * s.G;
+    constexpr uint32_t PER = 256 * BS_MAXG / 1024;
+    K lo, hi;
+    int shift;
+    split_range(s, lo, hi, shift, sh);
+    uint32_t loc = 0;
+    for (uint32_t q = 0; q < PER; ++q) {
+        const uint32_t i = tid * PER + q;
+        const uint32_t c = i < E ? s.cnt[i] : 0u;
+        v[tid * PER + q] = c;
+        loc += c;
+    }
+    const uint32_t incl = wave_incl_scan(loc);
+    if (lane_id() == WAVE - 1) wsum[wave_id()] = incl;
+    __syncthreads();
+    uint32_t run = incl - loc;
+    for (uint32_t w = 0; w < wave_id(); ++w) run += wsum[w];
+    for (uint32_t q = 0; q < PER; ++q) {
+        const uint32_t i = tid * PER + q;
+        const uint32_t c = v[i];
+        v[i] = run;
+        if (i < E) s.cnt[i] = run;
+        run += c;
+    }
+    __syncthreads();
+    if (tid < 256) {
+        st0[tid] = v[tid * s.G];
+        sz[tid] = (tid < 255 ? v[(tid + 1) * s.G] : s.n) - v[tid * s.G];
+    }
+    __syncthreads();
+    uint32_t items = 0;
+    if (tid < 256) {
+        const uint32_t me = sz[tid];
+        uint32_t rank = 0;
+        for (uint32_t e = 0; e < 256; ++e) {
+            const uint32_t o = sz[e];
+            rank += (o > me || (o == me && e < tid)) ? 1u : 0u;
+            items += (shift > 0 && o > 0) ? 1u : 0u;
+        }
+        if (shift > 0 && me > 0) s.items[rank] = BucketItem{0u, tid, st0[tid], me};
+        if (shift > 0 && tid < 255) {
+            s.piv[tid] = (K)(lo + ((K)(tid + 1) << shift));
+            s.strict[tid] = 1;
+        }
+    }
+    if (tid < (uint32_t)CTR_WORDS)
+        s.ctr[tid] = tid == CLS_BIG ? items : tid == 2 * NCLS + CLS_BIG ? s.n : 0u;
+    if (tid == 0) {
+        NodeDesc nd{};
+        nd.n = s.n;
+        nd.m = shift > 0 ? (uint32_t)((K)(hi - lo) >> shift) + 1u : 1u;
+        *s.node = nd;
+    }
+}
+
+template <class K, bool HV>
+__global__ __launch_bounds__(BS_NT) void k_base_scatter(const K *A, const uint32_t *VA, K *D, uint32_t *VD,
+                                                        BaseSplit<K> s)
+{
+    using T = KeyT<K>;
+    __shared__ BsSm sm;
+    __shared__ uint32_t gb[256];
+    __shared__ K sh[2];
+    const uint32_t g = blockIdx.x, tid = threadIdx.x;
+    K lo, hi;
+    int shift;
+    split_range(s, lo, hi, shift, sh);
+    tables_clear<BS_NW, 256>(sm.s.tab);
+    for (uint32_t d = tid; d < 256; d += BS_NT) gb[d] = s.cnt[d * s.G + g];
+    __syncthreads();
+    const uint32_t c0 = g * BS_CH;
+    const uint32_t chN = min(BS_CH, s.n - c0);
+    const int nrows = wave_rows<BS_IPT>(chN);
+    RankTab<256> &tab = sm.s.tab[wave_id()];
+    K kk[BS_IPT];
+    uint32_t vv[BS_IPT], pos[BS_IPT];
+#pragma unroll
+    for (int r = 0; r < BS_IPT; ++r) {
+        if (r < nrows) {
+            const uint32_t p = item_pos<BS_NW, BS_IPT>(r);
+            kk[r] = p < chN ? A[c0 + p] : (K)0;
+            if (HV) vv[r] = p < chN ? VA[c0 + p] : 0u;
+            const uint32_t d = p < chN ? (uint32_t)((K)(kk[r] - lo) >> shift) : 255u;
+            pos[r] = rank_row(tab, d);
+        }
+    }
+    __syncthreads();
+    scan_tables<BS_NW, 256>(sm.s.tab, sm.wsum);
+#pragma unroll
+    for (int r = 0; r < BS_IPT; ++r) {
+        if (r < nrows) {
+            const uint32_t p = item_pos<BS_NW, BS_IPT>(r);
+            const uint32_t d = p < chN ? (uint32_t)((K)(kk[r] - lo) >> shift) : 255u;
+            pos[r] += tab.off[d];
+        }
+    }
+#pragma unroll
+    for (int wd = 0; wd < T::WORDS; ++wd) {
+#pragma unroll
+        for (int r = 0; r < BS_IPT; ++r)
+            if (r < nrows) sm.s.buf[pos[r]] = T::word(kk[r], wd);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < BS_IPT; ++r)
+            if (r < nrows) kk[r] = T::set_word(kk[r], wd, sm.s.buf[item_pos<BS_NW, BS_IPT>(r)]);
+        __syncthreads();
+    }
+    if (HV) {
+#pragma unroll
+        for (int r = 0; r < BS_IPT; ++r) if (r < nrows) sm.s.buf[pos[r]] = vv[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < BS_IPT; ++r) if (r < nrows) vv[r] = sm.s.buf[item_pos<BS_NW, BS_IPT>(r)];
+    }
+    // chunk-sorted position p holds a key of digit d: it goes to the chunk's
+    // first slot of d plus its place among the chunk's keys of d
+#pragma unroll
+    for (int r = 0; r < BS_IPT; ++r) {
+        if (r < nrows) {
+            const uint32_t p = item_pos<BS_NW, BS_IPT>(r);
+            if (p < chN) {
+                const uint32_t d = (uint32_t)((K)(kk[r] - lo) >> shift);
+                const uint32_t at = gb[d] + (p - sm.s.tab[0].off[d]);
+                D[at] = kk[r];
+                if (HV) VD[at] = vv[r];
+            }
+        }
     }
 }
 

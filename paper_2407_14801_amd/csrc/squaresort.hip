@@ -91,6 +91,17 @@ inline uint32_t shift_of(uint32_t cap)
     return bits > 8 ? bits - 8 : 0u;
 }
 
+// Work-groups per column group: the largest power of two <= cap that keeps
+// groups * sub <= target (at least 1).
+constexpr uint32_t COL_WG_BIG = 256;     // 16-wave column work-groups: one per CU
+constexpr uint32_t COL_WG_SML = 1024;    // 4-wave column work-groups: a few per CU
+inline uint32_t sub_groups(uint32_t groups, uint32_t target, uint32_t cap)
+{
+    uint32_t sub = 1;
+    while (groups && sub * 2 <= cap && (uint64_t)groups * sub * 2 <= target) sub *= 2;
+    return sub;
+}
+
 struct HostNode {
     uint64_t off;
     uint32_t n;
@@ -142,7 +153,13 @@ uint64_t workspace_bound(uint64_t n, uint64_t C, uint64_t key_bytes)
 {
     // n <= C needs no batch; the skew-transpose entry point still runs the
     // root step, so cover one node of n keys
-    if (n <= C) return node_meta_bytes(std::max<uint64_t>(n, 2), key_bytes) + (64 << 10);
+    if (n <= C) {
+        // a base case above one LDS sort: the grid-wide split's metadata
+        const uint64_t G = cdiv(n, BS_CH);
+        const uint64_t split = align_up(2 * G * key_bytes, 256) + align_up(256 * G * 4, 256) +
+                               256 * (key_bytes + 1 + sizeof(BucketItem)) + 4 * 256 + (8 << 10);
+        return std::max(node_meta_bytes(std::max<uint64_t>(n, 2), key_bytes) + (64 << 10), split);
+    }
     // nested batches: a chain of column recursions, each at most the size of n
     uint64_t chain = 1;
     for (uint64_t s = ceil_isqrt_host(n); s > C && chain < 8; s = ceil_isqrt_host(s)) ++chain;
@@ -248,7 +265,7 @@ template <class K, bool HV> struct Engine {
             d.src = srcTot;
             d.blk = blkTot;
             d.flags = 0;
-            d.pad = 0;
+            d.sub = 1;
             const bool huge = d.m > (uint32_t)SORT_CAP;
             if (huge) {
                 // columns do not fit one LDS sort: sorted into D first (the
@@ -300,6 +317,21 @@ template <class K, bool HV> struct Engine {
             blkTot += (uint64_t)d.groups * d.m;
         }
         const uint32_t NB = (uint32_t)bigIdx.size(), NS = (uint32_t)smlIdx.size();
+        // Few column groups (a mid-size root): split each group over several
+        // work-groups so that the column kernels fill the chip; they then add
+        // their bucket counts into the group's (cleared below).
+        const uint32_t subBig = sub_groups(bigGrp.back(), COL_WG_BIG, TG);
+        const uint32_t subSml = sub_groups(smlGrp.back(), COL_WG_SML, TG / SM_NW);
+        if (subBig > 1)
+            for (uint32_t q = 0; q < NB; ++q) {
+                desc[bigIdx[q]].sub = subBig;
+                bigGrp[q + 1] = bigGrp[q] + desc[bigIdx[q]].groups * subBig;
+            }
+        if (subSml > 1)
+            for (uint32_t q = 0; q < NS; ++q) {
+                desc[smlIdx[q]].sub = subSml;
+                smlGrp[q + 1] = smlGrp[q] + desc[smlIdx[q]].groups * subSml;
+            }
         std::vector<uint32_t> idx;
         idx.reserve(pfx.size() + 2 * N + 2);
         idx.insert(idx.end(), pfx.begin(), pfx.end());
@@ -337,6 +369,7 @@ template <class K, bool HV> struct Engine {
         b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID] = capMid;
         b.cap[CLS_BIG] = capBig; b.cap[CLS_INTERNAL] = capInt;
         for (int c = 0; c < NCLS; ++c) b.order[c] = nullptr;
+        b.bigInD = 0;
         uint32_t *ordMid = ws.take<uint32_t>(capMid);
         uint32_t *ordBig = cutoff > (uint32_t)SORT_CAP ? ws.take<uint32_t>(capBig) : nullptr;
         b.order[CLS_MID] = ordMid; b.order[CLS_BIG] = ordBig;
@@ -362,6 +395,7 @@ template <class K, bool HV> struct Engine {
         // ---- pivots (drawn from the node inputs before any child clobbers them)
         // counters (list sizes, take counters, key totals, the pivot-rule flag)
         k_fill_u32<<<1, 64, 0, st>>>(b.ctr, CTR_WORDS, 0u);
+        if ((subBig > 1 || subSml > 1) && blkTot) k_fill_u32<<<cdiv(blkTot, 256), 256, 0, st>>>(b.blk, blkTot, 0u);
         if (alg1) {                                   // node minima for the Alg. 1 pivot rule
             if (sizeof(K) == 4) k_fill_u32<<<cdiv(N, 256), 256, 0, st>>>(reinterpret_cast<uint32_t *>(b.nmin), N, 0xFFFFFFFFu);
             else k_fill_u64<<<cdiv(N, 256), 256, 0, st>>>(reinterpret_cast<unsigned long long *>(b.nmin), N, ~0ull);
@@ -484,38 +518,41 @@ template <class K, bool HV> struct Engine {
         return SQS_OK;
     }
 
-    // A whole array that is a base case larger than one LDS sort: the
-    // large-bucket kernel on a one-item work list (one node, one bucket
-    // whose bounds are the whole key range).
+    // A whole array that is a base case larger than one LDS sort: one MSD
+    // split over the whole grid (A -> D), then the parts as items of the
+    // large-bucket kernel, which reads them from D.  Nothing is uploaded from
+    // the host, so the call does not wait for the stream.
     int sort_big_base(uint64_t n)
     {
         const uint64_t mark = ws.top;
-        Batch<K> b{};
-        NodeDesc *dDesc = ws.take<NodeDesc>(1);
-        BucketItem *item = ws.take<BucketItem>(1);
-        uint32_t *ctr = ws.take<uint32_t>(CTR_WORDS);
+        BaseSplit<K> s;
+        s.n = (uint32_t)n;
+        s.G = cdiv(n, BS_CH);
+        s.mm = ws.take<K>(2 * s.G);
+        s.cnt = ws.take<uint32_t>(256 * s.G);
+        s.node = ws.take<NodeDesc>(1);
+        s.piv = ws.take<K>(256);
+        s.strict = ws.take<uint8_t>(256);
+        s.items = ws.take<BucketItem>(256);
+        s.ctr = ws.take<uint32_t>(CTR_WORDS);
+        ws.top = mark;                     // stream-ordered: later work on this stream may reuse it
         if (ws.overflow) return SQS_ERR_WORKSPACE;
-        host_node_ = NodeDesc{};
-        host_node_.n = (uint32_t)n;
-        host_node_.m = 1;
-        host_item_ = BucketItem{0u, 0u, 0u, (uint32_t)n};
-        for (int c = 0; c < CTR_WORDS; ++c) host_ctr_[c] = c == CLS_BIG ? 1u : 0u;
-        if (hipMemcpyAsync(dDesc, &host_node_, sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(item, &host_item_, sizeof(BucketItem), hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(ctr, host_ctr_, sizeof(host_ctr_), hipMemcpyHostToDevice, st) != hipSuccess)
-            return SQS_ERR_DEVICE;
-        b.nodes = dDesc; b.N = 1; b.ctr = ctr;
-        b.list[CLS_BIG] = item; b.cap[CLS_BIG] = 1;
-        launch("k_bucket_big", n, [&] { k_bucket_big<K, HV><<<1, BK_NT, 0, st>>>(b, A, VA, D, VD); });
-        if (int rc = check()) return rc;
-        if (hipStreamSynchronize(st) != hipSuccess) return SQS_ERR_DEVICE;   // host copies outlive the upload
-        resolve_timing();
-        ws.top = mark;
-        return SQS_OK;
+        if (s.G > BS_MAXG) return SQS_ERR_ARG;   // cannot happen: n <= cutoff <= BIG_CAP
+        Batch<K> b{};
+        b.nodes = s.node; b.N = 1;
+        b.piv = s.piv; b.strict = s.strict;
+        b.list[CLS_BIG] = s.items; b.cap[CLS_BIG] = 256;
+        b.ctr = s.ctr;
+        b.bigInD = 1;
+        launch("k_base_split", n, [&] {
+            k_base_range<K><<<s.G, BS_NT, 0, st>>>(A, s);
+            k_base_count<K><<<s.G, BS_NT, 0, st>>>(A, s);
+            k_base_scan<K><<<1, 1024, 0, st>>>(s);
+            k_base_scatter<K, HV><<<s.G, BS_NT, 0, st>>>(A, VA, D, VD, s); });
+        launch("k_bucket_big", n, [&] { k_bucket_big<K, HV><<<256, BK_NT, 0, st>>>(b, A, VA, D, VD); });
+        if (g_timing.on && hipStreamSynchronize(st) == hipSuccess) resolve_timing();
+        return check();
     }
-    NodeDesc host_node_{};
-    BucketItem host_item_{};
-    uint32_t host_ctr_[CTR_WORDS] = {};
 
     int sort_root(uint64_t n, uint64_t seed)
     {

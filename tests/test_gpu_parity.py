@@ -214,6 +214,56 @@ def test_kv_matches_oracle(b, ws, n, cutoff):
     assert dg == wdg
 
 
+# ------------------------------------------------------------------ whole-array base cases
+# A base case above one LDS sort is split once over the whole grid by the top
+# 8 bits of x - min: key spans of 8 bits (every part one value), 9 bits,
+# keys next to the largest value of the type, and a span of one value.
+def _span_keys(n, name, seed):
+    g = np.random.default_rng(seed)
+    top = 2**32 - 1
+    return {
+        "span8": g.integers(1000, 1256, size=n).astype(np.uint32),
+        "span9": g.integers(1000, 1512, size=n).astype(np.uint32),
+        "near_max": (top - g.integers(0, 1 << 20, size=n)).astype(np.uint32),
+        "max_and_near": np.where(g.random(n) < 0.3, top, top - g.integers(0, 300, size=n)).astype(np.uint32),
+        "one_value": np.full(n, top - 1, np.uint32),
+        "sparse_outlier": np.where(np.arange(n) == n // 2, top, g.integers(0, 1 << 12, size=n)).astype(np.uint32),
+    }[name]
+
+
+@pytest.mark.parametrize("n", [16_385, 150_001, 262_144])
+@pytest.mark.parametrize("name", ["span8", "span9", "near_max", "max_and_near", "one_value", "sparse_outlier"])
+def test_u32_base_split_ranges(b, ws, n, name):
+    _say(f"u32 base split {name} n={n}")
+    x = _span_keys(n, name, seed=n + 1)
+    got, used = gpu_u32(b, ws, x, seed=3, cutoff=0)
+    assert used >= n
+    assert np.array_equal(got, np.sort(x))
+
+
+@pytest.mark.parametrize("name", ["span8", "near_max", "one_value", "sparse_outlier"])
+def test_kv_base_split_stable(b, ws, name):
+    n = 200_001
+    _say(f"kv base split {name} n={n}")
+    k = _span_keys(n, name, seed=9).astype(np.uint64) << np.uint64(32)
+    v = np.arange(n, dtype=np.uint32)
+    ko, vo, used = gpu_kv(b, ws, k, v, seed=1, cutoff=0)
+    order = np.argsort(k, kind="stable")
+    assert np.array_equal(ko, k[order])
+    assert np.array_equal(vo, v[order])
+
+
+def test_u64_base_split_full_range(b, ws):
+    n = 250_000
+    _say(f"u64 base split full range n={n}")
+    x = datagen.uniform_u64(n, seed=17)
+    x[:100] = 2**64 - 1
+    x[100:200] = 0
+    got, used = gpu_u64(b, ws, x, seed=4, cutoff=0)
+    assert used >= n
+    assert np.array_equal(got, np.sort(x))
+
+
 # ------------------------------------------------------------------ determinism
 def test_repeat_runs_identical(b, ws):
     x = datagen.uniform_u32(2_000_003, seed=2)
