@@ -72,7 +72,12 @@ enum { CLS_COPY = 0, CLS_SMALL = 1, CLS_MID = 2, CLS_BIG = 3, CLS_INTERNAL = 4, 
 // device counters of a batch: NCLS list sizes, NCLS take counters, NCLS key
 // totals, then a flag set when the Alg. 1 pivot rule found no valid sample
 constexpr int CTR_FAIL = 3 * NCLS;
-constexpr int CTR_WORDS = 3 * NCLS + 1;
+// SkewTranspose chunks of heavy tiles: item count, take counter, and a flag
+// set when a chunk's wait for its predecessor ran past its bound
+constexpr int CTR_TR_ITEMS = 3 * NCLS + 1;
+constexpr int CTR_TR_TAKE = 3 * NCLS + 2;
+constexpr int CTR_TR_FAIL = 3 * NCLS + 3;
+constexpr int CTR_WORDS = 3 * NCLS + 4;
 // sample attempts of the Alg. 1 pivot rule before a node gives up
 constexpr uint32_t ALG1_ATTEMPTS = 64;
 constexpr uint32_t COPY_CH = 32768;           // keys per piece of a single-value bucket copy
@@ -104,6 +109,9 @@ template <class K> struct Batch {
     K *nmin;            // per node: smallest key of its input (Alg. 1 pivot rule)
     uint32_t alg1;      // 1: Alg. 1 pivot rule (distinct, above the minimum, resampled; [ ) buckets)
     uint32_t bigInD;    // 1: the big-list items start in D (else in A)
+    uint32_t *trItem;   // heavy transpose chunks: (tile, chunk) pairs, a tile's chunks adjacent
+    unsigned long long *trRec;   // per heavy chunk: TB words (status << 62 | value), see k_transpose
+    uint32_t trCap;
     unsigned long long *H;
 };
 
@@ -671,15 +679,85 @@ __device__ inline uint32_t tile_bucket(K x, K lo, int sh, const TileSmem<K> &sm)
     return a;
 }
 
-template <class K, bool HV>
-__global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K *src, const uint32_t *vsrc,
-                                                            K *dst, uint32_t *vdst)
+// Tiles with more than TR_HEAVY keys (presorted inputs put a column group's
+// keys into a few bucket blocks) are not processed by their own work-group:
+// each of their chunks is an item for the TR_EXTRA persistent work-groups of
+// k_transpose_heavy.  A chunk's destinations depend on the bucket counts of
+// the tile's earlier chunks; it publishes its own counts (aggregate), walks
+// back over its predecessors' records until one holds an inclusive prefix,
+// then publishes its inclusive prefix (decoupled look-back).  Items are taken
+// in ticket order, so every predecessor belongs to a running work-group that
+// publishes its aggregate before it waits: the walk always ends.  Record
+// words pack status and value, and are read and written as device-scope
+// atomics (coherent across the chip's L2 caches).
+constexpr uint32_t TR_HEAVY = 2 * TR_CH;
+constexpr uint32_t TR_EXTRA = 1024;
+constexpr unsigned long long TR_AGG = 1ull << 62, TR_INCL = 2ull << 62;
+constexpr uint32_t TR_SPIN = 1u << 16;       // bound of one wait (tens of ms: far above a chunk's time)
+constexpr uint32_t TR_SEQ = 0xFFFFFFFFu;     // item index of a tile processed whole by its work-group
+
+// Keys of every tile; the heavy ones become chunk items (records cleared).
+// One wave per tile.
+template <class K>
+__global__ __launch_bounds__(TR_NW * WAVE) void k_tile_plan(Batch<K> b, uint32_t tiles)
 {
-    __shared__ TileSmem<K> sm;
-    using T = KeyT<K>;
-    const uint32_t k = find_node(b.tileStart, b.N, blockIdx.x);
+    const uint32_t tile = blockIdx.x * TR_NW + wave_id();
+    if (tile >= tiles) return;
+    const uint32_t l = lane_id();
+    const uint32_t k = find_node(b.tileStart, b.N, tile);
     const NodeDesc nd = b.nodes[k];
-    const uint32_t tix = blockIdx.x - b.tileStart[k];
+    const uint32_t tix = tile - b.tileStart[k];
+    const uint32_t g = tix / nd.nJ, J = tix % nd.nJ, m = nd.m;
+    const uint32_t i0 = g * TG, ncol = min((uint32_t)TG, m - i0);
+    uint32_t len = 0;
+    if (l < ncol)
+        len = b.srcOff[nd.src + (uint64_t)(J + 1) * m + i0 + l] - b.srcOff[nd.src + (uint64_t)J * m + i0 + l];
+    const uint32_t N = __builtin_amdgcn_readlane(wave_incl_scan(len), WAVE - 1);
+    if (N <= TR_HEAVY) return;
+    const uint32_t nch = (N + TR_CH - 1) / TR_CH;
+    uint32_t s0 = 0;
+    if (l == 0) s0 = atomicAdd(&b.ctr[CTR_TR_ITEMS], nch);
+    s0 = __builtin_amdgcn_readfirstlane(s0);
+    if (s0 + nch > b.trCap) {                      // cannot happen: trCap bounds the chunks
+        if (l == 0) atomicOr(&b.ctr[CTR_TR_FAIL], 1u);
+        return;
+    }
+    for (uint32_t c = l; c < nch; c += WAVE) { b.trItem[2 * (s0 + c)] = tile; b.trItem[2 * (s0 + c) + 1] = c; }
+    for (uint32_t c = 0; c < nch; ++c) b.trRec[(uint64_t)(s0 + c) * TB + l] = 0ull;
+}
+
+// Keys of bucket d in the tile's chunks before this one, plus the bucket's
+// tile destination: walk back over the records of the earlier items.
+template <class K>
+__device__ inline uint32_t tr_lookback(const Batch<K> &b, uint32_t item, uint32_t d)
+{
+    uint32_t run = 0;
+    for (uint32_t p = item - 1;; --p) {
+        unsigned long long v;
+        uint32_t spins = 0;
+        while (((v = __hip_atomic_load(&b.trRec[(uint64_t)p * TB + d], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT)) >> 62) == 0) {
+            if (++spins > TR_SPIN) {                 // never expected: report instead of waiting on
+                atomicOr(&b.ctr[CTR_TR_FAIL], 1u);
+                return run;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        run += (uint32_t)v;
+        if ((v >> 62) == 2) return run;
+    }
+}
+
+// One tile (item == TR_SEQ: all its chunks in order, unless it is heavy) or
+// one chunk of a heavy tile (item: its index in the chunk list).
+template <class K, bool HV>
+__device__ void transpose_tile(const Batch<K> &b, const K *src, const uint32_t *vsrc, K *dst, uint32_t *vdst,
+                               TileSmem<K> &sm, uint32_t tile, uint32_t item, uint32_t chunk)
+{
+    using T = KeyT<K>;
+    const uint32_t k = find_node(b.tileStart, b.N, tile);
+    const NodeDesc nd = b.nodes[k];
+    const uint32_t tix = tile - b.tileStart[k];
     const uint32_t g = tix / nd.nJ, J = tix % nd.nJ;
     const uint32_t m = nd.m;
     const uint32_t i0 = g * TG, ncol = min((uint32_t)TG, m - i0);
@@ -688,7 +766,6 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
     const uint32_t tid = threadIdx.x;
     const uint32_t l = lane_id(), w = wave_id();
 
-    tables_clear<TR_NW, TB>(sm.tab);
     if (tid < WAVE) {                      // one wave builds the run table
         uint32_t a = 0, len = 0;
         if (tid < ncol) {
@@ -728,8 +805,13 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
     }
     const uint32_t N = sm.cOff[ncol];
     RankTab<TB> &tab = sm.tab[w];
+    const bool seq = item == TR_SEQ;
+    if (seq && N > TR_HEAVY) {             // its chunks are items of the persistent work-groups
+        __syncthreads();
+        return;
+    }
 
-    for (uint32_t q0 = 0; q0 < N; q0 += TR_CH) {
+    for (uint32_t q0 = seq ? 0u : chunk * TR_CH; q0 < (seq ? N : min(N, (chunk + 1) * TR_CH)); q0 += TR_CH) {
         const uint32_t chN = min((uint32_t)TR_CH, N - q0);
         const int nrows = wave_rows<TR_IPT>(chN);
         // column map of the chunk: wave w fills the runs of columns w, w + TR_NW, ...
@@ -760,14 +842,6 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
         }
         __syncthreads();
         scan_tables<TR_NW, TB>(sm.tab, sm.wsum);
-        // sorted chunk position p of bucket d goes to wbase[d] + p; positions
-        // past chN carry the padding digit TB - 1 and come last
-        if (tid < nb) {
-            const uint32_t s0 = min(sm.tab[0].off[tid], chN);
-            const uint32_t e0 = min(tid + 1 < TB ? sm.tab[0].off[tid + 1] : (uint32_t)TR_CH, chN);
-            sm.wbase[tid] = sm.dstb[tid] - s0;
-            sm.dstb[tid] += e0 - s0;
-        }
 #pragma unroll
         for (int r = 0; r < TR_IPT; ++r) if (r < nrows) pos[r] += tab.off[dig[r]];
 #pragma unroll
@@ -793,6 +867,32 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
             for (int r = 0; r < TR_IPT; ++r) if (r < nrows) vv[r] = sm.buf[item_pos<TR_NW, TR_IPT>(r)];
             __syncthreads();
         }
+        // sorted chunk position p of bucket d goes to wbase[d] + p; positions
+        // past chN carry the padding digit TB - 1 and come last
+        if (seq) {
+            if (tid < nb) {
+                const uint32_t s0 = min(sm.tab[0].off[tid], chN);
+                const uint32_t e0 = min(tid + 1 < TB ? sm.tab[0].off[tid + 1] : (uint32_t)TR_CH, chN);
+                sm.wbase[tid] = sm.dstb[tid] - s0;
+                sm.dstb[tid] += e0 - s0;
+            }
+        } else if (tid < WAVE) {            // wave 0, lane = bucket of the block
+            static_assert(TB == WAVE, "one lane per bucket of a tile");
+            const uint32_t d = tid;
+            const uint32_t s0 = d < nb ? min(sm.tab[0].off[d], chN) : 0u;
+            const uint32_t e0 = d < nb ? min(d + 1 < TB ? sm.tab[0].off[d + 1] : (uint32_t)TR_CH, chN) : 0u;
+            unsigned long long *rec = b.trRec + (uint64_t)item * TB + d;
+            uint32_t base;
+            if (chunk == 0) {
+                base = d < nb ? sm.dstb[d] : 0u;
+            } else {
+                __hip_atomic_store(rec, TR_AGG | (e0 - s0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                base = tr_lookback(b, item, d);
+            }
+            __hip_atomic_store(rec, TR_INCL | (uint32_t)(base + e0 - s0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (d < nb) sm.wbase[d] = base - s0;
+        }
+        __syncthreads();
 #pragma unroll
         for (int r = 0; r < TR_IPT; ++r) {
             if (r < nrows) {
@@ -807,6 +907,42 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K 
             }
         }
         __syncthreads();
+    }
+}
+
+// Every tile that is not heavy, whole, by its own work-group.
+template <class K, bool HV>
+__global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K *src, const uint32_t *vsrc,
+                                                            K *dst, uint32_t *vdst)
+{
+    __shared__ TileSmem<K> sm;
+    tables_clear<TR_NW, TB>(sm.tab);
+    transpose_tile<K, HV>(b, src, vsrc, dst, vdst, sm, blockIdx.x, TR_SEQ, 0u);
+}
+
+// The chunks of the heavy tiles, taken in ticket order by TR_EXTRA
+// persistent work-groups (after k_transpose).
+template <class K, bool HV>
+__global__ __launch_bounds__(TR_NW * WAVE) void k_transpose_heavy(Batch<K> b, const K *src, const uint32_t *vsrc,
+                                                                  K *dst, uint32_t *vdst, uint32_t tiles)
+{
+    __shared__ TileSmem<K> sm;
+    __shared__ uint32_t item_sh;
+    const uint32_t cnt = min(b.ctr[CTR_TR_ITEMS], b.trCap);
+    if (cnt == 0) return;
+    tables_clear<TR_NW, TB>(sm.tab);
+    while (true) {
+        if (threadIdx.x == 0) item_sh = atomicAdd(&b.ctr[CTR_TR_TAKE], 1u);
+        __syncthreads();
+        const uint32_t it = item_sh;
+        __syncthreads();
+        if (it >= cnt) break;
+        const uint32_t tile = b.trItem[2 * it];
+        if (tile >= tiles) {                       // cannot happen: k_tile_plan writes every item
+            if (threadIdx.x == 0) atomicOr(&b.ctr[CTR_TR_FAIL], 1u);
+            continue;
+        }
+        transpose_tile<K, HV>(b, src, vsrc, dst, vdst, sm, tile, it, b.trItem[2 * it + 1]);
     }
 }
 

@@ -130,6 +130,7 @@ uint64_t node_meta_bytes(uint64_t n, uint64_t key_bytes)
     const uint64_t groups = cdiv(m, TG), nJ = cdiv(m, TB);
     return sizeof(NodeDesc) + 7 * 4 + 8 + (m - 1 + PIV_ALIGN) * (key_bytes + 1) + 4 * m * (nJ + 1) +
            4 * groups * m + 4 * (m + 1) + 4 * m + 4 * sizeof(BucketItem) * m + 2 * 4 * m +
+           (3 * n / (2 * TR_CH) + 1) * (8 + 8 * TB) + 512 +
            sizeof(BucketItem) * (n / COPY_CH + 1) + 8;
 }
 
@@ -374,6 +375,11 @@ template <class K, bool HV> struct Engine {
         uint32_t *ordBig = cutoff > (uint32_t)SORT_CAP ? ws.take<uint32_t>(capBig) : nullptr;
         b.order[CLS_MID] = ordMid; b.order[CLS_BIG] = ordBig;
         b.ctr = ws.take<uint32_t>(CTR_WORDS);
+        // heavy-tile transpose chunks: a tile above TR_HEAVY = 2 chunks has fewer
+        // than 1.5 * keys / TR_CH chunks, so the sum over tiles is below that
+        b.trCap = (uint32_t)std::min<uint64_t>(0xFFFFFFFFull, 3 * keysTot / (2 * TR_CH) + 1);
+        b.trItem = ws.take<uint32_t>(2 * (uint64_t)b.trCap);
+        b.trRec = ws.take<unsigned long long>((uint64_t)b.trCap * TB);
         b.nmin = ws.take<K>(N);
         b.alg1 = alg1 ? 1u : 0u;
         b.H = ws.take<unsigned long long>(N);
@@ -442,15 +448,24 @@ template <class K, bool HV> struct Engine {
 
         // ---- SkewTranspose D -> A (skew mode: A -> out)
         if (skew_only) {
-            launch("k_transpose", keysTot, [&] { k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, A, VA, skew_out, nullptr); });
+            launch("k_transpose", keysTot, [&] {
+                k_tile_plan<K><<<cdiv(tileS[N], TR_NW), TR_NW * WAVE, 0, st>>>(b, tileS[N]);
+                k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, A, VA, skew_out, nullptr);
+                k_transpose_heavy<K, HV><<<TR_EXTRA, TR_NW * WAVE, 0, st>>>(b, A, VA, skew_out, nullptr, tileS[N]); });
             ws.top = mark;
             if (int rc = check()) return rc;
             // the host-side plan must outlive its upload
-            if (hipStreamSynchronize(st) != hipSuccess) return SQS_ERR_DEVICE;
+            uint32_t fail = 0;
+            if (hipMemcpyAsync(&fail, b.ctr + CTR_TR_FAIL, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return SQS_ERR_DEVICE;
             resolve_timing();
-            return SQS_OK;
+            return fail ? SQS_ERR_DEVICE : SQS_OK;
         }
-        launch("k_transpose", keysTot, [&] { k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, D, VD, A, VA); });
+        launch("k_transpose", keysTot, [&] {
+            k_tile_plan<K><<<cdiv(tileS[N], TR_NW), TR_NW * WAVE, 0, st>>>(b, tileS[N]);
+            k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, D, VD, A, VA);
+            k_transpose_heavy<K, HV><<<TR_EXTRA, TR_NW * WAVE, 0, st>>>(b, D, VD, A, VA, tileS[N]); });
         if (digest) {
             k_fill_u64<<<cdiv(N, 256), 256, 0, st>>>(b.H, N, 0ull);
             k_digest<K, HV><<<digS[N], 256, 0, st>>>(b, A, VA);
@@ -487,6 +502,7 @@ template <class K, bool HV> struct Engine {
         set_units("k_bucket_big", hctr[2 * NCLS + CLS_BIG]);
         resolve_timing();
         if (alg1 && hctr[CTR_FAIL]) return SQS_ERR_PRECOND;  // no valid Alg. 1 sample for some node
+        if (hctr[CTR_TR_FAIL]) return SQS_ERR_DEVICE;          // a transpose chunk's wait ran out
         for (int c = 0; c < NCLS; ++c)
             if (hctr[c] > b.cap[c]) return SQS_ERR_DEVICE;   // cannot happen: capacities are bounds
         if (debug_on()) {

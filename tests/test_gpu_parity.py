@@ -264,6 +264,62 @@ def test_u64_base_split_full_range(b, ws):
     assert np.array_equal(got, np.sort(x))
 
 
+# ------------------------------------------------------------------ presorted inputs
+# Presorted inputs put a column group's keys into a few bucket blocks: those
+# SkewTranspose tiles hold many chunks, which other work-groups take as items
+# whose destinations come from the tile's earlier chunks.  The intermediate
+# order is checked exactly (against the oracle, or through the digest).
+def _presorted(n, name, seed):
+    g = np.random.default_rng(seed)
+    u = np.sort(datagen.uniform_u32(n, seed=seed))
+    if name == "sorted":
+        return u
+    if name == "reversed":
+        return u[::-1].copy()
+    if name == "near_sorted":              # 1% of positions swapped in pairs
+        x = u.copy()
+        p = g.permutation(n)[: (n // 100) * 2].reshape(-1, 2)
+        x[p[:, 0]], x[p[:, 1]] = u[p[:, 1]], u[p[:, 0]]
+        return x
+    if name == "sawtooth":                 # 37 sorted runs
+        return np.concatenate([np.sort(a) for a in np.array_split(datagen.uniform_u32(n, seed=seed), 37)])
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["sorted", "reversed", "near_sorted", "sawtooth"])
+def test_skew_transpose_presorted(b, ws, name):
+    n = 2_100_001
+    _say(f"skew presorted {name} n={n}")
+    x = _presorted(n, name, seed=5)
+    got, bs = gpu_skew(b, ws, x, seed=3)
+    want, wbs = oracle.root_intermediate(x.astype(np.uint64), seed=3)
+    assert np.array_equal(bs, wbs)
+    assert np.array_equal(got.astype(np.uint64), want)
+
+
+@pytest.mark.parametrize("name", ["sorted", "near_sorted", "sawtooth"])
+def test_u32_presorted_digest(b, ws, name):
+    n = 4_000_037
+    _say(f"u32 presorted {name} n={n}")
+    x = _presorted(n, name, seed=6)
+    got, dg, used = gpu_u32(b, ws, x, seed=2, cutoff=0, digest=True)
+    assert np.array_equal(got, np.sort(x))
+    want, wdg, _ = oracle.squaresort_u32(x, 2, used, want_digest=True)
+    assert np.array_equal(got, want)
+    assert dg == wdg
+
+
+def test_kv_presorted_stable(b, ws):
+    n = 3_000_017
+    _say(f"kv presorted n={n}")
+    k = np.sort(datagen.uniform_u64(n, seed=8) >> np.uint64(40))     # sorted, with duplicates
+    v = np.arange(n, dtype=np.uint32)
+    ko, vo, dg, used = gpu_kv(b, ws, k, v, seed=1, cutoff=0, digest=True)
+    assert np.array_equal(ko, k) and np.array_equal(vo, v)
+    _, _, wdg, _ = oracle.squaresort_kv(k, v, 1, used, want_digest=True)
+    assert dg == wdg
+
+
 # ------------------------------------------------------------------ determinism
 def test_repeat_runs_identical(b, ws):
     x = datagen.uniform_u32(2_000_003, seed=2)
