@@ -33,6 +33,8 @@ constexpr int SORT_CAP = SORT_NT * SORT_IPT; // 16384 keys per block sort
 constexpr int WR = 16;                       // rows of a wave sort
 constexpr int WCAP = WR * WAVE;              // 1024 keys per wave sort
 constexpr int SM_NW = 4;                     // waves of the small-segment work-groups
+constexpr int M4_NW = 4;                     // waves of the mid4 bucket work-groups
+constexpr uint32_t M4_CAP = M4_NW * WAVE * SORT_IPT;  // 4096 keys per mid4 sort
 constexpr int TG = 64;                       // columns per column group
 constexpr int TB = 64;                       // buckets per bucket block
 constexpr int TR_NW = 4;                     // waves of the transpose work-group
@@ -68,7 +70,10 @@ constexpr uint32_t PIV_ALIGN = 16;
 struct BucketItem {
     uint32_t node, j, lo, size;   // lo: node-local first slot
 };
-enum { CLS_COPY = 0, CLS_SMALL = 1, CLS_MID = 2, CLS_BIG = 3, CLS_INTERNAL = 4, NCLS = 5 };
+// Bucket classes by size: copy (one key value), small (<= WCAP, a wave),
+// mid4 (<= M4_CAP, a 4-wave work-group), mid (<= SORT_CAP, a 16-wave
+// work-group), big (<= cut-off, MSD splits), internal (> cut-off).
+enum { CLS_COPY = 0, CLS_SMALL = 1, CLS_MID4 = 2, CLS_MID = 3, CLS_BIG = 4, CLS_INTERNAL = 5, NCLS = 6 };
 // device counters of a batch: NCLS list sizes, NCLS take counters, NCLS key
 // totals, then a flag set when the Alg. 1 pivot rule found no valid sample
 constexpr int CTR_FAIL = 3 * NCLS;
@@ -1125,6 +1130,7 @@ __global__ void k_classify(Batch<K> b, uint32_t cutoff)
             if (single_value_bucket(b, nd, j)) cls = CLS_COPY;
             else if (s > cutoff) cls = CLS_INTERNAL;
             else if (s <= (uint32_t)WCAP) cls = CLS_SMALL;
+            else if (s <= M4_CAP) cls = CLS_MID4;
             else if (s <= (uint32_t)SORT_CAP) cls = CLS_MID;
             else cls = CLS_BIG;
         }
@@ -1261,22 +1267,24 @@ __global__ __launch_bounds__(1024) void k_order_lists(Batch<K> b, uint32_t *ordM
         ord[atomicAdd(&at[255u - min((lst[i].size - 1u) >> shift, 255u)], 1u)] = i;
 }
 
-// Buckets of WCAP+1 .. cutoff keys: one work-group per bucket (persistent).
-template <class K, bool HV>
-__global__ __launch_bounds__(SORT_NT) void k_bucket_mid(Batch<K> b, const K *A, const uint32_t *VA,
-                                                        K *D, uint32_t *VD)
+// Buckets of one LDS sort: one work-group of NW waves per bucket
+// (persistent), of class CLS (mid4: 4 waves, up to M4_CAP keys, several
+// work-groups per CU; mid: 16 waves, up to SORT_CAP keys).
+template <class K, bool HV, int NW, int CLS>
+__global__ __launch_bounds__(NW * WAVE) void k_bucket_mid(Batch<K> b, const K *A, const uint32_t *VA,
+                                                          K *D, uint32_t *VD)
 {
-    __shared__ SortSm sm;
-    tables_clear<SORT_NW, 256>(sm.s.tab);
+    __shared__ SortSmem<NW, SORT_IPT> sm;
+    tables_clear<NW, 256>(sm.s.tab);
     __syncthreads();
     __shared__ uint32_t take_sh;
-    const uint32_t cnt = min(b.ctr[CLS_MID], b.cap[CLS_MID]);
-    for (uint32_t it = take_item(b.ctr, CLS_MID, &take_sh); it < cnt; it = take_item(b.ctr, CLS_MID, &take_sh)) {
-        const BucketItem e = b.list[CLS_MID][b.order[CLS_MID] ? b.order[CLS_MID][it] : it];
+    const uint32_t cnt = min(b.ctr[CLS], b.cap[CLS]);
+    for (uint32_t it = take_item(b.ctr, CLS, &take_sh); it < cnt; it = take_item(b.ctr, CLS, &take_sh)) {
+        const BucketItem e = b.list[CLS][b.order[CLS] ? b.order[CLS][it] : it];
         const uint64_t base = b.nodes[e.node].off + e.lo;
         K kk[SORT_IPT];
         uint32_t vv[SORT_IPT];
-        const int R = block_rows<SORT_NW, SORT_IPT>(e.size);
+        const int R = block_rows<NW, SORT_IPT>(e.size);
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
             const uint32_t p = bpos(r, R);
@@ -1285,7 +1293,7 @@ __global__ __launch_bounds__(SORT_NT) void k_bucket_mid(Batch<K> b, const K *A, 
         }
         K blo, bhi;
         bucket_bounds(b, b.nodes[e.node], e.j, blo, bhi);
-        block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, e.size, sm, true, blo, bhi);
+        block_sort<K, HV, NW, SORT_IPT>(kk, vv, e.size, sm, true, blo, bhi);
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
             const uint32_t p = bpos(r, R);

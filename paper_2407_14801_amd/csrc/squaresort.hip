@@ -102,6 +102,12 @@ inline uint32_t sub_groups(uint32_t groups, uint32_t target, uint32_t cap)
     return sub;
 }
 
+// base-case class of a segment of n > 0 keys (n <= cut-off)
+inline int size_class(uint64_t n)
+{
+    return n <= (uint64_t)WCAP ? CLS_SMALL : n <= M4_CAP ? CLS_MID4 : n <= (uint64_t)SORT_CAP ? CLS_MID : CLS_BIG;
+}
+
 struct HostNode {
     uint64_t off;
     uint32_t n;
@@ -129,7 +135,7 @@ uint64_t node_meta_bytes(uint64_t n, uint64_t key_bytes)
     const uint64_t m = ceil_isqrt_host(n);
     const uint64_t groups = cdiv(m, TG), nJ = cdiv(m, TB);
     return sizeof(NodeDesc) + 7 * 4 + 8 + (m - 1 + PIV_ALIGN) * (key_bytes + 1) + 4 * m * (nJ + 1) +
-           4 * groups * m + 4 * (m + 1) + 4 * m + 4 * sizeof(BucketItem) * m + 2 * 4 * m +
+           4 * groups * m + 4 * (m + 1) + 4 * m + 5 * sizeof(BucketItem) * m + 2 * 4 * m +
            (3 * n / (2 * TR_CH) + 1) * (8 + 8 * TB) + 512 +
            sizeof(BucketItem) * (n / COPY_CH + 1) + 8;
 }
@@ -145,7 +151,7 @@ uint64_t batch_bound(uint64_t S, uint64_t C, uint64_t key_bytes)
     const uint64_t big = node_meta_bytes(S, key_bytes);
     const uint64_t nodes = S / (C + 1) + 1;
     const uint64_t sq = ceil_isqrt_host(C + 1);
-    const uint64_t per_m = key_bytes + 1 + 4 * 2 + 4 + 4 + 4 + 4 * sizeof(BucketItem) + 2 * 4 + 8;   // generous
+    const uint64_t per_m = key_bytes + 1 + 4 * 2 + 4 + 4 + 4 + 5 * sizeof(BucketItem) + 2 * 4 + 8;   // generous
     return big + nodes * (sizeof(NodeDesc) + 64 + 4 * per_m) + (S / sq + nodes) * per_m * 2 +
            S / 8 + 32 * 256;
 }
@@ -292,7 +298,7 @@ template <class K, bool HV> struct Engine {
                     if (lo >= h.n) break;
                     const uint32_t len = (uint32_t)std::min<uint64_t>(d.m, h.n - lo);
                     if (len > cutoff) { col_kids.push_back({h.off + lo, len, node_child_key(h.key, 0, i)}); continue; }
-                    const int cls = len <= (uint32_t)WCAP ? CLS_SMALL : len <= (uint32_t)SORT_CAP ? CLS_MID : CLS_BIG;
+                    const int cls = size_class(len);
                     colLists[cls].push_back(BucketItem{cnode, 0u, (uint32_t)lo, len});
                 }
             } else if (!skew_only && d.m > cutoff) {
@@ -348,7 +354,8 @@ template <class K, bool HV> struct Engine {
         // mid buckets hold > WCAP keys and internal ones > cutoff keys
         const uint32_t capSmall = bucS[N];
         const uint32_t capCopy = (uint32_t)std::min<uint64_t>(0xFFFFFFFFull, bucS[N] + keysTot / COPY_CH + 1);
-        const uint32_t capMid = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (WCAP + 1) + 1);
+        const uint32_t capMid4 = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (WCAP + 1) + 1);
+        const uint32_t capMid = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (M4_CAP + 1) + 1);
         const uint32_t capBig = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (SORT_CAP + 1) + 1);
         const uint32_t capInt = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / ((uint64_t)cutoff + 1) + 1);
 
@@ -364,10 +371,11 @@ template <class K, bool HV> struct Engine {
         b.tot = ws.take<uint32_t>(bktTot);
         b.list[CLS_COPY] = ws.take<BucketItem>(capCopy);
         b.list[CLS_SMALL] = ws.take<BucketItem>(capSmall);
+        b.list[CLS_MID4] = ws.take<BucketItem>(capMid4);
         b.list[CLS_MID] = ws.take<BucketItem>(capMid);
         b.list[CLS_BIG] = ws.take<BucketItem>(capBig);
         b.list[CLS_INTERNAL] = ws.take<BucketItem>(capInt);
-        b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID] = capMid;
+        b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID4] = capMid4; b.cap[CLS_MID] = capMid;
         b.cap[CLS_BIG] = capBig; b.cap[CLS_INTERNAL] = capInt;
         for (int c = 0; c < NCLS; ++c) b.order[c] = nullptr;
         b.bigInD = 0;
@@ -480,8 +488,10 @@ template <class K, bool HV> struct Engine {
         launch("k_bucket_copy", keysTot, [&] { k_bucket_copy<K, HV><<<512, 256, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket_w", keysTot, [&] {
             k_bucket_small<K, HV><<<std::min<uint32_t>(cdiv(capSmall, SM_NW), 2048), SM_NW * WAVE, 0, st>>>(b, A, VA, D, VD); });
+        launch("k_bucket4", keysTot, [&] {
+            k_bucket_mid<K, HV, M4_NW, CLS_MID4><<<std::min<uint32_t>(capMid4, 2048), M4_NW * WAVE, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket", keysTot, [&] {
-            k_bucket_mid<K, HV><<<std::min<uint32_t>(capMid, 512), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
+            k_bucket_mid<K, HV, SORT_NW, CLS_MID><<<std::min<uint32_t>(capMid, 512), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
         if (cutoff > (uint32_t)SORT_CAP)
             launch("k_bucket_big", keysTot, [&] {
                 k_bucket_big<K, HV><<<std::min<uint32_t>(capBig, 512), BK_NT, 0, st>>>(b, A, VA, D, VD); });
@@ -498,6 +508,7 @@ template <class K, bool HV> struct Engine {
         // the bucket kernels processed the keys of their own class only
         set_units("k_bucket_copy", hctr[2 * NCLS + CLS_COPY]);
         set_units("k_bucket_w", hctr[2 * NCLS + CLS_SMALL]);
+        set_units("k_bucket4", hctr[2 * NCLS + CLS_MID4]);
         set_units("k_bucket", hctr[2 * NCLS + CLS_MID]);
         set_units("k_bucket_big", hctr[2 * NCLS + CLS_BIG]);
         resolve_timing();
@@ -593,7 +604,7 @@ template <class K, bool HV> struct Engine {
                       std::vector<BucketItem> (&lists)[NCLS])
     {
         Batch<K> b{};
-        for (int c = CLS_MID; c <= CLS_BIG; ++c)      // largest first, as k_order_lists orders device lists
+        for (int c = CLS_MID4; c <= CLS_BIG; ++c)     // largest first, as k_order_lists orders device lists
             std::stable_sort(lists[c].begin(), lists[c].end(),
                              [](const BucketItem &x, const BucketItem &y) { return x.size > y.size; });
         NodeDesc *dDesc = ws.take<NodeDesc>(pn.size());
@@ -624,9 +635,14 @@ template <class K, bool HV> struct Engine {
             launch("k_bucket_w", keys[CLS_SMALL], [&] {
                 k_bucket_small<K, HV2><<<std::min<uint32_t>(cdiv(b.cap[CLS_SMALL], SM_NW), 2048), SM_NW * WAVE, 0, st>>>(
                     b, sA, sVA, sD, sVD); });
+        if (!lists[CLS_MID4].empty())
+            launch("k_bucket4", keys[CLS_MID4], [&] {
+                k_bucket_mid<K, HV2, M4_NW, CLS_MID4><<<std::min<uint32_t>(b.cap[CLS_MID4], 2048), M4_NW * WAVE, 0, st>>>(
+                    b, sA, sVA, sD, sVD); });
         if (!lists[CLS_MID].empty())
             launch("k_bucket", keys[CLS_MID], [&] {
-                k_bucket_mid<K, HV2><<<std::min<uint32_t>(b.cap[CLS_MID], 512), SORT_NT, 0, st>>>(b, sA, sVA, sD, sVD); });
+                k_bucket_mid<K, HV2, SORT_NW, CLS_MID><<<std::min<uint32_t>(b.cap[CLS_MID], 512), SORT_NT, 0, st>>>(
+                    b, sA, sVA, sD, sVD); });
         if (!lists[CLS_BIG].empty())
             launch("k_bucket_big", keys[CLS_BIG], [&] {
                 k_bucket_big<K, HV2><<<std::min<uint32_t>(b.cap[CLS_BIG], 512), BK_NT, 0, st>>>(b, sA, sVA, sD, sVD); });
@@ -652,7 +668,7 @@ template <class K, bool HV> struct Engine {
             d.off = offs[i];
             d.n = (uint32_t)n;
             d.m = 1;
-            const int cls = n <= (uint64_t)WCAP ? CLS_SMALL : n <= (uint64_t)SORT_CAP ? CLS_MID : CLS_BIG;
+            const int cls = size_class(n);
             lists[cls].push_back(BucketItem{(uint32_t)leaf.size(), 0u, 0u, (uint32_t)n});
             leaf.push_back(d);
         }
@@ -677,7 +693,7 @@ uint64_t batched_workspace_bound(uint32_t count, const uint64_t *offs, uint64_t 
         const uint64_t n = offs[i + 1] - offs[i];
         if (n > C) { S += n; big = std::max(big, n); }
     }
-    const uint64_t leaves = (uint64_t)count * (sizeof(NodeDesc) + 3 * sizeof(BucketItem)) + 8 * 256;
+    const uint64_t leaves = (uint64_t)count * (sizeof(NodeDesc) + 4 * sizeof(BucketItem)) + 8 * 256;
     if (S == 0) return leaves;
     uint64_t chain = 1;
     for (uint64_t s = ceil_isqrt_host(big); s > C && chain < 8; s = ceil_isqrt_host(s)) ++chain;
