@@ -498,18 +498,20 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
 }
 
 // Nodes with m <= WCAP: one work-group of SM_NW waves per (node, column
-// group), one wave per column.  Every key finds its bucket by a binary search
-// over the node's pivots in LDS; the group's bucket counts are LDS atomic
-// adds (commutative, so the counts do not depend on order) and the column's
-// bucket-block offsets are read off where the bucket index crosses a block.
+// group), one wave per column.  After the wave sort the column is put in the
+// wave's LDS and every pivot finds its position in it (keys at or below it)
+// as in k_colsort_big: lane l owns pivots 16l .. 16l + 15 (in registers for
+// the whole group), searches its first and last over the column and the
+// others inside that bracket.  Summed over the group's columns the positions
+// give the group's bucket counts; every 64th gives a bucket-block offset.
 template <class K, bool HV>
 __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, const K *src, const uint32_t *vsrc,
                                                                  K *dst, uint32_t *vdst, uint32_t cutoff)
 {
+    static_assert(PIV_ALIGN * WAVE >= WCAP, "one pivot slice per lane covers a node");
     __shared__ WaveSmem<WR> wsm[SM_NW];
-    __shared__ K spiv[WCAP];
-    __shared__ uint8_t sst[WCAP];
-    __shared__ uint32_t hist[WCAP];
+    __shared__ uint32_t Pl[WCAP];
+    __shared__ uint32_t total_sh;
     const uint32_t si = find_node(b.smlGrp, b.NS, blockIdx.x);
     const NodeDesc nd = b.nodes[b.smlIdx[si]];
     const uint32_t wi = blockIdx.x - b.smlGrp[si];
@@ -520,21 +522,42 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
     const uint32_t ncol = min(cps, m - i0);
     const bool recursed = nd.flags & NODE_COLS_RECURSED;
     const uint32_t w = wave_id(), l = lane_id();
+    // the sorted column: the wave's exchange buffer (u32 keys), or its table
+    // and buffer together (u64 keys; the table is cleared again after)
+    static_assert(sizeof(RankTab<256>) + sizeof(uint32_t) * WR * WAVE >= sizeof(uint64_t) * WCAP, "column fits");
+    K *ck = sizeof(K) == 4 ? reinterpret_cast<K *>(wsm[w].buf) : reinterpret_cast<K *>(&wsm[w]);
 
-    for (uint32_t t = threadIdx.x; t < m; t += SM_NW * WAVE) {
-        if (t < npiv) { spiv[t] = b.piv[nd.piv + t]; sst[t] = b.strict[nd.piv + t]; }
-        hist[t] = 0;
-    }
+    for (uint32_t t = threadIdx.x; t < WCAP; t += SM_NW * WAVE) Pl[t] = 0;
+    if (threadIdx.x == 0) total_sh = 0;
     wave_table_clear(wsm[w].tab);
+    // this lane's pivots and strict flags (16-byte loads of its aligned, padded slice)
+    constexpr int PPT = PIV_ALIGN;
+    constexpr int PV4 = PPT * (int)sizeof(K) / 16;
+    const uint32_t t0 = l * PPT;
+    const uint32_t nq = t0 < npiv ? min((uint32_t)PPT, npiv - t0) : 0u;
+    uint4 praw[PV4];
+    uint4 sraw = make_uint4(0u, 0u, 0u, 0u);
+    if (nq > 0) {
+        const uint4 *p4 = reinterpret_cast<const uint4 *>(b.piv + nd.piv + t0);
+#pragma unroll
+        for (int v4 = 0; v4 < PV4; ++v4) praw[v4] = p4[v4];
+        sraw = *reinterpret_cast<const uint4 *>(b.strict + nd.piv + t0);
+    }
+    uint32_t P[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) P[q] = 0;
+    uint32_t total = 0;
     __syncthreads();
 
     for (uint32_t c = w; c < ncol; c += SM_NW) {
         const uint32_t i = i0 + c;
         const uint32_t len = __builtin_amdgcn_readfirstlane(column_len(i, m, n));
         uint32_t *so = b.srcOff + nd.src + i;              // so[J*m]
+        total += len;
         if (len == 0) {
             for (uint32_t J = l; J <= nJ; J += WAVE) so[(uint64_t)J * m] = 0;
-        } else {
+            continue;
+        }
         const bool sorted = recursed && len > cutoff;
         const uint64_t base = nd.off + (uint64_t)i * m;
         K kk[WR];
@@ -557,38 +580,85 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
                 }
             }
         }
-        // counting: bucket of every key; block offsets where the bucket crosses a block
-        const int nrows = (int)((len + WAVE - 1) / WAVE);
-        uint32_t carry = 0xFFFFFFFFu;                      // bucket of the previous row's last key
+        wave_lds_sync();
 #pragma unroll
         for (int r = 0; r < WR; ++r) {
-            if (r < nrows) {
-                const uint32_t p = r * WAVE + l;
-                const bool ok = p < len;
-                const uint32_t bk = ok ? bucket_search(kk[r], spiv, sst, npiv) : 0xFFFFFFFFu;
-                if (ok) atomicAdd(&hist[bk], 1u);
-                uint32_t bp = __shfl_up(bk, 1, WAVE);
-                if (l == 0) bp = carry;
-                carry = __shfl(bk, WAVE - 1, WAVE);
-                if (ok) {
-                    const uint32_t Ja = (p == 0) ? 1u : bp / TB + 1;
-                    const uint32_t Jb = min(bk / TB, nJ - 1);
-                    for (uint32_t J = Ja; J <= Jb; ++J) so[(uint64_t)J * m] = p;
-                    if (p == len - 1)
-                        for (uint32_t J = max(bk / TB + 1, 1u); J < nJ; ++J) so[(uint64_t)J * m] = len;
+            const uint32_t p = r * WAVE + l;
+            if (p < len) ck[p] = kk[r];
+        }
+        wave_lds_sync();
+        // positions of the lane's first and last pivot over the column, the
+        // others inside that bracket (independent searches step together)
+        if (nq > 0) {
+            K pf = (K)0, pl = (K)0;
+            bool sf = false, sl = false;
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                if (q == 0) { pf = piv_of<K>(praw, q); sf = strict_of(sraw, q); }
+                if (q == (int)nq - 1) { pl = piv_of<K>(praw, q); sl = strict_of(sraw, q); }
+            }
+            uint32_t af = 0, ef = len, al = 0, el = len;
+            while (af < ef || al < el) {
+                if (af < ef) {
+                    const uint32_t mid = (af + ef) >> 1;
+                    if (le_pivot(ck[mid], pf, sf)) af = mid + 1; else ef = mid;
+                }
+                if (al < el) {
+                    const uint32_t mid = (al + el) >> 1;
+                    if (le_pivot(ck[mid], pl, sl)) al = mid + 1; else el = mid;
+                }
+            }
+            uint32_t A[PPT], E[PPT];
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                const bool inner = q > 0 && q + 1 < (int)nq;
+                A[q] = inner ? af : 0u;
+                E[q] = inner ? al : 0u;
+            }
+            bool more = true;
+            while (more) {
+                more = false;
+#pragma unroll
+                for (int q = 1; q + 1 < PPT; ++q) {
+                    if (A[q] < E[q]) {
+                        const uint32_t mid = (A[q] + E[q]) >> 1;
+                        if (le_pivot(ck[mid], piv_of<K>(praw, q), strict_of(sraw, q))) A[q] = mid + 1;
+                        else E[q] = mid;
+                        more |= A[q] < E[q];
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                if (q < (int)nq) {
+                    const uint32_t t = t0 + q;
+                    const uint32_t a = q == 0 ? af : (q == (int)nq - 1 ? al : A[q]);
+                    P[q] += a;
+                    if ((t + 1) % TB == 0) so[(uint64_t)((t + 1) / TB) * m] = a;
                 }
             }
         }
         if (l == 0) { so[0] = 0; so[(uint64_t)nJ * m] = len; }
+        wave_lds_sync();
+        if (sizeof(K) == 8) {                            // the column overlaid the table
+            wave_table_clear(wsm[w].tab);
+            wave_lds_sync();
         }
     }
+    // per-bucket counts of the group from the summed positions
+#pragma unroll
+    for (int q = 0; q < PPT; ++q)
+        if (q < (int)nq && P[q]) atomicAdd(&Pl[t0 + q], P[q]);
+    if (l == 0 && total) atomicAdd(&total_sh, total);
     __syncthreads();
+    const uint32_t tot = total_sh;
     uint32_t *blk = b.blk + nd.blk + (uint64_t)g * m;
-    if (S == 1)
-        for (uint32_t t = threadIdx.x; t < m; t += SM_NW * WAVE) blk[t] = hist[t];
-    else                                                 // the group's counts start at zero
-        for (uint32_t t = threadIdx.x; t < m; t += SM_NW * WAVE)
-            if (hist[t]) atomicAdd(&blk[t], hist[t]);
+    for (uint32_t t = threadIdx.x; t < m; t += SM_NW * WAVE) {
+        const uint32_t hi = t < npiv ? Pl[t] : tot;
+        const uint32_t c = hi - (t > 0 ? Pl[t - 1] : 0u);
+        if (S == 1) blk[t] = c;
+        else if (c) atomicAdd(&blk[t], c);               // the group's counts start at zero
+    }
 }
 
 // Per node and bucket j: exclusive prefix of the group counts over groups
