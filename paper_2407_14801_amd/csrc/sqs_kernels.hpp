@@ -40,6 +40,7 @@ constexpr int TB = 64;                       // buckets per bucket block
 constexpr int TR_NW = 4;                     // waves of the transpose work-group
 constexpr int TR_IPT = 16;                   // keys per thread per chunk
 constexpr int TR_CH = TR_NW * WAVE * TR_IPT; // 4096 keys per transpose chunk
+constexpr int CL_NT = 1024;                  // threads of the classify work-group
 
 using SortSm = SortSmem<SORT_NW, SORT_IPT>;
 
@@ -1182,12 +1183,17 @@ __device__ inline bool single_value_bucket(const Batch<K> &b, const NodeDesc &nd
     return lo == hi;
 }
 
-// Classify every bucket and append it to its work list (wave-aggregated
-// atomics; list order does not affect any result).
+// Classify every bucket and append it to its work list.  Appends are
+// counted per wave (ballots), then per work-group in LDS, and take one global
+// atomic per class and work-group (list order does not affect any result).
 template <class K>
-__global__ void k_classify(Batch<K> b, uint32_t cutoff)
+__global__ __launch_bounds__(CL_NT) void k_classify(Batch<K> b, uint32_t cutoff)
 {
+    __shared__ uint32_t wgCnt[NCLS], wgBase[NCLS];
+    __shared__ unsigned long long wgKeys[NCLS];
     const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (threadIdx.x < NCLS) { wgCnt[threadIdx.x] = 0; wgKeys[threadIdx.x] = 0; }
+    __syncthreads();
     int cls = -1;
     BucketItem it{0, 0, 0, 0};
     if (item < b.bucStart[b.N]) {
@@ -1206,37 +1212,43 @@ __global__ void k_classify(Batch<K> b, uint32_t cutoff)
         }
     }
     const uint32_t l = lane_id();
-    {   // single-value buckets are copied in pieces of at most COPY_CH keys
-        const uint32_t pieces = cls == CLS_COPY ? (it.size + COPY_CH - 1) / COPY_CH : 0u;
-        const uint32_t incl = wave_incl_scan(pieces);
-        const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
-        if (total > 0) {
-            uint32_t base = 0;
-            if (l == 0) base = atomicAdd(&b.ctr[CLS_COPY], total);
-            base = __shfl(base, 0, WAVE);
-            for (uint32_t q = 0; q < pieces; ++q) {
-                const uint32_t at = base + incl - pieces + q;
-                const uint32_t off = q * COPY_CH;
-                if (at < b.cap[CLS_COPY])
-                    b.list[CLS_COPY][at] = BucketItem{it.node, it.j, it.lo + off, min(COPY_CH, it.size - off)};
-            }
+    // single-value buckets are copied in pieces of at most COPY_CH keys
+    const uint32_t pieces = cls == CLS_COPY ? (it.size + COPY_CH - 1) / COPY_CH : 0u;
+    const uint32_t pincl = wave_incl_scan(pieces);
+    const uint32_t ptot = __shfl(pincl, WAVE - 1, WAVE);
+    uint32_t woff[NCLS] = {};                             // this wave's first slot in the work-group's run
+    if (ptot > 0 && l == 0) woff[CLS_COPY] = atomicAdd(&wgCnt[CLS_COPY], ptot);
+    woff[CLS_COPY] = __shfl(woff[CLS_COPY], 0, WAVE);
+    unsigned long long mask[NCLS];
+#pragma unroll
+    for (int c = 0; c < NCLS; ++c) {
+        const unsigned long long ks = wave_sum_u64(cls == c ? it.size : 0u);   // keys per class (measurement)
+        if (ks && l == 0) atomicAdd(&wgKeys[c], ks);
+        mask[c] = __ballot(cls == c);
+        if (c == CLS_COPY) continue;
+        uint32_t o = 0;
+        if (mask[c] && l == 0) o = atomicAdd(&wgCnt[c], (uint32_t)__popcll(mask[c]));
+        woff[c] = __shfl(o, 0, WAVE);
+    }
+    __syncthreads();
+    if (threadIdx.x < NCLS) {
+        const uint32_t c = threadIdx.x;
+        wgBase[c] = wgCnt[c] ? atomicAdd(&b.ctr[c], wgCnt[c]) : 0u;
+        if (wgKeys[c]) atomicAdd(&b.ctr[2 * NCLS + c], (uint32_t)wgKeys[c]);
+    }
+    __syncthreads();
+    if (pieces > 0) {
+        const uint32_t at0 = wgBase[CLS_COPY] + woff[CLS_COPY] + pincl - pieces;
+        for (uint32_t q = 0; q < pieces; ++q) {
+            const uint32_t off = q * COPY_CH;
+            if (at0 + q < b.cap[CLS_COPY])
+                b.list[CLS_COPY][at0 + q] = BucketItem{it.node, it.j, it.lo + off, min(COPY_CH, it.size - off)};
         }
     }
 #pragma unroll
-    for (int c = 0; c < NCLS; ++c) {                 // keys per class (measurement)
-        const unsigned long long ks = wave_sum_u64(cls == c ? it.size : 0u);
-        if (ks && l == 0) atomicAdd(&b.ctr[2 * NCLS + c], (uint32_t)ks);
-    }
-#pragma unroll
     for (int c = 1; c < NCLS; ++c) {
-        const unsigned long long m = __ballot(cls == c);
-        if (m == 0) continue;
-        uint32_t base = 0;
-        const uint32_t leader = __ffsll((long long)m) - 1;
-        if (l == leader) base = atomicAdd(&b.ctr[c], (uint32_t)__popcll(m));
-        base = __shfl(base, leader, WAVE);
         if (cls == c) {
-            const uint32_t at = base + rank_in_mask((uint32_t)m, (uint32_t)(m >> 32));
+            const uint32_t at = wgBase[c] + woff[c] + rank_in_mask((uint32_t)mask[c], (uint32_t)(mask[c] >> 32));
             if (at < b.cap[c]) b.list[c][at] = it;
         }
     }

@@ -482,7 +482,7 @@ template <class K, bool HV> struct Engine {
         if (int rc = check()) return rc;
 
         // ---- buckets A -> D, by class
-        launch("k_classify", bucS[N], [&] { k_classify<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b, cutoff); });
+        launch("k_classify", bucS[N], [&] { k_classify<K><<<cdiv(bucS[N], CL_NT), CL_NT, 0, st>>>(b, cutoff); });
         launch("k_order_lists", bucS[N], [&] {
             k_order_lists<K><<<2, 1024, 0, st>>>(b, ordMid, ordBig, shift_of(SORT_CAP), shift_of(cutoff)); });
         launch("k_bucket_copy", keysTot, [&] { k_bucket_copy<K, HV><<<512, 256, 0, st>>>(b, A, VA, D, VD); });
