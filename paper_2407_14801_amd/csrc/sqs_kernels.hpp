@@ -1608,42 +1608,65 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
     }
 }
 
-// ---- A whole array that is a base case larger than one LDS sort, on the
-// whole grid.  One MSD split by the top 8 bits of x - min runs over all
-// work-groups (chunk ranges, per-chunk digit counts, one scan, a stable
-// scatter into D); the parts are then items of the MSD-split kernel, which
-// reads them from D.  A pseudo node with one bucket per part carries the part
-// bounds as strict pivots: its bucket j holds min + j*2^shift ..
-// min + (j+1)*2^shift - 1 (the first and last buckets open towards 0 and
-// the largest key of the type).
+// ---- Base-case segments larger than one LDS sort (a whole array, or the
+// instances of a batch when they are too few to fill the chip), on the whole
+// grid.  One MSD split of each segment by the top 8 bits of x - min runs over
+// all work-groups (chunk ranges, per-chunk digit counts, one scan per
+// segment, a stable scatter into D); the parts are then items of the
+// MSD-split kernel, which reads them from D.  A pseudo node per segment, with
+// one bucket per part, carries the part bounds as strict pivots: its bucket j
+// holds min + j*2^shift .. min + (j+1)*2^shift - 1 (the first and last
+// buckets open towards 0 and the largest key of the type).
 constexpr int BS_NW = 4;
 constexpr int BS_IPT = 16;
 constexpr int BS_NT = BS_NW * WAVE;
 constexpr uint32_t BS_CH = BS_NT * BS_IPT;          // 4096 keys a chunk
-constexpr uint32_t BS_MAXG = BIG_CAP / BS_CH;       // chunks of the largest base case
+constexpr uint32_t BS_MAXG = BIG_CAP / BS_CH;       // chunks of the largest segment
 static_assert(BS_MAXG <= (uint32_t)WAVE, "one lane per chunk in split_range");
 using BsSm = SortSmem<BS_NW, BS_IPT>;
 
 template <class K> struct BaseSplit {
-    K *mm;               // [g][2]: smallest and largest key of chunk g
-    uint32_t *cnt;       // [d][g]: keys of chunk g with digit d; after the scan their first slot
-    NodeDesc *node;      // the pseudo node
-    K *piv;              // its pivots (255 slots)
-    uint8_t *strict;
-    BucketItem *items;   // its non-empty parts, largest first (<= 256)
-    uint32_t *ctr;       // the counters of the part sort
-    uint32_t n, G;
+    K *mm;                    // [chunk][2]: smallest and largest key of the chunk
+    uint32_t *cnt;            // segment s at 256 * its first chunk: [d][g] keys of its chunk g with
+                              // digit d, after the scan their first slot in the segment
+    NodeDesc *node;           // per segment: the pseudo node
+    K *piv;                   // per segment: 256 slots (255 pivots)
+    uint8_t *strict;          // per segment: 256 slots
+    BucketItem *items;        // the parts of every segment (<= 256 each)
+    uint32_t *ctr;            // the counters of the part sort
+    const uint64_t *segOff;   // per segment: first slot in A and D (null: one segment at 0)
+    const uint32_t *segN;     // per segment: keys (<= BIG_CAP)
+    const uint32_t *segChunk; // nseg + 1: prefix of the segments' chunk counts
+    uint32_t nseg;
+    uint32_t n;               // the one segment's keys (segOff null)
+    uint32_t G;               // chunks of all segments
 };
 
-// smallest key of the array and the split shift (all threads)
+struct SegInfo {
+    uint64_t off;
+    uint32_t n, c0, G;        // keys, first chunk, chunks
+};
 template <class K>
-__device__ inline void split_range(const BaseSplit<K> &s, K &lo, K &hi, int &shift, K *sh)
+__device__ inline SegInfo seg_info(const BaseSplit<K> &s, uint32_t seg)
+{
+    if (!s.segOff) return SegInfo{0ull, s.n, 0u, s.G};
+    return SegInfo{s.segOff[seg], s.segN[seg], s.segChunk[seg], s.segChunk[seg + 1] - s.segChunk[seg]};
+}
+template <class K>
+__device__ inline uint32_t seg_of_chunk(const BaseSplit<K> &s, uint32_t chunk)
+{
+    return s.segOff ? find_node(s.segChunk, s.nseg, chunk) : 0u;
+}
+
+// smallest key of the segment and the split shift (all threads)
+template <class K>
+__device__ inline void split_range(const BaseSplit<K> &s, const SegInfo &si, K &lo, K &hi, int &shift, K *sh)
 {
     using T = KeyT<K>;
     if (threadIdx.x < WAVE) {
         const uint32_t l = lane_id();
-        K a = l < s.G ? s.mm[2 * l] : (K)T::MAXV;
-        K c = l < s.G ? s.mm[2 * l + 1] : (K)0;
+        K a = l < si.G ? s.mm[2 * (si.c0 + l)] : (K)T::MAXV;
+        K c = l < si.G ? s.mm[2 * (si.c0 + l) + 1] : (K)0;
         a = wave_min(a);
         c = wave_max(c);
         if (l == 0) { sh[0] = a; sh[1] = c; }
@@ -1661,14 +1684,18 @@ __global__ __launch_bounds__(BS_NT) void k_base_range(const K *A, BaseSplit<K> s
     using T = KeyT<K>;
     __shared__ uint32_t red32[2 * BS_NW];
     __shared__ unsigned long long red64[2 * BS_NW];
-    const uint32_t g = blockIdx.x;
+    const uint32_t chunk = blockIdx.x;
+    const SegInfo si = seg_info(s, seg_of_chunk(s, chunk));
+    const uint32_t g = chunk - si.c0;
+    if (chunk == 0)                                  // the scans add their parts into them
+        for (uint32_t t = threadIdx.x; t < (uint32_t)CTR_WORDS; t += BS_NT) s.ctr[t] = 0u;
     K lo = (K)T::MAXV, hi = (K)0;
     for (uint32_t i = 0; i < (uint32_t)BS_IPT; ++i) {
         const uint32_t p = g * BS_CH + i * BS_NT + threadIdx.x;
-        if (p < s.n) { const K x = A[p]; lo = x < lo ? x : lo; hi = x > hi ? x : hi; }
+        if (p < si.n) { const K x = A[si.off + p]; lo = x < lo ? x : lo; hi = x > hi ? x : hi; }
     }
     block_minmax<K, BS_NW>(lo, hi, red32, red64);
-    if (threadIdx.x == 0) { s.mm[2 * g] = lo; s.mm[2 * g + 1] = hi; }
+    if (threadIdx.x == 0) { s.mm[2 * chunk] = lo; s.mm[2 * chunk + 1] = hi; }
 }
 
 template <class K>
@@ -1676,48 +1703,54 @@ __global__ __launch_bounds__(BS_NT) void k_base_count(const K *A, BaseSplit<K> s
 {
     __shared__ uint32_t h[BS_NW][256];
     __shared__ K sh[2];
-    const uint32_t g = blockIdx.x, tid = threadIdx.x;
+    const uint32_t chunk = blockIdx.x, tid = threadIdx.x;
+    const SegInfo si = seg_info(s, seg_of_chunk(s, chunk));
+    const uint32_t g = chunk - si.c0;
     K lo, hi;
     int shift;
-    split_range(s, lo, hi, shift, sh);
+    split_range(s, si, lo, hi, shift, sh);
     for (uint32_t i = tid; i < BS_NW * 256; i += BS_NT) (&h[0][0])[i] = 0;
     __syncthreads();
     uint32_t *wh = h[wave_id()];
     for (uint32_t i = 0; i < (uint32_t)BS_IPT; ++i) {
         const uint32_t p = g * BS_CH + i * BS_NT + tid;
-        if (p < s.n) atomicAdd(&wh[(uint32_t)((K)(A[p] - lo) >> shift)], 1u);
+        if (p < si.n) atomicAdd(&wh[(uint32_t)((K)(A[si.off + p] - lo) >> shift)], 1u);
     }
     __syncthreads();
+    uint32_t *cnt = s.cnt + 256ull * si.c0;
     for (uint32_t d = tid; d < 256; d += BS_NT) {
         uint32_t c = 0;
         for (int w = 0; w < BS_NW; ++w) c += h[w][d];
-        s.cnt[d * s.G + g] = c;
+        cnt[d * si.G + g] = c;
     }
 }
 
-// One work-group: exclusive scan of the [d][g] counts (digit-major, so the
-// chunks of a digit follow each other: the scatter is stable), then the
-// pseudo node, its pivots, its parts (largest first) and the part-sort
-// counters.  With shift 0 every part holds one key value and is final after
-// the scatter: no items.
+// One work-group per segment: exclusive scan of its [d][g] counts
+// (digit-major, so the chunks of a digit follow each other: the scatter is
+// stable), then its pseudo node, pivots and parts (largest first, appended
+// to the part list).  With shift 0 every part holds one key value and is
+// final after the scatter: no items.
 template <class K>
 __global__ __launch_bounds__(1024) void k_base_scan(BaseSplit<K> s)
 {
     __shared__ uint32_t v[256 * BS_MAXG];
     __shared__ uint32_t wsum[16];
     __shared__ uint32_t sz[256], st0[256];
+    __shared__ uint32_t base_sh;
     __shared__ K sh[2];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t E = 256 * s.G;
+    const uint32_t seg = blockIdx.x, tid = threadIdx.x;
+    const SegInfo si = seg_info(s, seg);
+    const uint32_t E = 256 * si.G;
     constexpr uint32_t PER = 256 * BS_MAXG / 1024;
+    uint32_t *cnt = s.cnt + 256ull * si.c0;
     K lo, hi;
     int shift;
-    split_range(s, lo, hi, shift, sh);
+    split_range(s, si, lo, hi, shift, sh);
     uint32_t loc = 0;
     for (uint32_t q = 0; q < PER; ++q) {
         const uint32_t i = tid * PER + q;
-        const uint32_t c = i < E ? s.cnt[i] : 0u;
-        v[tid * PER + q] = c;
+        const uint32_t c = i < E ? cnt[i] : 0u;
+        v[i] = c;
         loc += c;
     }
     const uint32_t incl = wave_incl_scan(loc);
@@ -1729,37 +1762,41 @@ __global__ __launch_bounds__(1024) void k_base_scan(BaseSplit<K> s)
         const uint32_t i = tid * PER + q;
         const uint32_t c = v[i];
         v[i] = run;
-        if (i < E) s.cnt[i] = run;
+        if (i < E) cnt[i] = run;
         run += c;
     }
     __syncthreads();
     if (tid < 256) {
-        st0[tid] = v[tid * s.G];
-        sz[tid] = (tid < 255 ? v[(tid + 1) * s.G] : s.n) - v[tid * s.G];
+        st0[tid] = v[tid * si.G];
+        sz[tid] = (tid < 255 ? v[(tid + 1) * si.G] : si.n) - v[tid * si.G];
     }
     __syncthreads();
-    uint32_t items = 0;
+    uint32_t items = 0, rank = 0;
     if (tid < 256) {
         const uint32_t me = sz[tid];
-        uint32_t rank = 0;
         for (uint32_t e = 0; e < 256; ++e) {
             const uint32_t o = sz[e];
             rank += (o > me || (o == me && e < tid)) ? 1u : 0u;
             items += (shift > 0 && o > 0) ? 1u : 0u;
         }
-        if (shift > 0 && me > 0) s.items[rank] = BucketItem{0u, tid, st0[tid], me};
-        if (shift > 0 && tid < 255) {
-            s.piv[tid] = (K)(lo + ((K)(tid + 1) << shift));
-            s.strict[tid] = 1;
-        }
     }
-    if (tid < (uint32_t)CTR_WORDS)
-        s.ctr[tid] = tid == CLS_BIG ? items : tid == 2 * NCLS + CLS_BIG ? s.n : 0u;
     if (tid == 0) {
+        base_sh = items ? atomicAdd(&s.ctr[CLS_BIG], items) : 0u;
+        if (items) atomicAdd(&s.ctr[2 * NCLS + CLS_BIG], si.n);
         NodeDesc nd{};
-        nd.n = s.n;
+        nd.off = si.off;
+        nd.n = si.n;
         nd.m = shift > 0 ? (uint32_t)((K)(hi - lo) >> shift) + 1u : 1u;
-        *s.node = nd;
+        nd.piv = seg * 256;
+        s.node[seg] = nd;
+    }
+    __syncthreads();
+    if (tid < 256 && shift > 0) {
+        if (sz[tid] > 0) s.items[base_sh + rank] = BucketItem{seg, tid, st0[tid], sz[tid]};
+        if (tid < 255) {
+            s.piv[seg * 256 + tid] = (K)(lo + ((K)(tid + 1) << shift));
+            s.strict[seg * 256 + tid] = 1;
+        }
     }
 }
 
@@ -1771,15 +1808,20 @@ __global__ __launch_bounds__(BS_NT) void k_base_scatter(const K *A, const uint32
     __shared__ BsSm sm;
     __shared__ uint32_t gb[256];
     __shared__ K sh[2];
-    const uint32_t g = blockIdx.x, tid = threadIdx.x;
+    const uint32_t chunk = blockIdx.x, tid = threadIdx.x;
+    const SegInfo si = seg_info(s, seg_of_chunk(s, chunk));
+    const uint32_t g = chunk - si.c0;
     K lo, hi;
     int shift;
-    split_range(s, lo, hi, shift, sh);
+    split_range(s, si, lo, hi, shift, sh);
     tables_clear<BS_NW, 256>(sm.s.tab);
-    for (uint32_t d = tid; d < 256; d += BS_NT) gb[d] = s.cnt[d * s.G + g];
+    const uint32_t *cnt = s.cnt + 256ull * si.c0;
+    for (uint32_t d = tid; d < 256; d += BS_NT) gb[d] = cnt[d * si.G + g];
     __syncthreads();
     const uint32_t c0 = g * BS_CH;
-    const uint32_t chN = min(BS_CH, s.n - c0);
+    const uint32_t chN = min(BS_CH, si.n - c0);
+    const K *src = A + si.off;
+    const uint32_t *vsrc = HV ? VA + si.off : nullptr;
     const int nrows = wave_rows<BS_IPT>(chN);
     RankTab<256> &tab = sm.s.tab[wave_id()];
     K kk[BS_IPT];
@@ -1788,8 +1830,8 @@ __global__ __launch_bounds__(BS_NT) void k_base_scatter(const K *A, const uint32
     for (int r = 0; r < BS_IPT; ++r) {
         if (r < nrows) {
             const uint32_t p = item_pos<BS_NW, BS_IPT>(r);
-            kk[r] = p < chN ? A[c0 + p] : (K)0;
-            if (HV) vv[r] = p < chN ? VA[c0 + p] : 0u;
+            kk[r] = p < chN ? src[c0 + p] : (K)0;
+            if (HV) vv[r] = p < chN ? vsrc[c0 + p] : 0u;
             const uint32_t d = p < chN ? (uint32_t)((K)(kk[r] - lo) >> shift) : 255u;
             pos[r] = rank_row(tab, d);
         }
@@ -1824,6 +1866,8 @@ __global__ __launch_bounds__(BS_NT) void k_base_scatter(const K *A, const uint32
     }
     // chunk-sorted position p holds a key of digit d: it goes to the chunk's
     // first slot of d plus its place among the chunk's keys of d
+    K *dseg = D + si.off;
+    uint32_t *vdseg = HV ? VD + si.off : nullptr;
 #pragma unroll
     for (int r = 0; r < BS_IPT; ++r) {
         if (r < nrows) {
@@ -1831,8 +1875,8 @@ __global__ __launch_bounds__(BS_NT) void k_base_scatter(const K *A, const uint32
             if (p < chN) {
                 const uint32_t d = (uint32_t)((K)(kk[r] - lo) >> shift);
                 const uint32_t at = gb[d] + (p - sm.s.tab[0].off[d]);
-                D[at] = kk[r];
-                if (HV) VD[at] = vv[r];
+                dseg[at] = kk[r];
+                if (HV) vdseg[at] = vv[r];
             }
         }
     }

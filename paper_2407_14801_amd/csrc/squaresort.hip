@@ -102,6 +102,10 @@ inline uint32_t sub_groups(uint32_t groups, uint32_t target, uint32_t cap)
     return sub;
 }
 
+// A batch with at most this many base-case instances above one LDS sort
+// splits each over the grid (k_base_*) instead of giving each one work-group.
+constexpr size_t SPLIT_SEGS = 256;
+
 // base-case class of a segment of n > 0 keys (n <= cut-off)
 inline int size_class(uint64_t n)
 {
@@ -545,40 +549,50 @@ template <class K, bool HV> struct Engine {
         return SQS_OK;
     }
 
-    // A whole array that is a base case larger than one LDS sort: one MSD
-    // split over the whole grid (A -> D), then the parts as items of the
-    // large-bucket kernel, which reads them from D.  Nothing is uploaded from
-    // the host, so the call does not wait for the stream.
-    int sort_big_base(uint64_t n)
+    // Base-case segments larger than one LDS sort, on the whole grid: one MSD
+    // split of each (A -> D), then the parts as items of the large-bucket
+    // kernel, which reads them from D.  nseg == 1 with segOff null is a whole
+    // array at 0 of n keys (nothing uploaded, so the call does not wait for
+    // the stream); otherwise segOff / segN / segChunk are device arrays.
+    int split_segments(uint32_t nseg, uint32_t G, uint64_t n1, const uint64_t *segOff, const uint32_t *segN,
+                       const uint32_t *segChunk, uint64_t keys)
     {
         const uint64_t mark = ws.top;
         BaseSplit<K> s;
-        s.n = (uint32_t)n;
-        s.G = cdiv(n, BS_CH);
-        s.mm = ws.take<K>(2 * s.G);
-        s.cnt = ws.take<uint32_t>(256 * s.G);
-        s.node = ws.take<NodeDesc>(1);
-        s.piv = ws.take<K>(256);
-        s.strict = ws.take<uint8_t>(256);
-        s.items = ws.take<BucketItem>(256);
+        s.nseg = nseg;
+        s.n = (uint32_t)n1;
+        s.G = G;
+        s.segOff = segOff; s.segN = segN; s.segChunk = segChunk;
+        s.mm = ws.take<K>(2 * (uint64_t)G);
+        s.cnt = ws.take<uint32_t>(256 * (uint64_t)G);
+        s.node = ws.take<NodeDesc>(nseg);
+        s.piv = ws.take<K>(256 * (uint64_t)nseg);
+        s.strict = ws.take<uint8_t>(256 * (uint64_t)nseg);
+        s.items = ws.take<BucketItem>(256 * (uint64_t)nseg);
         s.ctr = ws.take<uint32_t>(CTR_WORDS);
         ws.top = mark;                     // stream-ordered: later work on this stream may reuse it
         if (ws.overflow) return SQS_ERR_WORKSPACE;
-        if (s.G > BS_MAXG) return SQS_ERR_ARG;   // cannot happen: n <= cutoff <= BIG_CAP
         Batch<K> b{};
-        b.nodes = s.node; b.N = 1;
+        b.nodes = s.node; b.N = nseg;
         b.piv = s.piv; b.strict = s.strict;
-        b.list[CLS_BIG] = s.items; b.cap[CLS_BIG] = 256;
+        b.list[CLS_BIG] = s.items; b.cap[CLS_BIG] = 256 * nseg;
         b.ctr = s.ctr;
         b.bigInD = 1;
-        launch("k_base_split", n, [&] {
-            k_base_range<K><<<s.G, BS_NT, 0, st>>>(A, s);
-            k_base_count<K><<<s.G, BS_NT, 0, st>>>(A, s);
-            k_base_scan<K><<<1, 1024, 0, st>>>(s);
-            k_base_scatter<K, HV><<<s.G, BS_NT, 0, st>>>(A, VA, D, VD, s); });
-        launch("k_bucket_big", n, [&] { k_bucket_big<K, HV><<<256, BK_NT, 0, st>>>(b, A, VA, D, VD); });
-        if (g_timing.on && hipStreamSynchronize(st) == hipSuccess) resolve_timing();
+        launch("k_base_split", keys, [&] {
+            k_base_range<K><<<G, BS_NT, 0, st>>>(A, s);
+            k_base_count<K><<<G, BS_NT, 0, st>>>(A, s);
+            k_base_scan<K><<<nseg, 1024, 0, st>>>(s);
+            k_base_scatter<K, HV><<<G, BS_NT, 0, st>>>(A, VA, D, VD, s); });
+        launch("k_bucket_big", keys, [&] {
+            k_bucket_big<K, HV><<<std::min<uint32_t>(256 * nseg, 512), BK_NT, 0, st>>>(b, A, VA, D, VD); });
         return check();
+    }
+    int sort_big_base(uint64_t n)
+    {
+        if (cdiv(n, BS_CH) > BS_MAXG) return SQS_ERR_ARG;   // cannot happen: n <= cutoff <= BIG_CAP
+        if (int rc = split_segments(1, cdiv(n, BS_CH), n, nullptr, nullptr, nullptr, n)) return rc;
+        if (g_timing.on && hipStreamSynchronize(st) == hipSuccess) resolve_timing();
+        return SQS_OK;
     }
 
     int sort_root(uint64_t n, uint64_t seed)
@@ -674,8 +688,39 @@ template <class K, bool HV> struct Engine {
         }
         if (!leaf.empty()) {
             const uint64_t mark = ws.top;
-            if (int rc = sort_segments<HV>(A, VA, D, VD, leaf, lists)) return rc;
+            // Too few large leaves to fill the chip with one work-group each:
+            // split each over the grid instead.
+            std::vector<BucketItem> big;
+            if (!lists[CLS_BIG].empty() && lists[CLS_BIG].size() <= SPLIT_SEGS) big.swap(lists[CLS_BIG]);
+            bool rest = false;
+            for (int c = 0; c < NCLS; ++c) rest |= !lists[c].empty();
+            if (rest)
+                if (int rc = sort_segments<HV>(A, VA, D, VD, leaf, lists)) return rc;
+            if (!big.empty()) {
+                const uint32_t ns = (uint32_t)big.size();
+                keep_.emplace_back(ns * 8 + ns * 4 + (ns + 1) * 4, 0);
+                char *hb = keep_.back().data();
+                uint64_t *hOff = reinterpret_cast<uint64_t *>(hb);
+                uint32_t *hN = reinterpret_cast<uint32_t *>(hb + ns * 8);
+                uint32_t *hCh = hN + ns;
+                uint64_t keys = 0;
+                hCh[0] = 0;
+                for (uint32_t q = 0; q < ns; ++q) {
+                    hOff[q] = leaf[big[q].node].off;
+                    hN[q] = big[q].size;
+                    hCh[q + 1] = hCh[q] + cdiv(big[q].size, BS_CH);
+                    keys += big[q].size;
+                }
+                char *dSeg = ws.take<char>(keep_.back().size());
+                if (ws.overflow) return SQS_ERR_WORKSPACE;
+                if (hipMemcpyAsync(dSeg, hb, keep_.back().size(), hipMemcpyHostToDevice, st) != hipSuccess)
+                    return SQS_ERR_DEVICE;
+                const uint64_t *dOff = reinterpret_cast<const uint64_t *>(dSeg);
+                const uint32_t *dN = reinterpret_cast<const uint32_t *>(dSeg + ns * 8);
+                if (int rc = split_segments(ns, hCh[ns], 0, dOff, dN, dN + ns, keys)) return rc;
+            }
             if (hipStreamSynchronize(st) != hipSuccess) return SQS_ERR_DEVICE;   // host lists outlive the uploads
+            keep_.clear();
             resolve_timing();
             ws.top = mark;
         }
@@ -688,12 +733,17 @@ template <class K, bool HV> struct Engine {
 // released) the shared first batch of the other instances and its recursion.
 uint64_t batched_workspace_bound(uint32_t count, const uint64_t *offs, uint64_t C, uint64_t key_bytes)
 {
-    uint64_t S = 0, big = 0;
+    uint64_t S = 0, big = 0, L = 0, nl = 0;
     for (uint32_t i = 0; i < count; ++i) {
         const uint64_t n = offs[i + 1] - offs[i];
         if (n > C) { S += n; big = std::max(big, n); }
+        else if (n > (uint64_t)SORT_CAP) { L += n; ++nl; }
     }
-    const uint64_t leaves = (uint64_t)count * (sizeof(NodeDesc) + 4 * sizeof(BucketItem)) + 8 * 256;
+    // leaf lists, plus the grid-wide split of the large leaves (chunk ranges
+    // and counts per 4096 keys; node, pivots, flags and parts per leaf)
+    const uint64_t split = (L / BS_CH + nl) * (2 * key_bytes + 256 * 4) +
+                           nl * (sizeof(NodeDesc) + 256 * (key_bytes + 1 + sizeof(BucketItem)) + 16) + (64 << 10);
+    const uint64_t leaves = (uint64_t)count * (sizeof(NodeDesc) + 4 * sizeof(BucketItem)) + 8 * 256 + split;
     if (S == 0) return leaves;
     uint64_t chain = 1;
     for (uint64_t s = ceil_isqrt_host(big); s > C && chain < 8; s = ceil_isqrt_host(s)) ++chain;
