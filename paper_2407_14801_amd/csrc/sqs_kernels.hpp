@@ -898,21 +898,26 @@ __device__ void transpose_tile(const Batch<K> &b, const K *src, const uint32_t *
         __syncthreads();
         K kk[TR_IPT];
         uint32_t vv[TR_IPT], dig[TR_IPT], pos[TR_IPT];
+        // all loads of the chunk first, so that they are in flight together
+#pragma unroll
+        for (int r = 0; r < TR_IPT; ++r) {
+            kk[r] = (K)0;
+            vv[r] = 0;
+            const uint32_t p = item_pos<TR_NW, TR_IPT>(r);
+            if (r < nrows && p < chN) {
+                const uint32_t c = sm.colOf[p];
+                const uint64_t rel = sm.relBase[c] + q0 + p;
+                const uint64_t at = nd.off + (rel < nd.n ? rel : 0);   // guard: inside the node
+                kk[r] = src[at];
+                if (HV) vv[r] = vsrc[at];
+            }
+        }
 #pragma unroll
         for (int r = 0; r < TR_IPT; ++r) {
             dig[r] = TB - 1;
             if (r < nrows) {
                 const uint32_t p = item_pos<TR_NW, TR_IPT>(r);
-                kk[r] = (K)0;
-                vv[r] = 0;
-                if (p < chN) {
-                    const uint32_t c = sm.colOf[p];
-                    const uint64_t rel = sm.relBase[c] + q0 + p;
-                    const uint64_t at = nd.off + (rel < nd.n ? rel : 0);   // guard: inside the node
-                    kk[r] = src[at];
-                    if (HV) vv[r] = vsrc[at];
-                    dig[r] = tile_bucket(kk[r], lo, sh, sm);
-                }
+                if (p < chN) dig[r] = tile_bucket(kk[r], lo, sh, sm);
                 pos[r] = rank_row(tab, dig[r]);
             }
         }
@@ -1277,9 +1282,10 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_bucket_small(Batch<K> b, const
 {
     __shared__ WaveSmem<WR> wsm[SM_NW];
     const uint32_t w = wave_id(), l = lane_id();
+    const uint32_t cnt = min(b.ctr[CLS_SMALL], b.cap[CLS_SMALL]);
+    if (blockIdx.x * SM_NW + w >= cnt) return;      // no item for this wave
     wave_table_clear(wsm[w].tab);
     wave_lds_sync();
-    const uint32_t cnt = min(b.ctr[CLS_SMALL], b.cap[CLS_SMALL]);
     for (uint32_t it = blockIdx.x * SM_NW + w; it < cnt; it += gridDim.x * SM_NW) {
         const BucketItem e = b.list[CLS_SMALL][it];
         const uint64_t base = b.nodes[e.node].off + e.lo;
@@ -1357,11 +1363,13 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_mid(Batch<K> b, const K *A
                                                           K *D, uint32_t *VD)
 {
     __shared__ SortSmem<NW, SORT_IPT> sm;
-    tables_clear<NW, 256>(sm.s.tab);
-    __syncthreads();
     __shared__ uint32_t take_sh;
     const uint32_t cnt = min(b.ctr[CLS], b.cap[CLS]);
-    for (uint32_t it = take_item(b.ctr, CLS, &take_sh); it < cnt; it = take_item(b.ctr, CLS, &take_sh)) {
+    uint32_t it = take_item(b.ctr, CLS, &take_sh);
+    if (it >= cnt) return;                           // no item left: skip the table clear
+    tables_clear<NW, 256>(sm.s.tab);
+    __syncthreads();
+    for (; it < cnt; it = take_item(b.ctr, CLS, &take_sh)) {
         const BucketItem e = b.list[CLS][b.order[CLS] ? b.order[CLS][it] : it];
         const uint64_t base = b.nodes[e.node].off + e.lo;
         K kk[SORT_IPT];
@@ -1502,8 +1510,18 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
             __syncthreads();
             {                                                            // count, per-wave histograms
                 uint32_t *wh = whist[wave_id()];
-                for (uint32_t p = tid; p < sg.size; p += BK_NT)
-                    atomicAdd(&wh[min((uint32_t)(((K)(src[sb + p] - klo)) >> shift), nparts - 1)], 1u);
+                for (uint32_t p0 = 0; p0 < sg.size; p0 += BK_CAP) {    // a chunk's loads in flight together
+                    K x[BK_IPT];
+#pragma unroll
+                    for (int r = 0; r < BK_IPT; ++r) {
+                        const uint32_t p = p0 + r * BK_NT + tid;
+                        x[r] = p < sg.size ? src[sb + p] : klo;
+                    }
+#pragma unroll
+                    for (int r = 0; r < BK_IPT; ++r)
+                        if (p0 + r * BK_NT + tid < sg.size)
+                            atomicAdd(&wh[min((uint32_t)(((K)(x[r] - klo)) >> shift), nparts - 1)], 1u);
+                }
             }
             __syncthreads();
             if (tid < nparts) {
@@ -1527,11 +1545,15 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                 K kk[BK_IPT];
                 uint32_t vv[BK_IPT], pos[BK_IPT];
 #pragma unroll
+                for (int r = 0; r < BK_IPT; ++r) {                      // loads first, in flight together
+                    const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
+                    kk[r] = r < nrows && p < chN ? src[sb + c0 + p] : (K)0;
+                    if (HV) vv[r] = r < nrows && p < chN ? vsrc[sb + c0 + p] : 0u;
+                }
+#pragma unroll
                 for (int r = 0; r < BK_IPT; ++r) {
                     if (r < nrows) {
                         const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
-                        kk[r] = p < chN ? src[sb + c0 + p] : (K)0;
-                        if (HV) vv[r] = p < chN ? vsrc[sb + c0 + p] : 0u;
                         const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
                         pos[r] = rank_row(tab, d);
                     }
@@ -1689,11 +1711,15 @@ __global__ __launch_bounds__(BS_NT) void k_base_range(const K *A, BaseSplit<K> s
     const uint32_t g = chunk - si.c0;
     if (chunk == 0)                                  // the scans add their parts into them
         for (uint32_t t = threadIdx.x; t < (uint32_t)CTR_WORDS; t += BS_NT) s.ctr[t] = 0u;
-    K lo = (K)T::MAXV, hi = (K)0;
-    for (uint32_t i = 0; i < (uint32_t)BS_IPT; ++i) {
+    K lo = (K)T::MAXV, hi = (K)0, x[BS_IPT];
+#pragma unroll
+    for (int i = 0; i < BS_IPT; ++i) {
         const uint32_t p = g * BS_CH + i * BS_NT + threadIdx.x;
-        if (p < si.n) { const K x = A[si.off + p]; lo = x < lo ? x : lo; hi = x > hi ? x : hi; }
+        x[i] = p < si.n ? A[si.off + p] : (K)0;
     }
+#pragma unroll
+    for (int i = 0; i < BS_IPT; ++i)
+        if (g * BS_CH + i * BS_NT + threadIdx.x < si.n) { lo = x[i] < lo ? x[i] : lo; hi = x[i] > hi ? x[i] : hi; }
     block_minmax<K, BS_NW>(lo, hi, red32, red64);
     if (threadIdx.x == 0) { s.mm[2 * chunk] = lo; s.mm[2 * chunk + 1] = hi; }
 }
@@ -1712,10 +1738,15 @@ __global__ __launch_bounds__(BS_NT) void k_base_count(const K *A, BaseSplit<K> s
     for (uint32_t i = tid; i < BS_NW * 256; i += BS_NT) (&h[0][0])[i] = 0;
     __syncthreads();
     uint32_t *wh = h[wave_id()];
-    for (uint32_t i = 0; i < (uint32_t)BS_IPT; ++i) {
+    K x[BS_IPT];
+#pragma unroll
+    for (int i = 0; i < BS_IPT; ++i) {
         const uint32_t p = g * BS_CH + i * BS_NT + tid;
-        if (p < si.n) atomicAdd(&wh[(uint32_t)((K)(A[si.off + p] - lo) >> shift)], 1u);
+        x[i] = p < si.n ? A[si.off + p] : lo;
     }
+#pragma unroll
+    for (int i = 0; i < BS_IPT; ++i)
+        if (g * BS_CH + i * BS_NT + tid < si.n) atomicAdd(&wh[(uint32_t)((K)(x[i] - lo) >> shift)], 1u);
     __syncthreads();
     uint32_t *cnt = s.cnt + 256ull * si.c0;
     for (uint32_t d = tid; d < 256; d += BS_NT) {
@@ -1746,12 +1777,16 @@ __global__ __launch_bounds__(1024) void k_base_scan(BaseSplit<K> s)
     K lo, hi;
     int shift;
     split_range(s, si, lo, hi, shift, sh);
-    uint32_t loc = 0;
-    for (uint32_t q = 0; q < PER; ++q) {
+    uint32_t loc = 0, c[PER];
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {                 // loads first, in flight together
         const uint32_t i = tid * PER + q;
-        const uint32_t c = i < E ? cnt[i] : 0u;
-        v[i] = c;
-        loc += c;
+        c[q] = i < E ? cnt[i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+        v[tid * PER + q] = c[q];
+        loc += c[q];
     }
     const uint32_t incl = wave_incl_scan(loc);
     if (lane_id() == WAVE - 1) wsum[wave_id()] = incl;
@@ -1827,11 +1862,15 @@ __global__ __launch_bounds__(BS_NT) void k_base_scatter(const K *A, const uint32
     K kk[BS_IPT];
     uint32_t vv[BS_IPT], pos[BS_IPT];
 #pragma unroll
+    for (int r = 0; r < BS_IPT; ++r) {                          // loads first, in flight together
+        const uint32_t p = item_pos<BS_NW, BS_IPT>(r);
+        kk[r] = r < nrows && p < chN ? src[c0 + p] : (K)0;
+        if (HV) vv[r] = r < nrows && p < chN ? vsrc[c0 + p] : 0u;
+    }
+#pragma unroll
     for (int r = 0; r < BS_IPT; ++r) {
         if (r < nrows) {
             const uint32_t p = item_pos<BS_NW, BS_IPT>(r);
-            kk[r] = p < chN ? src[c0 + p] : (K)0;
-            if (HV) vv[r] = p < chN ? vsrc[c0 + p] : 0u;
             const uint32_t d = p < chN ? (uint32_t)((K)(kk[r] - lo) >> shift) : 255u;
             pos[r] = rank_row(tab, d);
         }
