@@ -84,6 +84,14 @@ __device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __b
 // the wave index, as a wave-uniform (scalar) value
 __device__ inline uint32_t wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE); }
 
+// Waits until every vector memory access of the wave has completed.  Used
+// right after a block of loads whose values feed per-row conditional code:
+// without it the compiler cannot tell that the loads are complete on every
+// path and waits for all memory accesses again before each later store,
+// which serialises the stores.  (gfx9 encoding: vmcnt 0, expcnt and
+// lgkmcnt at their maximum, i.e. not waited for.)
+__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // orders this wave's LDS accesses before and after (no work-group barrier)
 __device__ inline void wave_lds_sync()
 {

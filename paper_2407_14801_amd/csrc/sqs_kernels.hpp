@@ -387,6 +387,7 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
             kk[r] = ok ? (sorted ? dst[base + p] : src[base + p]) : (K)0;
             if (HV) vv[r] = ok && !sorted ? vsrc[base + p] : 0u;
         }
+        wait_vmem();
         __syncthreads();
         if (!sorted) {
             block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm);
@@ -973,6 +974,7 @@ __device__ void transpose_tile(const Batch<K> &b, const K *src, const uint32_t *
             __hip_atomic_store(rec, TR_INCL | (uint32_t)(base + e0 - s0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (d < nb) sm.wbase[d] = base - s0;
         }
+        wait_vmem();
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < TR_IPT; ++r) {
@@ -1474,6 +1476,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                         kk[r] = r < R && p < sg.size ? src[sb + p] : (K)0;
                         if (HV) vv[r] = r < R && p < sg.size ? vsrc[sb + p] : 0u;
                     }
+                    wait_vmem();
                     __syncthreads();
                     block_sort<K, HV, BK_NW, BK_IPT>(kk, vv, sg.size, sm, true, (K)sg.lo, (K)sg.hi);
 #pragma unroll
@@ -1550,6 +1553,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                     kk[r] = r < nrows && p < chN ? src[sb + c0 + p] : (K)0;
                     if (HV) vv[r] = r < nrows && p < chN ? vsrc[sb + c0 + p] : 0u;
                 }
+                wait_vmem();
 #pragma unroll
                 for (int r = 0; r < BK_IPT; ++r) {
                     if (r < nrows) {
@@ -1937,6 +1941,7 @@ __global__ __launch_bounds__(SORT_NT) void k_base_sort(uint32_t n, const K *A, c
         kk[r] = r < R && p < n ? A[p] : (K)0;
         if (HV) vv[r] = r < R && p < n ? VA[p] : 0u;
     }
+    wait_vmem();
     __syncthreads();
     block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, n, sm);
 #pragma unroll
