@@ -89,6 +89,15 @@ constexpr uint32_t ALG1_ATTEMPTS = 64;
 constexpr uint32_t COPY_CH = 32768;           // keys per piece of a single-value bucket copy
 constexpr uint32_t BIG_CAP = 16 * SORT_CAP;  // largest automatic cut-off: 262144 keys
 
+// A base-case sort item, resolved: its first slot in A and D, its size and
+// the inclusive key bounds of its bucket (one load gives a sort kernel all
+// it needs, instead of a chain of list entry, node and pivot loads).
+template <class K> struct Span {
+    uint64_t base;
+    uint32_t size, pad;
+    K lo, hi;
+};
+
 template <class K> struct Batch {
     const NodeDesc *nodes;
     uint32_t N;
@@ -110,7 +119,8 @@ template <class K> struct Batch {
     uint32_t *tot;      // [j] per node
     BucketItem *list[NCLS];
     uint32_t cap[NCLS];
-    const uint32_t *order[NCLS];   // claim order of a list (largest items first), or null: list order
+    Span<K> *span[NCLS];           // mid4, mid, big: the items resolved (same index as the list)
+    Span<K> *ord[NCLS];            // mid, big: the spans in claim order (largest first), or null
     uint32_t *ctr;      // NCLS list sizes, NCLS take counters (work-groups claim items), NCLS key totals, fail flag
     K *nmin;            // per node: smallest key of its input (Alg. 1 pivot rule)
     uint32_t alg1;      // 1: Alg. 1 pivot rule (distinct, above the minimum, resampled; [ ) buckets)
@@ -389,8 +399,24 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
         }
         wait_vmem();
         __syncthreads();
+        if (!sorted) block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm);
+        // this thread's pivots and strict flags, as 16-byte loads of its
+        // aligned, padded slice (entries past npiv are not used); for 32-bit
+        // keys issued here, so that they arrive while the column is stored
+        // (64-bit keys have no registers to spare: loaded before the search)
+        constexpr int PV4 = PPT * (int)sizeof(K) / 16;
+        uint4 praw[PV4];
+        uint4 sraw = make_uint4(0u, 0u, 0u, 0u);
+        auto load_pivots = [&] {
+            if (t0 < npiv) {
+                const uint4 *p4 = reinterpret_cast<const uint4 *>(b.piv + nd.piv + t0);
+#pragma unroll
+                for (int v4 = 0; v4 < PV4; ++v4) praw[v4] = p4[v4];
+                sraw = *reinterpret_cast<const uint4 *>(b.strict + nd.piv + t0);
+            }
+        };
+        if (sizeof(K) == 4) load_pivots();
         if (!sorted) {
-            block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm);
 #pragma unroll
             for (int r = 0; r < SORT_IPT; ++r) {
                 const uint32_t p = bpos(r, R);
@@ -407,17 +433,7 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
             if (r < R && p < len) { if (sizeof(K) == 4) sm.k32[p] = (uint32_t)kk[r]; else sm.k64[p] = (uint64_t)kk[r]; }
         }
         __syncthreads();
-        // this thread's pivots and strict flags, as 16-byte loads of its
-        // aligned, padded slice (entries past npiv are not used)
-        constexpr int PV4 = PPT * (int)sizeof(K) / 16;
-        uint4 praw[PV4];
-        uint4 sraw = make_uint4(0u, 0u, 0u, 0u);
-        if (t0 < npiv) {
-            const uint4 *p4 = reinterpret_cast<const uint4 *>(b.piv + nd.piv + t0);
-#pragma unroll
-            for (int v4 = 0; v4 < PV4; ++v4) praw[v4] = p4[v4];
-            sraw = *reinterpret_cast<const uint4 *>(b.strict + nd.piv + t0);
-        }
+        if (sizeof(K) != 4) load_pivots();
         // Each pivot's position in the sorted column (keys at or below it).
         // The slice's first and last pivot are searched over the whole
         // column, the others inside that bracket; the searches of one step
@@ -1173,21 +1189,20 @@ __global__ void k_digest_finish(Batch<K> b, unsigned long long *digest)
 }
 
 // ------------------------------------------------------------ bucket phase
-// A non-empty bucket admits exactly one key value (the appendix copies such
-// buckets instead of recursing).  Inclusive bounds: U_j = s_j, or s_j - 1
-// for a strict pivot, U_{m-1} = max; L_j = s_{j-1} + 1, or s_{j-1} after a
-// strict pivot, L_0 = 0.
+// Inclusive key bounds of bucket j: U_j = s_j, or s_j - 1 for a strict
+// pivot, U_{m-1} = max; L_j = s_{j-1} + 1, or s_{j-1} after a strict pivot,
+// L_0 = 0.  A non-empty bucket with L_j = U_j admits exactly one key value
+// (the appendix copies such buckets instead of recursing).
 template <class K>
-__device__ inline bool single_value_bucket(const Batch<K> &b, const NodeDesc &nd, uint32_t j)
+__device__ inline void bucket_bounds(const Batch<K> &b, const NodeDesc &nd, uint32_t j, K &lo, K &hi)
 {
-    const K MAXV = (K)KeyT<K>::MAXV;
-    const uint32_t m = nd.m;
-    K lo, hi;
-    if (j == 0) lo = 0;
-    else { const K s = b.piv[nd.piv + j - 1]; lo = b.strict[nd.piv + j - 1] ? s : (K)(s + 1); }
-    if (j == m - 1) hi = MAXV;
-    else { const K s = b.piv[nd.piv + j]; hi = b.strict[nd.piv + j] ? (K)(s - 1) : s; }
-    return lo == hi;
+    const bool hasLo = j > 0, hasHi = j + 1 < nd.m;
+    K sl = (K)0, sh = (K)0;
+    uint8_t tl = 1, th = 1;
+    if (hasLo) { sl = b.piv[nd.piv + j - 1]; tl = b.strict[nd.piv + j - 1]; }
+    if (hasHi) { sh = b.piv[nd.piv + j]; th = b.strict[nd.piv + j]; }
+    lo = hasLo ? (tl ? sl : (K)(sl + 1)) : (K)0;
+    hi = hasHi ? (th ? (K)(sh - 1) : sh) : (K)KeyT<K>::MAXV;
 }
 
 // Classify every bucket and append it to its work list.  Appends are
@@ -1203,6 +1218,8 @@ __global__ __launch_bounds__(CL_NT) void k_classify(Batch<K> b, uint32_t cutoff)
     __syncthreads();
     int cls = -1;
     BucketItem it{0, 0, 0, 0};
+    K blo = (K)0, bhi = (K)0;
+    uint64_t base = 0;
     if (item < b.bucStart[b.N]) {
         const uint32_t k = find_node(b.bucStart, b.N, item);
         const NodeDesc nd = b.nodes[k];
@@ -1210,7 +1227,9 @@ __global__ __launch_bounds__(CL_NT) void k_classify(Batch<K> b, uint32_t cutoff)
         const uint32_t lo = b.bs[nd.bkt + j], s = b.bs[nd.bkt + j + 1] - lo;
         it = BucketItem{k, j, lo, s};
         if (s > 0) {
-            if (single_value_bucket(b, nd, j)) cls = CLS_COPY;
+            bucket_bounds(b, nd, j, blo, bhi);
+            base = nd.off + lo;
+            if (blo == bhi) cls = CLS_COPY;
             else if (s > cutoff) cls = CLS_INTERNAL;
             else if (s <= (uint32_t)WCAP) cls = CLS_SMALL;
             else if (s <= M4_CAP) cls = CLS_MID4;
@@ -1256,7 +1275,10 @@ __global__ __launch_bounds__(CL_NT) void k_classify(Batch<K> b, uint32_t cutoff)
     for (int c = 1; c < NCLS; ++c) {
         if (cls == c) {
             const uint32_t at = wgBase[c] + woff[c] + rank_in_mask((uint32_t)mask[c], (uint32_t)(mask[c] >> 32));
-            if (at < b.cap[c]) b.list[c][at] = it;
+            if (at < b.cap[c]) {
+                b.list[c][at] = it;
+                if (b.span[c]) b.span[c][at] = Span<K>{base, it.size, 0u, blo, bhi};
+            }
         }
     }
 }
@@ -1311,40 +1333,29 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_bucket_small(Batch<K> b, const
     }
 }
 
-// Inclusive key bounds of bucket j (see single_value_bucket).
-template <class K>
-__device__ inline void bucket_bounds(const Batch<K> &b, const NodeDesc &nd, uint32_t j, K &lo, K &hi)
-{
-    const K MAXV = (K)KeyT<K>::MAXV;
-    if (j == 0) lo = 0;
-    else { const K s = b.piv[nd.piv + j - 1]; lo = b.strict[nd.piv + j - 1] ? s : (K)(s + 1); }
-    if (j == nd.m - 1) hi = MAXV;
-    else { const K s = b.piv[nd.piv + j]; hi = b.strict[nd.piv + j] ? (K)(s - 1) : s; }
-}
 
-// Claim order of the mid (block 0) and big (block 1) bucket lists: largest
-// items first.  Work-groups take items one at a time, so taking them in
+// Claim order of the mid (block 0) and big (block 1) spans: largest items
+// first, written as a permuted copy.  Work-groups take items one at a time, so taking them in
 // decreasing size (longest-processing-time order) makes the work-groups that
 // take the last items finish close together; in list order a large bucket
 // taken late sets the end of the whole kernel.  Sizes are counting-sorted
 // into 256 bins of 2^shift keys; the order inside a bin is whatever the
 // atomics give, and no output depends on it.
 template <class K>
-__global__ __launch_bounds__(1024) void k_order_lists(Batch<K> b, uint32_t *ordMid, uint32_t *ordBig,
-                                                      uint32_t shiftMid, uint32_t shiftBig)
+__global__ __launch_bounds__(1024) void k_order_lists(Batch<K> b, uint32_t shiftMid, uint32_t shiftBig)
 {
     __shared__ uint32_t at[256];
     const int c = blockIdx.x == 0 ? CLS_MID : CLS_BIG;
-    uint32_t *ord = blockIdx.x == 0 ? ordMid : ordBig;
     const uint32_t shift = blockIdx.x == 0 ? shiftMid : shiftBig;
+    Span<K> *ord = b.ord[c];
     if (!ord) return;
     const uint32_t tid = threadIdx.x;
     const uint32_t cnt = min(b.ctr[c], b.cap[c]);
-    const BucketItem *lst = b.list[c];
+    const Span<K> *sp = b.span[c];
     if (tid < 256) at[tid] = 0;
     __syncthreads();
     for (uint32_t i = tid; i < cnt; i += blockDim.x)                  // bin 0 holds the largest sizes
-        atomicAdd(&at[255u - min((lst[i].size - 1u) >> shift, 255u)], 1u);
+        atomicAdd(&at[255u - min((sp[i].size - 1u) >> shift, 255u)], 1u);
     __syncthreads();
     if (tid < WAVE) {                                                  // exclusive scan, 4 bins a lane
         uint32_t v[4], t4 = 0;
@@ -1353,8 +1364,10 @@ __global__ __launch_bounds__(1024) void k_order_lists(Batch<K> b, uint32_t *ordM
         for (int q = 0; q < 4; ++q) { at[4 * tid + q] = r0; r0 += v[q]; }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < cnt; i += blockDim.x)
-        ord[atomicAdd(&at[255u - min((lst[i].size - 1u) >> shift, 255u)], 1u)] = i;
+    for (uint32_t i = tid; i < cnt; i += blockDim.x) {
+        const Span<K> e = sp[i];
+        ord[atomicAdd(&at[255u - min((e.size - 1u) >> shift, 255u)], 1u)] = e;
+    }
 }
 
 // Buckets of one LDS sort: one work-group of NW waves per bucket
@@ -1372,8 +1385,9 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_mid(Batch<K> b, const K *A
     tables_clear<NW, 256>(sm.s.tab);
     __syncthreads();
     for (; it < cnt; it = take_item(b.ctr, CLS, &take_sh)) {
-        const BucketItem e = b.list[CLS][b.order[CLS] ? b.order[CLS][it] : it];
-        const uint64_t base = b.nodes[e.node].off + e.lo;
+        const Span<K> e = b.ord[CLS] ? b.ord[CLS][it] : b.span[CLS][it];
+        const uint64_t base = e.base;
+        const K blo = e.lo, bhi = e.hi;
         K kk[SORT_IPT];
         uint32_t vv[SORT_IPT];
         const int R = block_rows<NW, SORT_IPT>(e.size);
@@ -1383,8 +1397,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_mid(Batch<K> b, const K *A
             kk[r] = r < R && p < e.size ? A[base + p] : (K)0;
             if (HV) vv[r] = r < R && p < e.size ? VA[base + p] : 0u;
         }
-        K blo, bhi;
-        bucket_bounds(b, b.nodes[e.node], e.j, blo, bhi);
+        wait_vmem();
         block_sort<K, HV, NW, SORT_IPT>(kk, vv, e.size, sm, true, blo, bhi);
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
@@ -1438,13 +1451,10 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
     __shared__ uint32_t take_sh;
     const uint32_t cnt = min(b.ctr[CLS_BIG], b.cap[CLS_BIG]);
     for (uint32_t it = take_item(b.ctr, CLS_BIG, &take_sh); it < cnt; it = take_item(b.ctr, CLS_BIG, &take_sh)) {
-        const BucketItem e = b.list[CLS_BIG][b.order[CLS_BIG] ? b.order[CLS_BIG][it] : it];
-        const NodeDesc nd = b.nodes[e.node];
-        const uint64_t bbase = nd.off + e.lo;
+        const Span<K> e = b.ord[CLS_BIG] ? b.ord[CLS_BIG][it] : b.span[CLS_BIG][it];
+        const uint64_t bbase = e.base;
         if (tid == 0) {
-            K lo, hi;
-            bucket_bounds(b, nd, e.j, lo, hi);
-            stack[0] = BigSeg{0u, e.size, b.bigInD, 0u, (uint64_t)lo, (uint64_t)hi};
+            stack[0] = BigSeg{0u, e.size, b.bigInD, 0u, (uint64_t)e.lo, (uint64_t)e.hi};
             sp_sh = 1;
             overflow_sh = 0;
         }
@@ -1639,10 +1649,9 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
 // grid.  One MSD split of each segment by the top 8 bits of x - min runs over
 // all work-groups (chunk ranges, per-chunk digit counts, one scan per
 // segment, a stable scatter into D); the parts are then items of the
-// MSD-split kernel, which reads them from D.  A pseudo node per segment, with
-// one bucket per part, carries the part bounds as strict pivots: its bucket j
-// holds min + j*2^shift .. min + (j+1)*2^shift - 1 (the first and last
-// buckets open towards 0 and the largest key of the type).
+// MSD-split kernel, which reads them from D.  Part j holds the keys
+// min + j*2^shift .. min + (j+1)*2^shift - 1 (the first and last parts are
+// given bounds open towards 0 and the largest key of the type).
 constexpr int BS_NW = 4;
 constexpr int BS_IPT = 16;
 constexpr int BS_NT = BS_NW * WAVE;
@@ -1655,10 +1664,7 @@ template <class K> struct BaseSplit {
     K *mm;                    // [chunk][2]: smallest and largest key of the chunk
     uint32_t *cnt;            // segment s at 256 * its first chunk: [d][g] keys of its chunk g with
                               // digit d, after the scan their first slot in the segment
-    NodeDesc *node;           // per segment: the pseudo node
-    K *piv;                   // per segment: 256 slots (255 pivots)
-    uint8_t *strict;          // per segment: 256 slots
-    BucketItem *items;        // the parts of every segment (<= 256 each)
+    Span<K> *items;           // the parts of every segment (<= 256 each), resolved
     uint32_t *ctr;            // the counters of the part sort
     const uint64_t *segOff;   // per segment: first slot in A and D (null: one segment at 0)
     const uint32_t *segN;     // per segment: keys (<= BIG_CAP)
@@ -1762,9 +1768,9 @@ __global__ __launch_bounds__(BS_NT) void k_base_count(const K *A, BaseSplit<K> s
 
 // One work-group per segment: exclusive scan of its [d][g] counts
 // (digit-major, so the chunks of a digit follow each other: the scatter is
-// stable), then its pseudo node, pivots and parts (largest first, appended
-// to the part list).  With shift 0 every part holds one key value and is
-// final after the scatter: no items.
+// stable), then its parts (largest first, appended to the part list).  With
+// shift 0 every part holds one key value and is final after the scatter: no
+// items.
 template <class K>
 __global__ __launch_bounds__(1024) void k_base_scan(BaseSplit<K> s)
 {
@@ -1822,20 +1828,13 @@ __global__ __launch_bounds__(1024) void k_base_scan(BaseSplit<K> s)
     if (tid == 0) {
         base_sh = items ? atomicAdd(&s.ctr[CLS_BIG], items) : 0u;
         if (items) atomicAdd(&s.ctr[2 * NCLS + CLS_BIG], si.n);
-        NodeDesc nd{};
-        nd.off = si.off;
-        nd.n = si.n;
-        nd.m = shift > 0 ? (uint32_t)((K)(hi - lo) >> shift) + 1u : 1u;
-        nd.piv = seg * 256;
-        s.node[seg] = nd;
     }
     __syncthreads();
-    if (tid < 256 && shift > 0) {
-        if (sz[tid] > 0) s.items[base_sh + rank] = BucketItem{seg, tid, st0[tid], sz[tid]};
-        if (tid < 255) {
-            s.piv[seg * 256 + tid] = (K)(lo + ((K)(tid + 1) << shift));
-            s.strict[seg * 256 + tid] = 1;
-        }
+    if (tid < 256 && shift > 0 && sz[tid] > 0) {
+        const uint32_t last = (uint32_t)((K)(hi - lo) >> shift);     // the highest non-empty digit
+        const K plo = tid == 0 ? (K)0 : (K)(lo + ((K)tid << shift));
+        const K phi = tid == last ? (K)KeyT<K>::MAXV : (K)(lo + ((K)(tid + 1) << shift) - 1);
+        s.items[base_sh + rank] = Span<K>{si.off + st0[tid], sz[tid], 0u, plo, phi};
     }
 }
 

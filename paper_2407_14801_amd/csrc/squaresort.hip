@@ -139,7 +139,7 @@ uint64_t node_meta_bytes(uint64_t n, uint64_t key_bytes)
     const uint64_t m = ceil_isqrt_host(n);
     const uint64_t groups = cdiv(m, TG), nJ = cdiv(m, TB);
     return sizeof(NodeDesc) + 7 * 4 + 8 + (m - 1 + PIV_ALIGN) * (key_bytes + 1) + 4 * m * (nJ + 1) +
-           4 * groups * m + 4 * (m + 1) + 4 * m + 5 * sizeof(BucketItem) * m + 2 * 4 * m +
+           4 * groups * m + 4 * (m + 1) + 4 * m + 5 * sizeof(BucketItem) * m + 5 * (16 + 2 * key_bytes) * m +
            (3 * n / (2 * TR_CH) + 1) * (8 + 8 * TB) + 512 +
            sizeof(BucketItem) * (n / COPY_CH + 1) + 8;
 }
@@ -155,7 +155,7 @@ uint64_t batch_bound(uint64_t S, uint64_t C, uint64_t key_bytes)
     const uint64_t big = node_meta_bytes(S, key_bytes);
     const uint64_t nodes = S / (C + 1) + 1;
     const uint64_t sq = ceil_isqrt_host(C + 1);
-    const uint64_t per_m = key_bytes + 1 + 4 * 2 + 4 + 4 + 4 + 5 * sizeof(BucketItem) + 2 * 4 + 8;   // generous
+    const uint64_t per_m = key_bytes + 1 + 4 * 2 + 4 + 4 + 4 + 5 * sizeof(BucketItem) + 5 * (16 + 2 * key_bytes) + 8;   // generous
     return big + nodes * (sizeof(NodeDesc) + 64 + 4 * per_m) + (S / sq + nodes) * per_m * 2 +
            S / 8 + 32 * 256;
 }
@@ -168,7 +168,7 @@ uint64_t workspace_bound(uint64_t n, uint64_t C, uint64_t key_bytes)
         // a base case above one LDS sort: the grid-wide split's metadata
         const uint64_t G = cdiv(n, BS_CH);
         const uint64_t split = align_up(2 * G * key_bytes, 256) + align_up(256 * G * 4, 256) +
-                               256 * (key_bytes + 1 + sizeof(BucketItem)) + 4 * 256 + (8 << 10);
+                               256 * (16 + 2 * key_bytes) + (8 << 10);
         return std::max(node_meta_bytes(std::max<uint64_t>(n, 2), key_bytes) + (64 << 10), split);
     }
     // nested batches: a chain of column recursions, each at most the size of n
@@ -381,11 +381,15 @@ template <class K, bool HV> struct Engine {
         b.list[CLS_INTERNAL] = ws.take<BucketItem>(capInt);
         b.cap[CLS_COPY] = capCopy; b.cap[CLS_SMALL] = capSmall; b.cap[CLS_MID4] = capMid4; b.cap[CLS_MID] = capMid;
         b.cap[CLS_BIG] = capBig; b.cap[CLS_INTERNAL] = capInt;
-        for (int c = 0; c < NCLS; ++c) b.order[c] = nullptr;
+        for (int c = 0; c < NCLS; ++c) { b.span[c] = nullptr; b.ord[c] = nullptr; }
         b.bigInD = 0;
-        uint32_t *ordMid = ws.take<uint32_t>(capMid);
-        uint32_t *ordBig = cutoff > (uint32_t)SORT_CAP ? ws.take<uint32_t>(capBig) : nullptr;
-        b.order[CLS_MID] = ordMid; b.order[CLS_BIG] = ordBig;
+        b.span[CLS_MID4] = ws.take<Span<K>>(capMid4);
+        b.span[CLS_MID] = ws.take<Span<K>>(capMid);
+        b.ord[CLS_MID] = ws.take<Span<K>>(capMid);
+        if (cutoff > (uint32_t)SORT_CAP) {
+            b.span[CLS_BIG] = ws.take<Span<K>>(capBig);
+            b.ord[CLS_BIG] = ws.take<Span<K>>(capBig);
+        }
         b.ctr = ws.take<uint32_t>(CTR_WORDS);
         // heavy-tile transpose chunks: a tile above TR_HEAVY = 2 chunks has fewer
         // than 1.5 * keys / TR_CH chunks, so the sum over tiles is below that
@@ -488,7 +492,7 @@ template <class K, bool HV> struct Engine {
         // ---- buckets A -> D, by class
         launch("k_classify", bucS[N], [&] { k_classify<K><<<cdiv(bucS[N], CL_NT), CL_NT, 0, st>>>(b, cutoff); });
         launch("k_order_lists", bucS[N], [&] {
-            k_order_lists<K><<<2, 1024, 0, st>>>(b, ordMid, ordBig, shift_of(SORT_CAP), shift_of(cutoff)); });
+            k_order_lists<K><<<2, 1024, 0, st>>>(b, shift_of(SORT_CAP), shift_of(cutoff)); });
         launch("k_bucket_copy", keysTot, [&] { k_bucket_copy<K, HV><<<512, 256, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket_w", keysTot, [&] {
             k_bucket_small<K, HV><<<std::min<uint32_t>(cdiv(capSmall, SM_NW), 2048), SM_NW * WAVE, 0, st>>>(b, A, VA, D, VD); });
@@ -565,17 +569,12 @@ template <class K, bool HV> struct Engine {
         s.segOff = segOff; s.segN = segN; s.segChunk = segChunk;
         s.mm = ws.take<K>(2 * (uint64_t)G);
         s.cnt = ws.take<uint32_t>(256 * (uint64_t)G);
-        s.node = ws.take<NodeDesc>(nseg);
-        s.piv = ws.take<K>(256 * (uint64_t)nseg);
-        s.strict = ws.take<uint8_t>(256 * (uint64_t)nseg);
-        s.items = ws.take<BucketItem>(256 * (uint64_t)nseg);
+        s.items = ws.take<Span<K>>(256 * (uint64_t)nseg);
         s.ctr = ws.take<uint32_t>(CTR_WORDS);
         ws.top = mark;                     // stream-ordered: later work on this stream may reuse it
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         Batch<K> b{};
-        b.nodes = s.node; b.N = nseg;
-        b.piv = s.piv; b.strict = s.strict;
-        b.list[CLS_BIG] = s.items; b.cap[CLS_BIG] = 256 * nseg;
+        b.span[CLS_BIG] = s.items; b.cap[CLS_BIG] = 256 * nseg;
         b.ctr = s.ctr;
         b.bigInD = 1;
         launch("k_base_split", keys, [&] {
@@ -639,6 +638,20 @@ template <class K, bool HV> struct Engine {
                 hipMemcpyAsync(b.list[c], lists[c].data(), lists[c].size() * sizeof(BucketItem),
                                hipMemcpyHostToDevice, st) != hipSuccess)
                 return SQS_ERR_DEVICE;
+        // the sorted classes read resolved spans (one-bucket nodes: the whole key range)
+        for (int c = CLS_MID4; c <= CLS_BIG; ++c) {
+            if (lists[c].empty()) continue;
+            const size_t bytes = lists[c].size() * sizeof(Span<K>);
+            keep_.emplace_back(bytes, 0);
+            Span<K> *hs = reinterpret_cast<Span<K> *>(keep_.back().data());
+            for (size_t q = 0; q < lists[c].size(); ++q) {
+                const BucketItem &e = lists[c][q];
+                hs[q] = Span<K>{pn[e.node].off + e.lo, e.size, 0u, (K)0, (K)KeyT<K>::MAXV};
+            }
+            b.span[c] = ws.take<Span<K>>(lists[c].size());
+            if (ws.overflow) return SQS_ERR_WORKSPACE;
+            if (hipMemcpyAsync(b.span[c], hs, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return SQS_ERR_DEVICE;
+        }
         b.nodes = dDesc;
         b.N = (uint32_t)pn.size();
         b.ctr = ctr;
@@ -742,8 +755,9 @@ uint64_t batched_workspace_bound(uint32_t count, const uint64_t *offs, uint64_t 
     // leaf lists, plus the grid-wide split of the large leaves (chunk ranges
     // and counts per 4096 keys; node, pivots, flags and parts per leaf)
     const uint64_t split = (L / BS_CH + nl) * (2 * key_bytes + 256 * 4) +
-                           nl * (sizeof(NodeDesc) + 256 * (key_bytes + 1 + sizeof(BucketItem)) + 16) + (64 << 10);
-    const uint64_t leaves = (uint64_t)count * (sizeof(NodeDesc) + 4 * sizeof(BucketItem)) + 8 * 256 + split;
+                           nl * (256 * (16 + 2 * key_bytes) + 16) + (64 << 10);
+    const uint64_t leaves = (uint64_t)count * (sizeof(NodeDesc) + 4 * sizeof(BucketItem) + 16 + 2 * key_bytes) +
+                            12 * 256 + split;
     if (S == 0) return leaves;
     uint64_t chain = 1;
     for (uint64_t s = ceil_isqrt_host(big); s > C && chain < 8; s = ceil_isqrt_host(s)) ++chain;
