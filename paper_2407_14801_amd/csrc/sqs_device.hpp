@@ -187,7 +187,10 @@ template <int NW, int IPT> struct SortSmem {
 template <int NW, int IPT>
 __device__ inline uint32_t item_pos(int r)
 {
-    return wave_id() * (IPT * WAVE) + r * WAVE + lane_id();
+    // per-lane arithmetic on threadIdx (no scalar wave index), so that the
+    // row-independent part is computed once rather than in every row's branch
+    const uint32_t t = threadIdx.x;
+    return (t / WAVE) * (IPT * WAVE) + (t % WAVE) + (uint32_t)r * WAVE;
 }
 
 // rows of the calling wave that hold at least one of the first `count` positions
@@ -211,7 +214,8 @@ __device__ inline int block_rows(uint32_t count)
 }
 __device__ inline uint32_t bpos(int r, int R)
 {
-    return (wave_id() * (uint32_t)R + (uint32_t)r) * WAVE + lane_id();
+    const uint32_t t = threadIdx.x;
+    return (t / WAVE) * (uint32_t)R * WAVE + (t % WAVE) + (uint32_t)r * WAVE;
 }
 // rows of the calling wave (of R) that hold at least one of the first count positions
 __device__ inline int wave_rows_of(uint32_t count, int R)

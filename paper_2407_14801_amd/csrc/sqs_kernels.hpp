@@ -1009,9 +1009,11 @@ __device__ void transpose_tile(const Batch<K> &b, const K *src, const uint32_t *
     }
 }
 
-// Every tile that is not heavy, whole, by its own work-group.
+// Every tile that is not heavy, whole, by its own work-group.  Registers are
+// held to six waves per SIMD for 32-bit keys (LDS admits six work-groups per
+// CU) and five for 64-bit keys; key/value tiles would spill, so stay free.
 template <class K, bool HV>
-__global__ __launch_bounds__(TR_NW * WAVE) void k_transpose(Batch<K> b, const K *src, const uint32_t *vsrc,
+__global__ __launch_bounds__(TR_NW * WAVE, HV ? 1 : (sizeof(K) == 4 ? 6 : 5)) void k_transpose(Batch<K> b, const K *src, const uint32_t *vsrc,
                                                             K *dst, uint32_t *vdst)
 {
     __shared__ TileSmem<K> sm;
