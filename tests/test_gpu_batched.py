@@ -119,3 +119,62 @@ def test_batched_log_uniform_workload(b, ws):
     for i in range(len(sizes)):
         lo, hi = int(offs[i]), int(offs[i + 1])
         assert np.array_equal(got[lo:hi], np.sort(keys[lo:hi])), f"instance {i}"
+
+
+def _batched_kv(b, ws, k, v, sizes, seeds, cutoff, digest=False):
+    offs = b.batched_offsets(sizes)
+    ki = torch.from_numpy(np.ascontiguousarray(k, np.uint64).view(np.int64)).to(DEV)
+    vi = torch.from_numpy(np.ascontiguousarray(v, np.uint32).view(np.int32)).to(DEV)
+    ko, vo = torch.empty_like(ki), torch.empty_like(vi)
+    dg = torch.zeros(1, dtype=torch.int64, device=DEV) if digest else None
+    used = b.squaresort_batched_kv(ki, vi, ko, vo, offs, seeds, cutoff=cutoff, ws=ws, digest=dg)
+    torch.cuda.synchronize()
+    d = int(dg.cpu().numpy().view(np.uint64)[0]) if digest else None
+    return ko.cpu().numpy().view(np.uint64), vo.cpu().numpy().view(np.uint32), offs, used, d
+
+
+@pytest.mark.parametrize("cutoff", [0, 4096])
+def test_batched_kv_mixed_classes(b, ws, cutoff):
+    """Key/value instances of every class (base cases split over the grid
+    among them): each one is the stable sort of its range."""
+    _say(f"batched kv mixed cutoff={cutoff}")
+    sizes = np.array(MIXED, dtype=np.int64)
+    k, _ = datagen.kv_mixture(int(sizes.sum()), seed=21)
+    v = np.arange(k.size, dtype=np.uint32)
+    seeds = np.arange(len(sizes), dtype=np.uint64) * 31 + 7
+    gk, gv, offs, used, _ = _batched_kv(b, ws, k, v, sizes, seeds, cutoff)
+    for i in range(len(sizes)):
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        order = np.argsort(k[lo:hi], kind="stable")
+        assert np.array_equal(gk[lo:hi], k[lo:hi][order]), f"instance {i} (n={hi - lo})"
+        assert np.array_equal(gv[lo:hi], v[lo:hi][order]), f"instance {i} (n={hi - lo})"
+
+
+def test_batched_kv_digest_is_sum_of_instance_trees(b, ws):
+    _say("batched kv digest cutoff=64")
+    sizes = datagen.log_uniform_sizes(24, 10, 20_000, seed=9)
+    k, _ = datagen.kv_mixture(int(sizes.sum()), seed=22)
+    v = np.arange(k.size, dtype=np.uint32)
+    seeds = np.arange(1, len(sizes) + 1, dtype=np.uint64) * 7777
+    gk, gv, offs, used, dg = _batched_kv(b, ws, k, v, sizes, seeds, 64, digest=True)
+    want = 0
+    for i in range(len(sizes)):
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        wk, wv, wd, _ = oracle.squaresort_kv(k[lo:hi], v[lo:hi], int(seeds[i]), used, want_digest=True)
+        assert np.array_equal(gk[lo:hi], wk) and np.array_equal(gv[lo:hi], wv), f"instance {i}"
+        want = (want + wd) & 0xFFFFFFFFFFFFFFFF
+    assert dg == want
+
+
+def test_batched_many_large_base_cases(b, ws):
+    """More large base-case instances than the grid-wide split takes: each
+    is sorted by one work-group of the MSD-split kernel."""
+    _say("batched 300 large base cases")
+    sizes = np.random.default_rng(3).integers(16_385, 60_000, size=300)
+    keys = datagen.uniform_u32(int(sizes.sum()), seed=14)
+    seeds = np.arange(len(sizes), dtype=np.uint64) + 11
+    got, offs, used, _ = _batched(b, ws, keys, sizes, seeds, 0)
+    assert used >= int(sizes.max())
+    for i in range(len(sizes)):
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        assert np.array_equal(got[lo:hi], np.sort(keys[lo:hi])), f"instance {i}"
