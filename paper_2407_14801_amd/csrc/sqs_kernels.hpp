@@ -690,11 +690,15 @@ __global__ void k_colscan(Batch<K> b)
     const NodeDesc nd = b.nodes[k];
     const uint32_t j = item - b.bucStart[k];
     uint32_t run = 0;
-    for (uint32_t g = 0; g < nd.groups; ++g) {
-        uint32_t *p = b.blk + nd.blk + (uint64_t)g * nd.m + j;
-        const uint32_t c = *p;
-        *p = run;
-        run += c;
+    uint32_t *p = b.blk + nd.blk + j;
+    constexpr uint32_t B = 16;                       // loads of B groups in flight together
+    for (uint32_t g0 = 0; g0 < nd.groups; g0 += B) {
+        uint32_t c[B];
+#pragma unroll
+        for (uint32_t q = 0; q < B; ++q) c[q] = g0 + q < nd.groups ? p[(uint64_t)(g0 + q) * nd.m] : 0u;
+#pragma unroll
+        for (uint32_t q = 0; q < B; ++q)
+            if (g0 + q < nd.groups) { p[(uint64_t)(g0 + q) * nd.m] = run; run += c[q]; }
     }
     b.tot[nd.bkt + j] = run;
 }
@@ -716,11 +720,18 @@ __global__ __launch_bounds__(1024) void k_bucket_start(Batch<K> b, unsigned long
     __syncthreads();
     uint32_t run = incl - s;
     for (uint32_t w = 0; w < wave_id(); ++w) run += wsum[w];
-    for (uint32_t q = 0; q < per; ++q) {
-        if (j0 + q < m) {
-            b.bs[nd.bkt + j0 + q] = run;
-            if (bs64_out) bs64_out[j0 + q] = run;
-            run += b.tot[nd.bkt + j0 + q];
+    constexpr uint32_t B = 16;                       // loads of B totals in flight together
+    for (uint32_t q0 = 0; q0 < per; q0 += B) {
+        uint32_t t[B];
+#pragma unroll
+        for (uint32_t q = 0; q < B; ++q) t[q] = q0 + q < per && j0 + q0 + q < m ? b.tot[nd.bkt + j0 + q0 + q] : 0u;
+#pragma unroll
+        for (uint32_t q = 0; q < B; ++q) {
+            if (q0 + q < per && j0 + q0 + q < m) {
+                b.bs[nd.bkt + j0 + q0 + q] = run;
+                if (bs64_out) bs64_out[j0 + q0 + q] = run;
+                run += t[q];
+            }
         }
     }
     if (threadIdx.x == 0) {
