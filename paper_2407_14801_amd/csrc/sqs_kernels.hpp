@@ -749,23 +749,27 @@ __global__ __launch_bounds__(1024) void k_bucket_start(Batch<K> b, unsigned long
 // are processed chunk by chunk in column order, which keeps that order.
 //
 // Per key, the column is read from a per-position map filled run by run, and
-// the bucket from a 256-slot table over the block's key range: slot u holds
-// the bucket of the smallest key value of the slot, so a key's bucket lies
-// between the entries of its slot and the next, and a short binary search
-// over the pivots in between (usually none or one) finishes it.
-constexpr int TR_LUT = 256;
+// the bucket from a 512-slot table over the block's key range.  Pivot t is
+// passed by the keys at or above its threshold p_t (s_t for a strict pivot,
+// s_t + 1 otherwise; thresholds are non-decreasing).  Slot u starts at
+// lo + u*2^sh and holds the number of thresholds at or below its start, so a
+// key's bucket lies between the entries of its slot and the next, and a
+// binary search over the thresholds in between (usually none) finishes it.  The table is built by one atomic add per pivot at the first slot its
+// threshold does not exceed, then a scan.  A non-strict pivot equal to the
+// largest key has no threshold: no key passes it and no slot counts it.
+constexpr int TR_LUT_BITS = 9;
+constexpr int TR_LUT = 1 << TR_LUT_BITS;
 
 template <class K> struct TileSmem {
     RankTab<TB> tab[TR_NW];
     uint32_t wsum[TR_NW];
-    uint32_t buf[TR_CH];
+    uint32_t buf[TR_CH];         // exchange buffer; the slot counts while the table is built
     uint8_t colOf[TR_CH];        // column of each chunk position; then the bucket of each sorted position
-    uint64_t relBase[TG];        // node-relative source index of chunk position q is relBase[c] + q
+    uint32_t relBase[TG];        // node-relative source index of chunk position q is relBase[c] + q (mod 2^32)
     uint32_t cOff[TG + 1];
     uint32_t dstb[TB];           // node-relative destination of the bucket's next key
     uint32_t wbase[TB];          // per chunk: destination of sorted position p is wbase[d] + p
-    K piv[TB];
-    uint8_t st[TB];
+    K pth[TB];                   // pivot thresholds of the block
     uint8_t lut[TR_LUT + 1];
 };
 
@@ -776,11 +780,50 @@ __device__ inline uint32_t tile_bucket(K x, K lo, int sh, const TileSmem<K> &sm)
     const K du = (K)((K)(x - lo) >> sh);
     const uint32_t u = du < (K)(TR_LUT - 1) ? (uint32_t)du : (uint32_t)(TR_LUT - 1);
     uint32_t a = sm.lut[u], e = sm.lut[u + 1];
-    while (a < e) {
+    while (a < e) {                                  // duplicate pivots can share a slot
         const uint32_t mid = (a + e) >> 1;
-        if (le_pivot(x, sm.piv[mid], sm.st[mid] != 0)) e = mid; else a = mid + 1;
+        if (x >= sm.pth[mid]) a = mid + 1; else e = mid;
     }
     return a;
+}
+
+// The block's thresholds and slot table (all threads; two barriers inside;
+// wave 0 writes the table after the second, so it is visible after the
+// caller's next barrier).  lo: the pivot before the block
+// (or 0), which every key of the block is at or above; sh as returned.
+template <class K>
+__device__ inline int tile_table(const Batch<K> &b, const NodeDesc &nd, uint32_t j0, uint32_t npv, K lo,
+                                 TileSmem<K> &sm)
+{
+    using T = KeyT<K>;
+    const uint32_t tid = threadIdx.x;
+    const K hi = npv > 0 ? b.piv[nd.piv + j0 + npv - 1] : lo;
+    const int sh = max(0, T::bitlen((K)(hi - lo)) - TR_LUT_BITS);
+    for (uint32_t u = tid; u <= (uint32_t)TR_LUT; u += TR_NW * WAVE) sm.buf[u] = 0;
+    __syncthreads();
+    if (tid < npv) {
+        const K sv = b.piv[nd.piv + j0 + tid];
+        const bool strict = b.strict[nd.piv + j0 + tid] != 0;
+        const K p = strict ? sv : (K)(sv + 1);
+        sm.pth[tid] = p;
+        if (strict || sv != (K)T::MAXV) {            // else no key passes it
+            const K d = (K)(p - lo);
+            const K q = (K)(d >> sh) + (((d & (K)(((K)1 << sh) - 1)) != 0) ? (K)1 : (K)0);
+            atomicAdd(&sm.buf[q < (K)TR_LUT ? (uint32_t)q : (uint32_t)TR_LUT], 1u);
+        }
+    }
+    __syncthreads();
+    if (tid < WAVE) {                                // inclusive scan of the TR_LUT + 1 counts
+        constexpr int PER = TR_LUT / WAVE;
+        uint32_t c[PER], sum = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) { c[q] = sm.buf[tid * PER + q]; sum += c[q]; }
+        uint32_t run = wave_incl_scan(sum) - sum;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) { run += c[q]; sm.lut[tid * PER + q] = (uint8_t)run; }
+        if (tid == WAVE - 1) sm.lut[TR_LUT] = (uint8_t)(run + sm.buf[TR_LUT]);
+    }
+    return sh;
 }
 
 // Tiles with more than TR_HEAVY keys (presorted inputs put a column group's
@@ -879,34 +922,17 @@ __device__ void transpose_tile(const Batch<K> &b, const K *src, const uint32_t *
         const uint32_t incl = wave_incl_scan(len);
         if (tid < ncol) {
             sm.cOff[tid] = incl - len;
-            sm.relBase[tid] = (uint64_t)(i0 + tid) * m + a - (incl - len);
+            sm.relBase[tid] = (i0 + tid) * m + a - (incl - len);     // mod 2^32; the true value is < n
         }
         if (tid == ncol - 1) sm.cOff[ncol] = incl;
     }
     if (tid < nb) {
         const uint32_t j = j0 + tid;
         sm.dstb[tid] = b.bs[nd.bkt + j] + b.blk[nd.blk + (uint64_t)g * m + j];
-        if (tid < npv) { sm.piv[tid] = b.piv[nd.piv + j]; sm.st[tid] = b.strict[nd.piv + j]; }
     }
     // every key of the block is >= the pivot before it (or 0)
     const K lo = j0 > 0 ? b.piv[nd.piv + j0 - 1] : (K)0;
-    __syncthreads();
-    const K hi = npv > 0 ? sm.piv[npv - 1] : lo;
-    const int sh = max(0, T::bitlen((K)(hi - lo)) - 8);
-    for (uint32_t t = tid; t <= (uint32_t)TR_LUT; t += TR_NW * WAVE) {
-        uint32_t v = npv;
-        const K step = (K)((K)t << sh);
-        if (t < (uint32_t)TR_LUT && step <= (K)((K)T::MAXV - lo)) {   // t << sh cannot overflow: t < 256
-            const K x = (K)(lo + step);
-            uint32_t a = 0, e = npv;
-            while (a < e) {
-                const uint32_t mid = (a + e) >> 1;
-                if (le_pivot(x, sm.piv[mid], sm.st[mid] != 0)) e = mid; else a = mid + 1;
-            }
-            v = a;
-        }
-        sm.lut[t] = (uint8_t)v;
-    }
+    const int sh = tile_table(b, nd, j0, npv, lo, sm);
     const uint32_t N = sm.cOff[ncol];
     RankTab<TB> &tab = sm.tab[w];
     const bool seq = item == TR_SEQ;
@@ -934,8 +960,8 @@ __device__ void transpose_tile(const Batch<K> &b, const K *src, const uint32_t *
             const uint32_t p = item_pos<TR_NW, TR_IPT>(r);
             if (r < nrows && p < chN) {
                 const uint32_t c = sm.colOf[p];
-                const uint64_t rel = sm.relBase[c] + q0 + p;
-                const uint64_t at = nd.off + (rel < nd.n ? rel : 0);   // guard: inside the node
+                const uint32_t rel = sm.relBase[c] + q0 + p;
+                const uint64_t at = nd.off + (rel < nd.n ? rel : 0u);  // guard: inside the node
                 kk[r] = src[at];
                 if (HV) vv[r] = vsrc[at];
             }
@@ -1130,30 +1156,13 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_tilecount(Batch<K> b, const K 
         const uint32_t incl = wave_incl_scan(len);
         if (tid < ncol) {
             sm.cOff[tid] = incl - len;
-            sm.relBase[tid] = (uint64_t)(i0 + tid) * m + a - (incl - len);
+            sm.relBase[tid] = (i0 + tid) * m + a - (incl - len);     // mod 2^32; the true value is < n
         }
         if (tid == ncol - 1) sm.cOff[ncol] = incl;
     }
     if (tid < TB) hist[tid] = 0;
-    if (tid < npv) { sm.piv[tid] = b.piv[nd.piv + j0 + tid]; sm.st[tid] = b.strict[nd.piv + j0 + tid]; }
     const K lo = j0 > 0 ? b.piv[nd.piv + j0 - 1] : (K)0;
-    __syncthreads();
-    const K hi = npv > 0 ? sm.piv[npv - 1] : lo;
-    const int sh = max(0, T::bitlen((K)(hi - lo)) - 8);
-    for (uint32_t t = tid; t <= (uint32_t)TR_LUT; t += TR_NW * WAVE) {
-        uint32_t v = npv;
-        const K step = (K)((K)t << sh);
-        if (t < (uint32_t)TR_LUT && step <= (K)((K)T::MAXV - lo)) {
-            const K x = (K)(lo + step);
-            uint32_t a = 0, e = npv;
-            while (a < e) {
-                const uint32_t mid = (a + e) >> 1;
-                if (le_pivot(x, sm.piv[mid], sm.st[mid] != 0)) e = mid; else a = mid + 1;
-            }
-            v = a;
-        }
-        sm.lut[t] = (uint8_t)v;
-    }
+    const int sh = tile_table(b, nd, j0, npv, lo, sm);
     const uint32_t N = sm.cOff[ncol];
     for (uint32_t q0 = 0; q0 < N; q0 += TR_CH) {
         const uint32_t chN = min((uint32_t)TR_CH, N - q0);
@@ -1164,8 +1173,8 @@ __global__ __launch_bounds__(TR_NW * WAVE) void k_tilecount(Batch<K> b, const K 
         __syncthreads();
         for (uint32_t p = tid; p < chN; p += TR_NW * WAVE) {
             const uint32_t c = sm.colOf[p];
-            const uint64_t rel = sm.relBase[c] + q0 + p;
-            const K x = src[nd.off + (rel < nd.n ? rel : 0)];      // guard: inside the node
+            const uint32_t rel = sm.relBase[c] + q0 + p;
+            const K x = src[nd.off + (rel < nd.n ? rel : 0u)];     // guard: inside the node
             atomicAdd(&hist[tile_bucket(x, lo, sh, sm)], 1u);
         }
         __syncthreads();
