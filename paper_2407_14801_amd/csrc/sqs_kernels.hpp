@@ -402,20 +402,27 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
         if (!sorted) block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm);
         // this thread's pivots and strict flags, as 16-byte loads of its
         // aligned, padded slice (entries past npiv are not used); for 32-bit
-        // keys issued here, so that they arrive while the column is stored
-        // (64-bit keys have no registers to spare: loaded before the search)
-        constexpr int PV4 = PPT * (int)sizeof(K) / 16;
+        // keys issued here, so that they arrive while the column is stored.
+        // 64-bit keys have no registers to spare: they load and search the
+        // slice in two halves of 8, each just before its search.
+        constexpr int PH = sizeof(K) == 4 ? PPT : PPT / 2;
+        constexpr int PV4 = PH * (int)sizeof(K) / 16;
         uint4 praw[PV4];
         uint4 sraw = make_uint4(0u, 0u, 0u, 0u);
-        auto load_pivots = [&] {
-            if (t0 < npiv) {
-                const uint4 *p4 = reinterpret_cast<const uint4 *>(b.piv + nd.piv + t0);
+        auto load_pivots = [&](uint32_t th) {
+            if (th < npiv) {
+                const uint4 *p4 = reinterpret_cast<const uint4 *>(b.piv + nd.piv + th);
 #pragma unroll
                 for (int v4 = 0; v4 < PV4; ++v4) praw[v4] = p4[v4];
-                sraw = *reinterpret_cast<const uint4 *>(b.strict + nd.piv + t0);
+                if (PH == 16) {
+                    sraw = *reinterpret_cast<const uint4 *>(b.strict + nd.piv + th);
+                } else {
+                    const uint2 s2 = *reinterpret_cast<const uint2 *>(b.strict + nd.piv + th);
+                    sraw = make_uint4(s2.x, s2.y, 0u, 0u);
+                }
             }
         };
-        if (sizeof(K) == 4) load_pivots();
+        if (sizeof(K) == 4) load_pivots(t0);
         if (!sorted) {
 #pragma unroll
             for (int r = 0; r < SORT_IPT; ++r) {
@@ -433,58 +440,62 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
             if (r < R && p < len) { if (sizeof(K) == 4) sm.k32[p] = (uint32_t)kk[r]; else sm.k64[p] = (uint64_t)kk[r]; }
         }
         __syncthreads();
-        if (sizeof(K) != 4) load_pivots();
         // Each pivot's position in the sorted column (keys at or below it).
         // The slice's first and last pivot are searched over the whole
         // column, the others inside that bracket; the searches of one step
         // are independent, so their LDS reads overlap.
-        const uint32_t nq = t0 < npiv ? min((uint32_t)PPT, npiv - t0) : 0u;
-        if (nq > 0) {
-            K pf = (K)0, pl = (K)0;
-            bool sf = false, sl = false;
 #pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-                if (q == 0) { pf = piv_of<K>(praw, q); sf = strict_of(sraw, q); }
-                if (q == (int)nq - 1) { pl = piv_of<K>(praw, q); sl = strict_of(sraw, q); }
-            }
-            uint32_t af = 0, ef = len, al = 0, el = len;
-            while (af < ef || al < el) {
-                if (af < ef) {
-                    const uint32_t mid = (af + ef) >> 1;
-                    if (le_pivot(col_key<K>(sm, mid), pf, sf)) af = mid + 1; else ef = mid;
+        for (int h = 0; h < PPT / PH; ++h) {
+            const uint32_t th = t0 + h * PH;
+            if (sizeof(K) != 4) load_pivots(th);
+            const uint32_t nq = th < npiv ? min((uint32_t)PH, npiv - th) : 0u;
+            if (nq > 0) {
+                K pf = (K)0, pl = (K)0;
+                bool sf = false, sl = false;
+#pragma unroll
+                for (int q = 0; q < PH; ++q) {
+                    if (q == 0) { pf = piv_of<K>(praw, q); sf = strict_of(sraw, q); }
+                    if (q == (int)nq - 1) { pl = piv_of<K>(praw, q); sl = strict_of(sraw, q); }
                 }
-                if (al < el) {
-                    const uint32_t mid = (al + el) >> 1;
-                    if (le_pivot(col_key<K>(sm, mid), pl, sl)) al = mid + 1; else el = mid;
-                }
-            }
-            uint32_t A[PPT], E[PPT];
-#pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-                const bool inner = q > 0 && q + 1 < (int)nq;
-                A[q] = inner ? af : 0u;
-                E[q] = inner ? al : 0u;
-            }
-            bool more = true;
-            while (more) {
-                more = false;
-#pragma unroll
-                for (int q = 1; q + 1 < PPT; ++q) {
-                    if (A[q] < E[q]) {
-                        const uint32_t mid = (A[q] + E[q]) >> 1;
-                        if (le_pivot(col_key<K>(sm, mid), piv_of<K>(praw, q), strict_of(sraw, q))) A[q] = mid + 1;
-                        else E[q] = mid;
-                        more |= A[q] < E[q];
+                uint32_t af = 0, ef = len, al = 0, el = len;
+                while (af < ef || al < el) {
+                    if (af < ef) {
+                        const uint32_t mid = (af + ef) >> 1;
+                        if (le_pivot(col_key<K>(sm, mid), pf, sf)) af = mid + 1; else ef = mid;
+                    }
+                    if (al < el) {
+                        const uint32_t mid = (al + el) >> 1;
+                        if (le_pivot(col_key<K>(sm, mid), pl, sl)) al = mid + 1; else el = mid;
                     }
                 }
-            }
+                uint32_t A[PH], E[PH];
 #pragma unroll
-            for (int q = 0; q < PPT; ++q) {
-                if (q < (int)nq) {
-                    const uint32_t t = t0 + q;
-                    const uint32_t a = q == 0 ? af : (q == (int)nq - 1 ? al : A[q]);
-                    P[q] += a;
-                    if ((t + 1) % TB == 0) b.srcOff[nd.src + (uint64_t)((t + 1) / TB) * m + i] = a;
+                for (int q = 0; q < PH; ++q) {
+                    const bool inner = q > 0 && q + 1 < (int)nq;
+                    A[q] = inner ? af : 0u;
+                    E[q] = inner ? al : 0u;
+                }
+                bool more = true;
+                while (more) {
+                    more = false;
+#pragma unroll
+                    for (int q = 1; q + 1 < PH; ++q) {
+                        if (A[q] < E[q]) {
+                            const uint32_t mid = (A[q] + E[q]) >> 1;
+                            if (le_pivot(col_key<K>(sm, mid), piv_of<K>(praw, q), strict_of(sraw, q))) A[q] = mid + 1;
+                            else E[q] = mid;
+                            more |= A[q] < E[q];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < PH; ++q) {
+                    if (q < (int)nq) {
+                        const uint32_t t = th + q;
+                        const uint32_t a = q == 0 ? af : (q == (int)nq - 1 ? al : A[q]);
+                        P[h * PH + q] += a;
+                        if ((t + 1) % TB == 0) b.srcOff[nd.src + (uint64_t)((t + 1) / TB) * m + i] = a;
+                    }
                 }
             }
         }
