@@ -87,6 +87,7 @@ constexpr int CTR_WORDS = 3 * NCLS + 4;
 // sample attempts of the Alg. 1 pivot rule before a node gives up
 constexpr uint32_t ALG1_ATTEMPTS = 64;
 constexpr uint32_t COPY_CH = 32768;           // keys per piece of a single-value bucket copy
+constexpr uint32_t CP_NT = 1024;              // threads of a copy work-group
 constexpr uint32_t BIG_CAP = 16 * SORT_CAP;  // largest automatic cut-off: 262144 keys
 
 // A base-case sort item, resolved: its first slot in A and D, its size and
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(SORT_NT) void k_sort_pivots_big(Batch<K> b, const K
             k[r] = (K)0;
             if (r < R && p < cnt) k[r] = a == 0 ? b.piv[nd.piv + p] : A[nd.off + pivot_draw_alg1(nd.key, a, p, nd.n)];
         }
+        wait_vmem();
         __syncthreads();
         block_sort<K, false, SORT_NW, SORT_IPT>(k, v, cnt, sm);
 #pragma unroll
@@ -1319,15 +1321,27 @@ __global__ __launch_bounds__(CL_NT) void k_classify(Batch<K> b, uint32_t cutoff)
 // Single-value buckets: copy A -> D (one work-group per piece of at most
 // COPY_CH keys, persistent).
 template <class K, bool HV>
-__global__ __launch_bounds__(256) void k_bucket_copy(Batch<K> b, const K *A, const uint32_t *VA, K *D, uint32_t *VD)
+__global__ __launch_bounds__(CP_NT) void k_bucket_copy(Batch<K> b, const K *A, const uint32_t *VA, K *D, uint32_t *VD)
 {
     const uint32_t cnt = min(b.ctr[CLS_COPY], b.cap[CLS_COPY]);
+    constexpr uint32_t U = 8;                        // loads in flight per thread
     for (uint32_t it = blockIdx.x; it < cnt; it += gridDim.x) {
         const BucketItem e = b.list[CLS_COPY][it];
         const uint64_t base = b.nodes[e.node].off + e.lo;
-        for (uint32_t p = threadIdx.x; p < e.size; p += 256) {
-            D[base + p] = A[base + p];
-            if (HV) VD[base + p] = VA[base + p];
+        for (uint32_t p0 = 0; p0 < e.size; p0 += CP_NT * U) {
+            K x[U];
+            uint32_t y[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t p = p0 + u * CP_NT + threadIdx.x;
+                if (p < e.size) { x[u] = A[base + p]; if (HV) y[u] = VA[base + p]; }
+            }
+            wait_vmem();
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t p = p0 + u * CP_NT + threadIdx.x;
+                if (p < e.size) { D[base + p] = x[u]; if (HV) VD[base + p] = y[u]; }
+            }
         }
     }
 }

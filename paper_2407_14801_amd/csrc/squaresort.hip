@@ -493,7 +493,7 @@ template <class K, bool HV> struct Engine {
         launch("k_classify", bucS[N], [&] { k_classify<K><<<cdiv(bucS[N], CL_NT), CL_NT, 0, st>>>(b, cutoff); });
         launch("k_order_lists", bucS[N], [&] {
             k_order_lists<K><<<2, 1024, 0, st>>>(b, shift_of(SORT_CAP), shift_of(cutoff)); });
-        launch("k_bucket_copy", keysTot, [&] { k_bucket_copy<K, HV><<<512, 256, 0, st>>>(b, A, VA, D, VD); });
+        launch("k_bucket_copy", keysTot, [&] { k_bucket_copy<K, HV><<<512, CP_NT, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket_w", keysTot, [&] {
             k_bucket_small<K, HV><<<std::min<uint32_t>(cdiv(capSmall, SM_NW), 2048), SM_NW * WAVE, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket4", keysTot, [&] {
