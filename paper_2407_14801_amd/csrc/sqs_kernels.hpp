@@ -11,14 +11,21 @@
 //                     and bucket j the keys of g in j
 //   k_colscan         prefix of the group counts over groups, bucket totals
 //   k_bucket_start    exclusive scan of totals: bucket j = [bs[j], bs[j+1])
+//   k_tile_plan       keys per SkewTranspose tile; heavy tiles' chunks listed
 //   k_transpose       SkewTranspose D -> A over (column group x bucket block)
-//                     tiles, staged through LDS
-//   k_classify        per bucket: empty / single value / small / mid / internal
-//   k_bucket_*        copy single-value buckets, sort small (one wave) and mid
-//                     (one work-group) buckets A -> D; internal buckets form
-//                     the next batch
+//                     tiles, staged through LDS; k_transpose_heavy takes the
+//                     chunks of heavy tiles (decoupled look-back)
+//   k_classify        per bucket: empty / single value / small / mid4 / mid /
+//                     big / internal, with a resolved span per sorted bucket
+//   k_order_lists     largest-first claim order of the mid and big spans
+//   k_bucket_*        copy single-value buckets, sort small (one wave), mid4
+//                     and mid (one work-group) and big (MSD splits) buckets
+//                     A -> D; internal buckets form the next batch
 // Columns and buckets of at most WCAP keys are sorted by one wave each; the
-// block kernels handle up to CAP keys.
+// block kernels handle up to their LDS capacity.  Also here: the grid-wide
+// split of large base-case segments (k_base_*), the HBM count of columns
+// longer than one LDS sort (k_blockoff, k_tilecount), the Alg. 1 node minima
+// (k_node_min) and the tree digest (k_digest*).
 #pragma once
 
 #include "sqs_device.hpp"
