@@ -306,9 +306,14 @@ __device__ inline uint32_t digit8(uint64_t x, int sh)
 // must be clear on entry (tables_clear + barrier); they are clear again on
 // return.  Ends with a barrier unless it returns at once (count <= 1 or a
 // single key value).  On return only positions < count hold meaningful keys.
+// With passes_out (and lo_out), the passes run and the offset: when at least
+// one pass ran for keys without values, sm.s.buf holds the sorted keys minus
+// lo (word 0 for 64-bit keys), and sm.s.tab[0].off[d] is the first position
+// of the keys whose last-pass digit is d (padding sorts last).
 template <class K, bool HV, int NW, int IPT>
 __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, SortSmem<NW, IPT> &sm,
-                           bool bounded = false, K blo = (K)0, K bhi = (K)0)
+                           bool bounded = false, K blo = (K)0, K bhi = (K)0, K *lo_out = nullptr,
+                           int *passes_out = nullptr)
 {
     using T = KeyT<K>;
     const int R = block_rows<NW, IPT>(count);
@@ -322,8 +327,11 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
             if (r < nrows && bpos(r, R) < count) { lo = k[r] < lo ? k[r] : lo; hi = k[r] > hi ? k[r] : hi; }
         block_minmax<K, NW>(lo, hi, sm.red32, sm.red64);
     }
+    if (passes_out) *passes_out = 0;
     if (count <= 1 || !(lo < hi)) return;          // already in order (uniform branch)
     const int passes = (T::bitlen((K)(hi - lo)) + 7) / 8;
+    if (lo_out) *lo_out = lo;
+    if (passes_out) *passes_out = passes;
 #pragma unroll
     for (int r = 0; r < IPT; ++r)
         if (r < nrows) k[r] = bpos(r, R) < count ? (K)(k[r] - lo) : (K)T::MAXV;

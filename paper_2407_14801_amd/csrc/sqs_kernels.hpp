@@ -408,7 +408,15 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
         }
         wait_vmem();
         __syncthreads();
-        if (!sorted) block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm);
+        K clo = (K)0;
+        int passes = 0;
+        if (!sorted) block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm, false, (K)0, (K)0, &clo, &passes);
+        // 32-bit keys without values: the sorted column (minus clo) is still in
+        // the exchange buffer and the last pass's digit starts in the tables,
+        // so the count searches there and narrows each whole-column search to
+        // the keys of the pivot's last-pass digit
+        const bool fast = sizeof(K) == 4 && !HV && !sorted && passes > 0;
+        const int fsh = 8 * (passes - 1);
         // this thread's pivots and strict flags, as 16-byte loads of its
         // aligned, padded slice (entries past npiv are not used); for 32-bit
         // keys issued here, so that they arrive while the column is stored.
@@ -442,17 +450,39 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
                 }
             }
         }
-        __syncthreads();
+        if (!fast) {
+            __syncthreads();
 #pragma unroll
-        for (int r = 0; r < SORT_IPT; ++r) {
-            const uint32_t p = bpos(r, R);
-            if (r < R && p < len) { if (sizeof(K) == 4) sm.k32[p] = (uint32_t)kk[r]; else sm.k64[p] = (uint64_t)kk[r]; }
+            for (int r = 0; r < SORT_IPT; ++r) {
+                const uint32_t p = bpos(r, R);
+                if (r < R && p < len) { if (sizeof(K) == 4) sm.k32[p] = (uint32_t)kk[r]; else sm.k64[p] = (uint64_t)kk[r]; }
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        // key at position q of the sorted column, and a pivot in the same
+        // space (below the column minimum: 0 taken as strict, below every key)
+        auto ck = [&](uint32_t q) -> K { return fast ? (K)sm.s.buf[q] : col_key<K>(sm, q); };
+        auto tpiv = [&](K p, bool &st) -> K {
+            if (!fast) return p;
+            if (p < clo) { st = true; return (K)0; }
+            return (K)(p - clo);
+        };
+        // whole-column search range of a pivot (fast: its last-pass digit)
+        auto range = [&](K p, uint32_t &a, uint32_t &e) {
+            a = 0;
+            e = len;
+            if (fast) {
+                const K d = (K)(p >> fsh);
+                if (d > (K)255) { a = len; return; }                  // above every key
+                a = min(sm.s.tab[0].off[(uint32_t)d], len);
+                e = d < (K)255 ? min(sm.s.tab[0].off[(uint32_t)d + 1], len) : len;
+            }
+        };
         // Each pivot's position in the sorted column (keys at or below it).
         // The slice's first and last pivot are searched over the whole
-        // column, the others inside that bracket; the searches of one step
-        // are independent, so their LDS reads overlap.
+        // column (or their digit's range), the others inside that bracket;
+        // the searches of one step are independent, so their LDS reads
+        // overlap.
 #pragma unroll
         for (int h = 0; h < PPT / PH; ++h) {
             const uint32_t th = t0 + h * PH;
@@ -463,18 +493,20 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
                 bool sf = false, sl = false;
 #pragma unroll
                 for (int q = 0; q < PH; ++q) {
-                    if (q == 0) { pf = piv_of<K>(praw, q); sf = strict_of(sraw, q); }
-                    if (q == (int)nq - 1) { pl = piv_of<K>(praw, q); sl = strict_of(sraw, q); }
+                    if (q == 0) { sf = strict_of(sraw, q); pf = tpiv(piv_of<K>(praw, q), sf); }
+                    if (q == (int)nq - 1) { sl = strict_of(sraw, q); pl = tpiv(piv_of<K>(praw, q), sl); }
                 }
-                uint32_t af = 0, ef = len, al = 0, el = len;
+                uint32_t af, ef, al, el;
+                range(pf, af, ef);
+                range(pl, al, el);
                 while (af < ef || al < el) {
                     if (af < ef) {
                         const uint32_t mid = (af + ef) >> 1;
-                        if (le_pivot(col_key<K>(sm, mid), pf, sf)) af = mid + 1; else ef = mid;
+                        if (le_pivot(ck(mid), pf, sf)) af = mid + 1; else ef = mid;
                     }
                     if (al < el) {
                         const uint32_t mid = (al + el) >> 1;
-                        if (le_pivot(col_key<K>(sm, mid), pl, sl)) al = mid + 1; else el = mid;
+                        if (le_pivot(ck(mid), pl, sl)) al = mid + 1; else el = mid;
                     }
                 }
                 uint32_t A[PH], E[PH];
@@ -491,7 +523,9 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
                     for (int q = 1; q + 1 < PH; ++q) {
                         if (A[q] < E[q]) {
                             const uint32_t mid = (A[q] + E[q]) >> 1;
-                            if (le_pivot(col_key<K>(sm, mid), piv_of<K>(praw, q), strict_of(sraw, q))) A[q] = mid + 1;
+                            bool sq = strict_of(sraw, q);
+                            const K pq = tpiv(piv_of<K>(praw, q), sq);
+                            if (le_pivot(ck(mid), pq, sq)) A[q] = mid + 1;
                             else E[q] = mid;
                             more |= A[q] < E[q];
                         }
