@@ -378,14 +378,18 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
 // ---------------------------------------------------------------- wave sort
 // One wave sorts up to 64*R keys at positions r*64 + lane with its own table
 // and buffer; no work-group barrier.  The table must be clear on entry and is
-// clear on return.
+// clear on return (its counts; the offsets of the last pass remain).  With
+// passes_out and lo_out as in block_sort: after at least one pass over keys
+// without values, sm.buf holds the sorted keys minus lo (word 0) and
+// sm.tab.off[d] the first position of last-pass digit d.
 template <int R> struct WaveSmem {
     RankTab<256> tab;
     uint32_t buf[R * WAVE];
 };
 
 template <class K, bool HV, int R>
-__device__ void wave_sort(K (&k)[R], uint32_t (&v)[R], uint32_t count, WaveSmem<R> &sm)
+__device__ void wave_sort(K (&k)[R], uint32_t (&v)[R], uint32_t count, WaveSmem<R> &sm, K *lo_out = nullptr,
+                          int *passes_out = nullptr)
 {
     using T = KeyT<K>;
     const uint32_t l = lane_id();
@@ -396,8 +400,11 @@ __device__ void wave_sort(K (&k)[R], uint32_t (&v)[R], uint32_t count, WaveSmem<
         if (r < nrows && r * WAVE + l < count) { lo = k[r] < lo ? k[r] : lo; hi = k[r] > hi ? k[r] : hi; }
     lo = wave_min(lo);
     hi = wave_max(hi);
+    if (passes_out) *passes_out = 0;
     if (count <= 1 || !(lo < hi)) return;
     const int passes = (T::bitlen((K)(hi - lo)) + 7) / 8;
+    if (lo_out) *lo_out = lo;
+    if (passes_out) *passes_out = passes;
     // offset keys; padding gets the all-ones key (digit 255 in every pass)
 #pragma unroll
     for (int r = 0; r < R; ++r)

@@ -641,8 +641,10 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
             kk[r] = ok ? (sorted ? dst[base + p] : src[base + p]) : (K)0;
             if (HV) vv[r] = ok && !sorted ? vsrc[base + p] : 0u;
         }
+        K clo = (K)0;
+        int passes = 0;
         if (!sorted) {
-            wave_sort<K, HV, WR>(kk, vv, len, wsm[w]);
+            wave_sort<K, HV, WR>(kk, vv, len, wsm[w], &clo, &passes);
 #pragma unroll
             for (int r = 0; r < WR; ++r) {
                 const uint32_t p = r * WAVE + l;
@@ -652,13 +654,36 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
                 }
             }
         }
+        // 32-bit keys without values: the sorted column (minus clo) is still
+        // in the wave's buffer and the last pass's digit starts in its table;
+        // the count searches there, each whole-column search narrowed to the
+        // pivot's digit (as in k_colsort_big)
+        const bool fast = sizeof(K) == 4 && !HV && !sorted && passes > 0;
+        const int fsh = 8 * (passes - 1);
         wave_lds_sync();
+        if (!fast) {
 #pragma unroll
-        for (int r = 0; r < WR; ++r) {
-            const uint32_t p = r * WAVE + l;
-            if (p < len) ck[p] = kk[r];
+            for (int r = 0; r < WR; ++r) {
+                const uint32_t p = r * WAVE + l;
+                if (p < len) ck[p] = kk[r];
+            }
+            wave_lds_sync();
         }
-        wave_lds_sync();
+        auto tpiv = [&](K p, bool &st) -> K {
+            if (!fast) return p;
+            if (p < clo) { st = true; return (K)0; }
+            return (K)(p - clo);
+        };
+        auto range = [&](K p, uint32_t &a, uint32_t &e) {
+            a = 0;
+            e = len;
+            if (fast) {
+                const K d = (K)(p >> fsh);
+                if (d > (K)255) { a = len; return; }
+                a = min(wsm[w].tab.off[(uint32_t)d], len);
+                e = d < (K)255 ? min(wsm[w].tab.off[(uint32_t)d + 1], len) : len;
+            }
+        };
         // positions of the lane's first and last pivot over the column, the
         // others inside that bracket (independent searches step together)
         if (nq > 0) {
@@ -666,10 +691,12 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
             bool sf = false, sl = false;
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
-                if (q == 0) { pf = piv_of<K>(praw, q); sf = strict_of(sraw, q); }
-                if (q == (int)nq - 1) { pl = piv_of<K>(praw, q); sl = strict_of(sraw, q); }
+                if (q == 0) { sf = strict_of(sraw, q); pf = tpiv(piv_of<K>(praw, q), sf); }
+                if (q == (int)nq - 1) { sl = strict_of(sraw, q); pl = tpiv(piv_of<K>(praw, q), sl); }
             }
-            uint32_t af = 0, ef = len, al = 0, el = len;
+            uint32_t af, ef, al, el;
+            range(pf, af, ef);
+            range(pl, al, el);
             while (af < ef || al < el) {
                 if (af < ef) {
                     const uint32_t mid = (af + ef) >> 1;
@@ -694,7 +721,9 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
                 for (int q = 1; q + 1 < PPT; ++q) {
                     if (A[q] < E[q]) {
                         const uint32_t mid = (A[q] + E[q]) >> 1;
-                        if (le_pivot(ck[mid], piv_of<K>(praw, q), strict_of(sraw, q))) A[q] = mid + 1;
+                        bool sq = strict_of(sraw, q);
+                        const K pq = tpiv(piv_of<K>(praw, q), sq);
+                        if (le_pivot(ck[mid], pq, sq)) A[q] = mid + 1;
                         else E[q] = mid;
                         more |= A[q] < E[q];
                     }
