@@ -375,6 +375,140 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
         if (r < nrows) k[r] = (K)(k[r] + lo);
 }
 
+// ------------------------------------------------------------ bin sort (u32)
+// Bitonic network over N registers (N a power of two), ascending.
+template <int N>
+__device__ inline void bitonic_regs(uint32_t (&x)[N])
+{
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint32_t a = x[i], c = x[l];
+                    const bool up = (i & k) == 0;
+                    x[i] = up ? min(a, c) : max(a, c);
+                    x[l] = up ? max(a, c) : min(a, c);
+                }
+            }
+        }
+    }
+}
+
+// sorts the c <= N keys at buf[s ..) (lanes with c < 2 leave theirs alone)
+template <int N>
+__device__ inline void bin_net(uint32_t *buf, uint32_t s, uint32_t c)
+{
+    uint32_t x[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) x[j] = (uint32_t)j < c ? buf[s + j] : 0xffffffffu;
+    bitonic_regs<N>(x);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if ((uint32_t)j < c && c > 1) buf[s + j] = x[j];
+}
+
+constexpr int BIN_BITS = 11;                 // at most 2048 bins of the key range
+constexpr int BIN_CAP = 1 << BIN_BITS;
+constexpr int BIN_NET = 32;                  // largest bin sorted in registers
+
+// Sort of `count` 32-bit keys without values (block_rows / bpos layout) by
+// bins of the key range: bin = (key - lo) >> sh for the fewest bins of equal
+// width, at most 2^BIN_BITS and about count/8; every key takes its place in
+// its bin from an LDS atomic add (equal keys are interchangeable when no
+// values ride along, so the order among them does not matter), a scan lays
+// the bins out, and every bin of at most BIN_NET keys is sorted in registers
+// by one thread.  Returns 0 when nothing is to be sorted (count <= 1 or one
+// key value), 2 when a bin holds more than BIN_NET keys (nothing has been
+// moved; the digit tables are not clear), and 1 after sorting: then k holds
+// the sorted keys, sm.s.buf the sorted keys minus lo, and the words
+// bin_starts(sm)[0 .. nbin) the first position of every bin.  No LDS write
+// is pending on return.
+template <int NW, int IPT>
+__device__ inline uint32_t *bin_starts(SortSmem<NW, IPT> &sm)
+{
+    return reinterpret_cast<uint32_t *>(sm.s.tab) + BIN_CAP;
+}
+
+template <int NW, int IPT>
+__device__ int bin_sort(uint32_t (&k)[IPT], uint32_t count, SortSmem<NW, IPT> &sm, uint32_t &lo_out,
+                        int &sh_out, uint32_t &nbin_out)
+{
+    static_assert(BIN_CAP <= 2 * NW * WAVE, "two bins per thread");
+    static_assert(2 * BIN_CAP * 4 <= (int)sizeof(sm.s.tab), "bin counts and starts fit the tables");
+    constexpr int NT = NW * WAVE;
+    const int R = block_rows<NW, IPT>(count);
+    const int nrows = wave_rows_of(count, R);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(sm.s.tab);
+    uint32_t *st = cnt + BIN_CAP;
+    uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (r < nrows && bpos(r, R) < count) { lo = min(lo, k[r]); hi = max(hi, k[r]); }
+    for (uint32_t i = threadIdx.x; i < (uint32_t)BIN_CAP; i += NT) cnt[i] = 0u;
+    block_minmax<uint32_t, NW>(lo, hi, sm.red32, sm.red64);
+    if (count <= 1 || !(lo < hi)) return 0;
+    const int nb = min(max(KeyT<uint32_t>::bitlen(count) - 3, 1), BIN_BITS);
+    const int kb = KeyT<uint32_t>::bitlen(hi - lo);
+    const int sh = kb > nb ? kb - nb : 0;
+    const uint32_t nbin = ((hi - lo) >> sh) + 1u;
+    uint32_t rk[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (r < nrows && bpos(r, R) < count) rk[r] = atomicAdd(&cnt[(k[r] - lo) >> sh], 1u);
+    __syncthreads();
+    // bins 2t and 2t + 1 belong to thread t
+    const uint32_t t = threadIdx.x, w = wave_id();
+    const uint32_t c0 = 2 * t < nbin ? cnt[2 * t] : 0u, c1 = 2 * t + 1 < nbin ? cnt[2 * t + 1] : 0u;
+    const uint32_t tot = c0 + c1;
+    const uint32_t incl = wave_incl_scan(tot);
+    const bool over = __ballot(c0 > (uint32_t)BIN_NET || c1 > (uint32_t)BIN_NET) != 0ull;
+    if (lane_id() == WAVE - 1) { sm.wsum[w] = incl; sm.red32[w] = over ? 1u : 0u; }
+    __syncthreads();
+    uint32_t run = incl - tot;
+    bool any = false;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+        if ((uint32_t)ww < w) run += sm.wsum[ww];
+        any |= sm.red32[ww] != 0u;
+    }
+    if (any) return 2;                             // uniform over the work-group
+    if (2 * t < nbin) st[2 * t] = run;
+    if (2 * t + 1 < nbin) st[2 * t + 1] = run + c0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (r < nrows && bpos(r, R) < count) {
+            const uint32_t x = k[r] - lo;
+            sm.s.buf[st[x >> sh] + rk[r]] = x;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < BIN_CAP / NT; ++it) {
+        const uint32_t bb = t + (uint32_t)it * NT;
+        const uint32_t c = bb < nbin ? cnt[bb] : 0u;
+        const uint32_t s = bb < nbin ? st[bb] : 0u;
+        const uint32_t cm = wave_max(c);               // uniform within the wave
+        if (cm <= 1u) continue;
+        if (cm <= 8u) bin_net<8>(sm.s.buf, s, c);
+        else if (cm <= 16u) bin_net<16>(sm.s.buf, s, c);
+        else bin_net<32>(sm.s.buf, s, c);
+    }
+    __syncthreads();
+    // every row (positions past count read stale words of the buffer, which
+    // stays in bounds: bpos(r, R) < NW * IPT * 64), so that no old key stays
+    // live across the bin sorts
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) k[r] = sm.s.buf[bpos(r, R)] + lo;
+    lo_out = lo;
+    sh_out = sh;
+    nbin_out = nbin;
+    return 1;
+}
+
 // ---------------------------------------------------------------- wave sort
 // One wave sorts up to 64*R keys at positions r*64 + lane with its own table
 // and buffer; no work-group barrier.  The table must be clear on entry and is

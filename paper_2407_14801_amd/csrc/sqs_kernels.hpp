@@ -410,13 +410,33 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
         __syncthreads();
         K clo = (K)0;
         int passes = 0;
-        if (!sorted) block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm, false, (K)0, (K)0, &clo, &passes);
+        // 32-bit keys without values sort by bins of the key range; a column
+        // with a crowded bin (and every other key type) by LSD radix passes
+        int binned = 2;
+        int rsh = 0;
+        uint32_t rlast = 255u;
+        if constexpr (sizeof(K) == 4 && !HV) {
+            if (!sorted) {
+                uint32_t blo = 0u, nbin = 0u;
+                binned = bin_sort<SORT_NW, SORT_IPT>(kk, len, sm, blo, rsh, nbin);
+                if (binned == 1) { clo = (K)blo; rlast = nbin - 1u; }
+                if (binned == 2) {
+                    tables_clear<SORT_NW, 256>(sm.s.tab);
+                    __syncthreads();
+                }
+            }
+        }
+        if (!sorted && binned == 2) {
+            block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm, false, (K)0, (K)0, &clo, &passes);
+            rsh = 8 * (passes - 1);
+        }
         // 32-bit keys without values: the sorted column (minus clo) is still in
-        // the exchange buffer and the last pass's digit starts in the tables,
-        // so the count searches there and narrows each whole-column search to
-        // the keys of the pivot's last-pass digit
-        const bool fast = sizeof(K) == 4 && !HV && !sorted && passes > 0;
-        const int fsh = 8 * (passes - 1);
+        // the exchange buffer, and the start of every bin (or of every
+        // last-pass digit) in the tables' space, so the count searches there
+        // and narrows each whole-column search to the keys of the pivot's bin
+        // (digit)
+        const bool fast = sizeof(K) == 4 && !HV && !sorted && (passes > 0 || binned == 1);
+        const uint32_t *rtab = binned == 1 ? bin_starts(sm) : sm.s.tab[0].off;
         // this thread's pivots and strict flags, as 16-byte loads of its
         // aligned, padded slice (entries past npiv are not used); for 32-bit
         // keys issued here, so that they arrive while the column is stored.
@@ -467,15 +487,15 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
             if (p < clo) { st = true; return (K)0; }
             return (K)(p - clo);
         };
-        // whole-column search range of a pivot (fast: its last-pass digit)
+        // whole-column search range of a pivot (fast: its bin or last-pass digit)
         auto range = [&](K p, uint32_t &a, uint32_t &e) {
             a = 0;
             e = len;
             if (fast) {
-                const K d = (K)(p >> fsh);
-                if (d > (K)255) { a = len; return; }                  // above every key
-                a = min(sm.s.tab[0].off[(uint32_t)d], len);
-                e = d < (K)255 ? min(sm.s.tab[0].off[(uint32_t)d + 1], len) : len;
+                const K d = (K)(p >> rsh);
+                if (d > (K)rlast) { a = len; return; }                // above every key
+                a = min(rtab[(uint32_t)d], len);
+                e = d < (K)rlast ? min(rtab[(uint32_t)d + 1], len) : len;
             }
         };
         // Each pivot's position in the sorted column (keys at or below it).
