@@ -411,47 +411,63 @@ __device__ inline void bin_net(uint32_t *buf, uint32_t s, uint32_t c)
         if ((uint32_t)j < c && c > 1) buf[s + j] = x[j];
 }
 
-constexpr int BIN_BITS = 11;                 // at most 2048 bins of the key range
-constexpr int BIN_CAP = 1 << BIN_BITS;
-constexpr int BIN_NET = 32;                  // largest bin sorted in registers
+constexpr int BIN_NET = 16;                  // largest bin sorted in registers (a 32-key
+                                             // network needs twice the registers)
 
 // Sort of `count` 32-bit keys without values (block_rows / bpos layout) by
 // bins of the key range: bin = (key - lo) >> sh for the fewest bins of equal
-// width, at most 2^BIN_BITS and about count/8; every key takes its place in
+// width, about count/4 and at most bin_cap (uniform keys overfill a bin of
+// 16 about once in a million bins; bins of one key value need no sort and
+// have no size limit); every key takes its place in
 // its bin from an LDS atomic add (equal keys are interchangeable when no
 // values ride along, so the order among them does not matter), a scan lays
 // the bins out, and every bin of at most BIN_NET keys is sorted in registers
-// by one thread.  Returns 0 when nothing is to be sorted (count <= 1 or one
-// key value), 2 when a bin holds more than BIN_NET keys (nothing has been
+// by one thread.  With `bounded`, [blo, bhi] is a caller-known range of the
+// keys (as in block_sort).  Returns 0 when nothing is to be sorted (count <= 1
+// or one key value), 2 when a bin holds more than BIN_NET keys (nothing has been
 // moved; the digit tables are not clear), and 1 after sorting: then k holds
 // the sorted keys, sm.s.buf the sorted keys minus lo, and the words
 // bin_starts(sm)[0 .. nbin) the first position of every bin.  No LDS write
 // is pending on return.
+// bins of one sort: counts and starts share the digit tables' space
+template <int NW, int IPT> constexpr int bin_cap()
+{
+    return (int)sizeof(RankTab<256>) * NW / 8 < 4096 ? (int)sizeof(RankTab<256>) * NW / 8 : 4096;
+}
 template <int NW, int IPT>
 __device__ inline uint32_t *bin_starts(SortSmem<NW, IPT> &sm)
 {
-    return reinterpret_cast<uint32_t *>(sm.s.tab) + BIN_CAP;
+    return reinterpret_cast<uint32_t *>(sm.s.tab) + bin_cap<NW, IPT>();
 }
 
 template <int NW, int IPT>
 __device__ int bin_sort(uint32_t (&k)[IPT], uint32_t count, SortSmem<NW, IPT> &sm, uint32_t &lo_out,
-                        int &sh_out, uint32_t &nbin_out)
+                        int &sh_out, uint32_t &nbin_out, bool bounded = false, uint32_t blo = 0u,
+                        uint32_t bhi = 0u)
 {
-    static_assert(BIN_CAP <= 2 * NW * WAVE, "two bins per thread");
-    static_assert(2 * BIN_CAP * 4 <= (int)sizeof(sm.s.tab), "bin counts and starts fit the tables");
     constexpr int NT = NW * WAVE;
+    constexpr int BIN_CAP = bin_cap<NW, IPT>();
+    constexpr int BPT = BIN_CAP / NT;              // bins BPT*t .. BPT*t + BPT - 1 belong to thread t
+    static_assert(BPT >= 1 && BPT * NT == BIN_CAP, "whole bins per thread");
+    static_assert(2 * BIN_CAP * 4 <= (int)sizeof(sm.s.tab), "bin counts and starts fit the tables");
     const int R = block_rows<NW, IPT>(count);
     const int nrows = wave_rows_of(count, R);
     uint32_t *cnt = reinterpret_cast<uint32_t *>(sm.s.tab);
     uint32_t *st = cnt + BIN_CAP;
-    uint32_t lo = 0xffffffffu, hi = 0u;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r)
-        if (r < nrows && bpos(r, R) < count) { lo = min(lo, k[r]); hi = max(hi, k[r]); }
+    uint32_t lo = blo, hi = bhi;                   // bounded: every key lies in [blo, bhi]
     for (uint32_t i = threadIdx.x; i < (uint32_t)BIN_CAP; i += NT) cnt[i] = 0u;
-    block_minmax<uint32_t, NW>(lo, hi, sm.red32, sm.red64);
+    if (bounded) {
+        __syncthreads();
+    } else {
+        lo = 0xffffffffu;
+        hi = 0u;
+#pragma unroll
+        for (int r = 0; r < IPT; ++r)
+            if (r < nrows && bpos(r, R) < count) { lo = min(lo, k[r]); hi = max(hi, k[r]); }
+        block_minmax<uint32_t, NW>(lo, hi, sm.red32, sm.red64);
+    }
     if (count <= 1 || !(lo < hi)) return 0;
-    const int nb = min(max(KeyT<uint32_t>::bitlen(count) - 3, 1), BIN_BITS);
+    const int nb = min(max(KeyT<uint32_t>::bitlen(count) - 2, 1), KeyT<uint32_t>::bitlen(BIN_CAP) - 1);
     const int kb = KeyT<uint32_t>::bitlen(hi - lo);
     const int sh = kb > nb ? kb - nb : 0;
     const uint32_t nbin = ((hi - lo) >> sh) + 1u;
@@ -460,12 +476,18 @@ __device__ int bin_sort(uint32_t (&k)[IPT], uint32_t count, SortSmem<NW, IPT> &s
     for (int r = 0; r < IPT; ++r)
         if (r < nrows && bpos(r, R) < count) rk[r] = atomicAdd(&cnt[(k[r] - lo) >> sh], 1u);
     __syncthreads();
-    // bins 2t and 2t + 1 belong to thread t
     const uint32_t t = threadIdx.x, w = wave_id();
-    const uint32_t c0 = 2 * t < nbin ? cnt[2 * t] : 0u, c1 = 2 * t + 1 < nbin ? cnt[2 * t + 1] : 0u;
-    const uint32_t tot = c0 + c1;
+    uint32_t c[BPT], tot = 0u;
+    bool big = false;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+        const uint32_t bb = BPT * t + q;
+        c[q] = bb < nbin ? cnt[bb] : 0u;
+        tot += c[q];
+        big |= c[q] > (uint32_t)BIN_NET;
+    }
     const uint32_t incl = wave_incl_scan(tot);
-    const bool over = __ballot(c0 > (uint32_t)BIN_NET || c1 > (uint32_t)BIN_NET) != 0ull;
+    const bool over = sh > 0 && __ballot(big) != 0ull;   // a bin of one key value needs no sort
     if (lane_id() == WAVE - 1) { sm.wsum[w] = incl; sm.red32[w] = over ? 1u : 0u; }
     __syncthreads();
     uint32_t run = incl - tot;
@@ -476,8 +498,11 @@ __device__ int bin_sort(uint32_t (&k)[IPT], uint32_t count, SortSmem<NW, IPT> &s
         any |= sm.red32[ww] != 0u;
     }
     if (any) return 2;                             // uniform over the work-group
-    if (2 * t < nbin) st[2 * t] = run;
-    if (2 * t + 1 < nbin) st[2 * t + 1] = run + c0;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+        if (BPT * t + q < nbin) st[BPT * t + q] = run;
+        run += c[q];
+    }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < IPT; ++r)
@@ -486,16 +511,17 @@ __device__ int bin_sort(uint32_t (&k)[IPT], uint32_t count, SortSmem<NW, IPT> &s
             sm.s.buf[st[x >> sh] + rk[r]] = x;
         }
     __syncthreads();
-#pragma unroll
-    for (int it = 0; it < BIN_CAP / NT; ++it) {
+#pragma unroll 1
+    for (int it = 0; it < BPT; ++it) {
+        if ((uint32_t)it * NT >= nbin) break;         // no bin left (uniform)
         const uint32_t bb = t + (uint32_t)it * NT;
-        const uint32_t c = bb < nbin ? cnt[bb] : 0u;
+        const uint32_t cb = bb < nbin ? cnt[bb] : 0u;
         const uint32_t s = bb < nbin ? st[bb] : 0u;
-        const uint32_t cm = wave_max(c);               // uniform within the wave
+        const uint32_t cm = sh > 0 ? wave_max(cb) : 0u; // uniform within the wave
         if (cm <= 1u) continue;
-        if (cm <= 8u) bin_net<8>(sm.s.buf, s, c);
-        else if (cm <= 16u) bin_net<16>(sm.s.buf, s, c);
-        else bin_net<32>(sm.s.buf, s, c);
+        if (cm <= 4u) bin_net<4>(sm.s.buf, s, cb);
+        else if (cm <= 8u) bin_net<8>(sm.s.buf, s, cb);
+        else bin_net<16>(sm.s.buf, s, cb);
     }
     __syncthreads();
     // every row (positions past count read stale words of the buffer, which
@@ -507,6 +533,43 @@ __device__ int bin_sort(uint32_t (&k)[IPT], uint32_t count, SortSmem<NW, IPT> &s
     sh_out = sh;
     nbin_out = nbin;
     return 1;
+}
+
+// Loads the keys (and values) at from[0 .. count) in block_rows / bpos layout.
+template <class K, bool HV, int NW, int IPT>
+__device__ inline void block_load(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, const K *from,
+                                  const uint32_t *vfrom)
+{
+    const int R = block_rows<NW, IPT>(count);
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = bpos(r, R);
+        const bool ok = r < R && p < count;
+        k[r] = ok ? from[p] : (K)0;
+        if (HV) v[r] = ok ? vfrom[p] : 0u;
+    }
+    wait_vmem();
+}
+
+// Work-group LDS sort of `count` keys known to lie in [blo, bhi], loaded by
+// block_load from `from`, which still holds them: by bins for 32-bit keys
+// without values (when a bin is crowded, the keys are loaded again, so that
+// the registers of the first load are free during the bin sort, and sorted
+// by radix passes), by radix passes otherwise.  The digit tables must be
+// clear on entry; on return they are clear only for the other key types.
+template <class K, bool HV, int NW, int IPT>
+__device__ inline void lds_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, SortSmem<NW, IPT> &sm, K blo,
+                                K bhi, const K *from)
+{
+    if constexpr (sizeof(K) == 4 && !HV) {
+        uint32_t lo, nbin;
+        int sh;
+        if (bin_sort<NW, IPT>(k, count, sm, lo, sh, nbin, true, (uint32_t)blo, (uint32_t)bhi) != 2) return;
+        block_load<K, HV, NW, IPT>(k, v, count, from, nullptr);
+        tables_clear<NW, 256>(sm.s.tab);
+        __syncthreads();
+    }
+    block_sort<K, HV, NW, IPT>(k, v, count, sm, true, blo, bhi);
 }
 
 // ---------------------------------------------------------------- wave sort

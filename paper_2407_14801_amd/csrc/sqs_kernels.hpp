@@ -420,7 +420,8 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
                 uint32_t blo = 0u, nbin = 0u;
                 binned = bin_sort<SORT_NW, SORT_IPT>(kk, len, sm, blo, rsh, nbin);
                 if (binned == 1) { clo = (K)blo; rlast = nbin - 1u; }
-                if (binned == 2) {
+                if (binned == 2) {                     // loaded again: see lds_sort
+                    block_load<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, src + base, nullptr);
                     tables_clear<SORT_NW, 256>(sm.s.tab);
                     __syncthreads();
                 }
@@ -1511,7 +1512,7 @@ __global__ __launch_bounds__(1024) void k_order_lists(Batch<K> b, uint32_t shift
 // (persistent), of class CLS (mid4: 4 waves, up to M4_CAP keys, several
 // work-groups per CU; mid: 16 waves, up to SORT_CAP keys).
 template <class K, bool HV, int NW, int CLS>
-__global__ __launch_bounds__(NW * WAVE) void k_bucket_mid(Batch<K> b, const K *A, const uint32_t *VA,
+__global__ __launch_bounds__(NW * WAVE, 4) void k_bucket_mid(Batch<K> b, const K *A, const uint32_t *VA,
                                                           K *D, uint32_t *VD)
 {
     __shared__ SortSmem<NW, SORT_IPT> sm;
@@ -1535,7 +1536,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_mid(Batch<K> b, const K *A
             if (HV) vv[r] = r < R && p < e.size ? VA[base + p] : 0u;
         }
         wait_vmem();
-        block_sort<K, HV, NW, SORT_IPT>(kk, vv, e.size, sm, true, blo, bhi);
+        lds_sort<K, HV, NW, SORT_IPT>(kk, vv, e.size, sm, blo, bhi, A + base);
 #pragma unroll
         for (int r = 0; r < SORT_IPT; ++r) {
             const uint32_t p = bpos(r, R);
@@ -1560,7 +1561,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_mid(Batch<K> b, const K *A
 struct BigSeg {
     uint32_t off, size;          // bucket-relative
     uint32_t in_d;               // segment currently lives in D (else in A)
-    uint32_t pad;
+    uint32_t split;              // split even if it fits one LDS sort (a bin sort found a crowded bin)
     uint64_t lo, hi;             // inclusive key range of the segment
 };
 // The MSD-split kernel runs half-size work-groups (8 waves, 8192-key LDS
@@ -1605,7 +1606,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
             K *src = sg.in_d ? D : A;
             uint32_t *vsrc = sg.in_d ? VD : VA;
             const uint64_t sb = bbase + sg.off;
-            if (sg.size <= (uint32_t)BK_CAP || sg.lo == sg.hi) {
+            if ((sg.size <= (uint32_t)BK_CAP && !sg.split) || sg.lo == sg.hi) {
                 if (sg.lo == sg.hi) {                       // one key value: already in order
                     if (!sg.in_d)
                         for (uint32_t p = tid; p < sg.size; p += BK_NT) {
@@ -1625,13 +1626,33 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                     }
                     wait_vmem();
                     __syncthreads();
-                    block_sort<K, HV, BK_NW, BK_IPT>(kk, vv, sg.size, sm, true, (K)sg.lo, (K)sg.hi);
+                    // 32-bit keys without values: bins; a crowded bin sends the
+                    // part back to the stack for one more split, which narrows
+                    // its key range (no radix sort here: with both sorts in the
+                    // kernel the register allocation spills)
+                    bool done = true;
+                    if constexpr (sizeof(K) == 4 && !HV) {
+                        uint32_t blo, nbin;
+                        int bsh;
+                        done = bin_sort<BK_NW, BK_IPT>(kk, sg.size, sm, blo, bsh, nbin, true, (uint32_t)sg.lo,
+                                                       (uint32_t)sg.hi) != 2;
+                        if (!done && tid == 0) {
+                            BigSeg again = sg;
+                            again.split = 1u;
+                            stack[sp - 1] = again;
+                            sp_sh = sp;
+                        }
+                    } else {
+                        block_sort<K, HV, BK_NW, BK_IPT>(kk, vv, sg.size, sm, true, (K)sg.lo, (K)sg.hi);
+                    }
+                    if (done) {
 #pragma unroll
-                    for (int r = 0; r < BK_IPT; ++r) {
-                        const uint32_t p = bpos(r, R);
-                        if (r < R && p < sg.size) {
-                            D[sb + p] = kk[r];
-                            if (HV) VD[sb + p] = vv[r];
+                        for (int r = 0; r < BK_IPT; ++r) {
+                            const uint32_t p = bpos(r, R);
+                            if (r < R && p < sg.size) {
+                                D[sb + p] = kk[r];
+                                if (HV) VD[sb + p] = vv[r];
+                            }
                         }
                     }
                 }
@@ -1648,7 +1669,9 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
             const K klo = (K)sg.lo;
             const int bits = T::bitlen((K)((K)sg.hi - klo));
             int sbits = bits;
-            if (bits > SPLIT_MAX) {
+            if (sg.split) {
+                sbits = min(bits, SPLIT_MAX);                    // at least one bit: lo < hi
+            } else if (bits > SPLIT_MAX) {
                 const int best = (bits - SPLIT_MAX + 7) / 8;
                 sbits = min(32 - __clz((sg.size - 1) / SPLIT_PART), SPLIT_MAX);
                 while (sbits < SPLIT_MAX && (bits - sbits + 7) / 8 > best) ++sbits;

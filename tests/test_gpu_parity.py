@@ -241,6 +241,63 @@ def test_u32_base_split_ranges(b, ws, n, name):
     assert np.array_equal(got, np.sort(x))
 
 
+def _crowded(n, name, seed):
+    # inputs that crowd a key-range bin of a column, bucket or MSD part (more
+    # than 16 keys inside one bin's width): half the keys in a narrow window
+    # ("window*"), or uniform keys with a few values of very high
+    # multiplicity (crowding columns) and a pool of values repeated about 64
+    # times each (crowding buckets and parts) ("spiky")
+    g = np.random.default_rng(seed)
+    x = g.integers(0, 2**32, size=n, dtype=np.uint64)
+    u = g.random(n)
+    if name.startswith("window"):
+        w = u < 0.5
+        x[w] = 123_456_789 + g.integers(0, 1 << int(name[6:]), size=int(w.sum()))
+    else:
+        heavy = g.integers(0, 2**32, size=4, dtype=np.uint64)
+        pool = g.integers(0, 2**32, size=max(1, n // 320), dtype=np.uint64)
+        h = u < 0.2
+        p = (u >= 0.2) & (u < 0.4)
+        x[h] = heavy[g.integers(0, 4, size=int(h.sum()))]
+        x[p] = pool[g.integers(0, pool.size, size=int(p.sum()))]
+    return x.astype(np.uint32)
+
+
+CROWDED_CASES = [(1 << 20, 0), (4_000_037, 0), ((1 << 22) + 1, 20_000), (300_001, 64), (200_000, 0)]
+
+
+@pytest.mark.parametrize("n,cutoff", CROWDED_CASES)
+@pytest.mark.parametrize("name", ["window8", "window16", "window24", "spiky"])
+def test_u32_crowded_bins_digest(b, ws, n, cutoff, name):
+    _say(f"u32 crowded {name} n={n} cutoff={cutoff}")
+    x = _crowded(n, name, seed=n + len(name))
+    got, dg, used = gpu_u32(b, ws, x, seed=5, cutoff=cutoff, digest=True)
+    assert np.array_equal(got, np.sort(x))
+    want, wdg, _ = oracle.squaresort_u32(x, 5, used, want_digest=True)
+    assert dg == wdg
+
+
+def test_u32_crowded_bins_large(b, ws):
+    n = (1 << 24) + 5
+    _say(f"u32 crowded spiky n={n}")
+    x = _crowded(n, "spiky", seed=11)
+    got, dg, used = gpu_u32(b, ws, x, seed=5, cutoff=0, digest=True)
+    assert np.array_equal(got, np.sort(x))
+    want, wdg, _ = oracle.squaresort_u32(x, 5, used, want_digest=True)
+    assert dg == wdg
+
+
+@pytest.mark.parametrize("name", ["window8", "window16", "spiky"])
+def test_skew_transpose_crowded(b, ws, name):
+    n = (1 << 22) + 7
+    _say(f"skew crowded {name}")
+    x = _crowded(n, name, seed=3)
+    got, bs = gpu_skew(b, ws, x, seed=9)
+    want, wbs = oracle.root_intermediate(x.astype(np.uint64), seed=9)
+    assert np.array_equal(bs, wbs)
+    assert np.array_equal(got.astype(np.uint64), want)
+
+
 @pytest.mark.parametrize("name", ["span8", "near_max", "one_value", "sparse_outlier"])
 def test_kv_base_split_stable(b, ws, name):
     n = 200_001
