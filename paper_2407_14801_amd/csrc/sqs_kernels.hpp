@@ -1584,6 +1584,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
     __shared__ BigSeg stack[BIG_STACK];
     __shared__ uint32_t hist[256], base[256], run[256];
     __shared__ uint32_t whist[BK_NW][1 << SPLIT_MAX];
+    __shared__ uint32_t ccnt[1 << SPLIT_MAX], coff[1 << SPLIT_MAX];
     __shared__ uint32_t sp_sh, overflow_sh;
     const uint32_t tid = threadIdx.x;
     __shared__ uint32_t take_sh;
@@ -1709,81 +1710,134 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                 uint32_t r0 = wave_incl_scan(t4) - t4;
                 for (int q = 0; q < 4; ++q) { if (4 * tid + q < 256) base[4 * tid + q] = r0; r0 += c[q]; }
             }
-            tables_clear<BK_NW, 256>(sm.s.tab);
-            __syncthreads();
-            for (uint32_t c0 = 0; c0 < sg.size; c0 += BK_CAP) {       // stable scatter, chunk by chunk
-                const uint32_t chN = min((uint32_t)BK_CAP, sg.size - c0);
-                const int nrows = wave_rows<BK_IPT>(chN);
-                RankTab<256> &tab = sm.s.tab[wave_id()];
-                K kk[BK_IPT];
-                uint32_t vv[BK_IPT], pos[BK_IPT];
-#pragma unroll
-                for (int r = 0; r < BK_IPT; ++r) {                      // loads first, in flight together
-                    const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
-                    kk[r] = r < nrows && p < chN ? src[sb + c0 + p] : (K)0;
-                    if (HV) vv[r] = r < nrows && p < chN ? vsrc[sb + c0 + p] : 0u;
-                }
-                wait_vmem();
-#pragma unroll
-                for (int r = 0; r < BK_IPT; ++r) {
-                    if (r < nrows) {
-                        const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
-                        const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
-                        pos[r] = rank_row(tab, d);
-                    }
-                }
+            if constexpr (sizeof(K) == 4 && !HV) {
+                // keys without values need no stable split: a key's place in
+                // its part's run of the chunk comes from an LDS atomic add
+                if (tid < (1u << SPLIT_MAX)) ccnt[tid] = 0u;
                 __syncthreads();
-                scan_tables<BK_NW, 256>(sm.s.tab, sm.wsum);
+                for (uint32_t c0 = 0; c0 < sg.size; c0 += BK_CAP) {
+                    const uint32_t chN = min((uint32_t)BK_CAP, sg.size - c0);
+                    K kk[BK_IPT];
+                    uint32_t rk[BK_IPT];
 #pragma unroll
-                for (int r = 0; r < BK_IPT; ++r) {
-                    if (r < nrows) {
+                    for (int r = 0; r < BK_IPT; ++r) {                  // loads first, in flight together
                         const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
-                        const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
-                        pos[r] += tab.off[d];
+                        kk[r] = p < chN ? src[sb + c0 + p] : (K)0;
                     }
-                }
+                    wait_vmem();
 #pragma unroll
-                for (int wd = 0; wd < T::WORDS; ++wd) {
-#pragma unroll
-                    for (int r = 0; r < BK_IPT; ++r)
-                        if (r < nrows) sm.s.buf[pos[r]] = T::word(kk[r], wd);
+                    for (int r = 0; r < BK_IPT; ++r) {
+                        const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
+                        if (p < chN)
+                            rk[r] = atomicAdd(&ccnt[min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1)], 1u);
+                    }
+                    __syncthreads();
+                    if (tid < WAVE) {                                    // runs of the chunk's parts
+                        const uint32_t cc = tid < nparts ? ccnt[tid] : 0u;
+                        const uint32_t ex = wave_incl_scan(cc) - cc;
+                        if (tid < nparts) coff[tid] = ex;
+                    }
                     __syncthreads();
 #pragma unroll
-                    for (int r = 0; r < BK_IPT; ++r)
-                        if (r < nrows) kk[r] = T::set_word(kk[r], wd, sm.s.buf[item_pos<BK_NW, BK_IPT>(r)]);
-                    __syncthreads();
-                }
-                if (HV) {
-#pragma unroll
-                    for (int r = 0; r < BK_IPT; ++r) if (r < nrows) sm.s.buf[pos[r]] = vv[r];
-                    __syncthreads();
-#pragma unroll
-                    for (int r = 0; r < BK_IPT; ++r) if (r < nrows) vv[r] = sm.s.buf[item_pos<BK_NW, BK_IPT>(r)];
-                    __syncthreads();
-                }
-                // element at chunk position p has digit d (recomputed from its key);
-                // it goes to base[d] + run[d] + (p - start of d in this chunk)
-#pragma unroll
-                for (int r = 0; r < BK_IPT; ++r) {
-                    if (r < nrows) {
+                    for (int r = 0; r < BK_IPT; ++r) {
                         const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
                         if (p < chN) {
                             const uint32_t d = min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1);
-                            const uint32_t at = base[d] + run[d] + (p - sm.s.tab[0].off[d]);
-                            if (at < sg.size) {                                  // guard: inside the segment
-                                dstb[sb + at] = kk[r];
-                                if (HV) vdstb[sb + at] = vv[r];
+                            sm.s.buf[coff[d] + rk[r]] = (uint32_t)kk[r];
+                        }
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < BK_IPT; ++r) {                  // in chunk order: contiguous runs
+                        const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
+                        if (p < chN) {
+                            const K x = (K)sm.s.buf[p];
+                            const uint32_t d = min((uint32_t)(((K)(x - klo)) >> shift), nparts - 1);
+                            const uint32_t at = base[d] + run[d] + (p - coff[d]);
+                            if (at < sg.size) dstb[sb + at] = x;         // guard: inside the segment
+                        }
+                    }
+                    __syncthreads();
+                    if (tid < nparts) { run[tid] += ccnt[tid]; ccnt[tid] = 0u; }
+                    __syncthreads();
+                }
+            } else {
+                tables_clear<BK_NW, 256>(sm.s.tab);
+                __syncthreads();
+                for (uint32_t c0 = 0; c0 < sg.size; c0 += BK_CAP) {       // stable scatter, chunk by chunk
+                    const uint32_t chN = min((uint32_t)BK_CAP, sg.size - c0);
+                    const int nrows = wave_rows<BK_IPT>(chN);
+                    RankTab<256> &tab = sm.s.tab[wave_id()];
+                    K kk[BK_IPT];
+                    uint32_t vv[BK_IPT], pos[BK_IPT];
+    #pragma unroll
+                    for (int r = 0; r < BK_IPT; ++r) {                      // loads first, in flight together
+                        const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
+                        kk[r] = r < nrows && p < chN ? src[sb + c0 + p] : (K)0;
+                        if (HV) vv[r] = r < nrows && p < chN ? vsrc[sb + c0 + p] : 0u;
+                    }
+                    wait_vmem();
+    #pragma unroll
+                    for (int r = 0; r < BK_IPT; ++r) {
+                        if (r < nrows) {
+                            const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
+                            const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
+                            pos[r] = rank_row(tab, d);
+                        }
+                    }
+                    __syncthreads();
+                    scan_tables<BK_NW, 256>(sm.s.tab, sm.wsum);
+    #pragma unroll
+                    for (int r = 0; r < BK_IPT; ++r) {
+                        if (r < nrows) {
+                            const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
+                            const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
+                            pos[r] += tab.off[d];
+                        }
+                    }
+    #pragma unroll
+                    for (int wd = 0; wd < T::WORDS; ++wd) {
+    #pragma unroll
+                        for (int r = 0; r < BK_IPT; ++r)
+                            if (r < nrows) sm.s.buf[pos[r]] = T::word(kk[r], wd);
+                        __syncthreads();
+    #pragma unroll
+                        for (int r = 0; r < BK_IPT; ++r)
+                            if (r < nrows) kk[r] = T::set_word(kk[r], wd, sm.s.buf[item_pos<BK_NW, BK_IPT>(r)]);
+                        __syncthreads();
+                    }
+                    if (HV) {
+    #pragma unroll
+                        for (int r = 0; r < BK_IPT; ++r) if (r < nrows) sm.s.buf[pos[r]] = vv[r];
+                        __syncthreads();
+    #pragma unroll
+                        for (int r = 0; r < BK_IPT; ++r) if (r < nrows) vv[r] = sm.s.buf[item_pos<BK_NW, BK_IPT>(r)];
+                        __syncthreads();
+                    }
+                    // element at chunk position p has digit d (recomputed from its key);
+                    // it goes to base[d] + run[d] + (p - start of d in this chunk)
+    #pragma unroll
+                    for (int r = 0; r < BK_IPT; ++r) {
+                        if (r < nrows) {
+                            const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
+                            if (p < chN) {
+                                const uint32_t d = min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1);
+                                const uint32_t at = base[d] + run[d] + (p - sm.s.tab[0].off[d]);
+                                if (at < sg.size) {                                  // guard: inside the segment
+                                    dstb[sb + at] = kk[r];
+                                    if (HV) vdstb[sb + at] = vv[r];
+                                }
                             }
                         }
                     }
+                    __syncthreads();
+                    if (tid < nparts) {
+                        const uint32_t st0 = sm.s.tab[0].off[tid];
+                        const uint32_t en = tid + 1 < 256 ? sm.s.tab[0].off[tid + 1] : chN;
+                        run[tid] += min(en, chN) - min(st0, chN);
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
-                if (tid < nparts) {
-                    const uint32_t st0 = sm.s.tab[0].off[tid];
-                    const uint32_t en = tid + 1 < 256 ? sm.s.tab[0].off[tid + 1] : chN;
-                    run[tid] += min(en, chN) - min(st0, chN);
-                }
-                __syncthreads();
             }
             if (tid == 0) {                                              // push the parts
                 uint32_t top = sp_sh;
