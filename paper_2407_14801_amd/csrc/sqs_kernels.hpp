@@ -1561,7 +1561,7 @@ __global__ __launch_bounds__(NW * WAVE, 4) void k_bucket_mid(Batch<K> b, const K
 struct BigSeg {
     uint32_t off, size;          // bucket-relative
     uint32_t in_d;               // segment currently lives in D (else in A)
-    uint32_t split;              // split even if it fits one LDS sort (a bin sort found a crowded bin)
+    uint32_t pad;
     uint64_t lo, hi;             // inclusive key range of the segment
 };
 // The MSD-split kernel runs half-size work-groups (8 waves, 8192-key LDS
@@ -1607,7 +1607,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
             K *src = sg.in_d ? D : A;
             uint32_t *vsrc = sg.in_d ? VD : VA;
             const uint64_t sb = bbase + sg.off;
-            if ((sg.size <= (uint32_t)BK_CAP && !sg.split) || sg.lo == sg.hi) {
+            if (sg.size <= (uint32_t)BK_CAP || sg.lo == sg.hi) {
                 if (sg.lo == sg.hi) {                       // one key value: already in order
                     if (!sg.in_d)
                         for (uint32_t p = tid; p < sg.size; p += BK_NT) {
@@ -1627,33 +1627,18 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                     }
                     wait_vmem();
                     __syncthreads();
-                    // 32-bit keys without values: bins; a crowded bin sends the
-                    // part back to the stack for one more split, which narrows
-                    // its key range (no radix sort here: with both sorts in the
-                    // kernel the register allocation spills)
-                    bool done = true;
-                    if constexpr (sizeof(K) == 4 && !HV) {
-                        uint32_t blo, nbin;
-                        int bsh;
-                        done = bin_sort<BK_NW, BK_IPT>(kk, sg.size, sm, blo, bsh, nbin, true, (uint32_t)sg.lo,
-                                                       (uint32_t)sg.hi) != 2;
-                        if (!done && tid == 0) {
-                            BigSeg again = sg;
-                            again.split = 1u;
-                            stack[sp - 1] = again;
-                            sp_sh = sp;
-                        }
-                    } else {
-                        block_sort<K, HV, BK_NW, BK_IPT>(kk, vv, sg.size, sm, true, (K)sg.lo, (K)sg.hi);
-                    }
-                    if (done) {
+                    // radix passes, also for 32-bit keys without values: a bin
+                    // sort here would need another fallback for crowded bins
+                    // (heavy duplicates), and neither a radix sort beside it
+                    // (register spills) nor splitting such a part again (up to
+                    // eight more passes over it, serially) is cheap
+                    block_sort<K, HV, BK_NW, BK_IPT>(kk, vv, sg.size, sm, true, (K)sg.lo, (K)sg.hi);
 #pragma unroll
-                        for (int r = 0; r < BK_IPT; ++r) {
-                            const uint32_t p = bpos(r, R);
-                            if (r < R && p < sg.size) {
-                                D[sb + p] = kk[r];
-                                if (HV) VD[sb + p] = vv[r];
-                            }
+                    for (int r = 0; r < BK_IPT; ++r) {
+                        const uint32_t p = bpos(r, R);
+                        if (r < R && p < sg.size) {
+                            D[sb + p] = kk[r];
+                            if (HV) VD[sb + p] = vv[r];
                         }
                     }
                 }
@@ -1670,9 +1655,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
             const K klo = (K)sg.lo;
             const int bits = T::bitlen((K)((K)sg.hi - klo));
             int sbits = bits;
-            if (sg.split) {
-                sbits = min(bits, SPLIT_MAX);                    // at least one bit: lo < hi
-            } else if (bits > SPLIT_MAX) {
+            if (bits > SPLIT_MAX) {
                 const int best = (bits - SPLIT_MAX + 7) / 8;
                 sbits = min(32 - __clz((sg.size - 1) / SPLIT_PART), SPLIT_MAX);
                 while (sbits < SPLIT_MAX && (bits - sbits + 7) / 8 > best) ++sbits;
