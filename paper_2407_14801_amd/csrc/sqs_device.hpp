@@ -235,7 +235,9 @@ __device__ inline void tables_clear(RankTab<RDX> *tab)
     }
 }
 
-template <class K, int NW>
+// Work-group min and max.  Without trailing_sync the caller must pass a
+// barrier before red32 / red64 are written again.
+template <class K, int NW, bool trailing_sync = true>
 __device__ inline void block_minmax(K &lo, K &hi, uint32_t *red32, unsigned long long *red64)
 {
     lo = wave_min(lo);
@@ -254,7 +256,7 @@ __device__ inline void block_minmax(K &lo, K &hi, uint32_t *red32, unsigned long
         for (int i = 1; i < NW; ++i) { a = min(a, red64[i]); b = max(b, red64[NW + i]); }
         lo = (K)a; hi = (K)b;
     }
-    __syncthreads();
+    if (trailing_sync) __syncthreads();
 }
 
 // Digit-major, wave-minor exclusive scan of the per-wave counts of RDX digit
@@ -376,22 +378,28 @@ __device__ void block_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count, Sort
 }
 
 // ------------------------------------------------------------ bin sort (u32)
-// Bitonic network over N registers (N a power of two), ascending.
+// Batcher's odd-even merge sort over N registers (N a power of two),
+// ascending: 5 / 19 / 63 compare-exchanges for N = 4 / 8 / 16 (a bitonic
+// network needs 6 / 24 / 80).  Merging runs of length p, it compares the
+// elements k apart (k = p, p/2, .., 1) that lie in the same run pair of
+// length 2p, starting at offset k mod p.
 template <int N>
-__device__ inline void bitonic_regs(uint32_t (&x)[N])
+__device__ inline void oddeven_regs(uint32_t (&x)[N])
 {
 #pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
+    for (int p = 1; p < N; p <<= 1) {
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int k = p; k >= 1; k >>= 1) {
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint32_t a = x[i], c = x[l];
-                    const bool up = (i & k) == 0;
-                    x[i] = up ? min(a, c) : max(a, c);
-                    x[l] = up ? max(a, c) : min(a, c);
+            for (int j = k % p; j + k < N; j += 2 * k) {
+#pragma unroll
+                for (int i = 0; i < k; ++i) {
+                    const int lo = i + j, hi = i + j + k;
+                    if (hi < N && lo / (2 * p) == hi / (2 * p)) {
+                        const uint32_t a = x[lo], c = x[hi];
+                        x[lo] = min(a, c);
+                        x[hi] = max(a, c);
+                    }
                 }
             }
         }
@@ -405,7 +413,7 @@ __device__ inline void bin_net(uint32_t *buf, uint32_t s, uint32_t c)
     uint32_t x[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) x[j] = (uint32_t)j < c ? buf[s + j] : 0xffffffffu;
-    bitonic_regs<N>(x);
+    oddeven_regs<N>(x);
 #pragma unroll
     for (int j = 0; j < N; ++j)
         if ((uint32_t)j < c && c > 1) buf[s + j] = x[j];
@@ -464,7 +472,9 @@ __device__ int bin_sort(uint32_t (&k)[IPT], uint32_t count, SortSmem<NW, IPT> &s
 #pragma unroll
         for (int r = 0; r < IPT; ++r)
             if (r < nrows && bpos(r, R) < count) { lo = min(lo, k[r]); hi = max(hi, k[r]); }
-        block_minmax<uint32_t, NW>(lo, hi, sm.red32, sm.red64);
+        // red32 is written again only after the barrier that follows the
+        // atomic adds (or, on return, after a caller's barrier)
+        block_minmax<uint32_t, NW, false>(lo, hi, sm.red32, sm.red64);
     }
     if (count <= 1 || !(lo < hi)) return 0;
     const int nb = min(max(KeyT<uint32_t>::bitlen(count) - 2, 1), KeyT<uint32_t>::bitlen(BIN_CAP) - 1);
