@@ -1576,6 +1576,26 @@ constexpr int BIG_STACK = 256;
 constexpr int SPLIT_MAX = 4;                 // at most 16 parts per split
 constexpr uint32_t SPLIT_PART = 6144;        // aimed part size (fits one LDS sort with room)
 
+// Radix sort of a part of 32-bit keys without values whose bin sort found a
+// crowded bin: from[0 .. size) -> to[0 .. size), keys in [lo, hi].  Not
+// inlined, so that its registers are allocated apart from the bin sort's
+// (both sorts inlined into one kernel spill).  All threads call it.
+__device__ __noinline__ void big_leaf_radix(const uint32_t *from, uint32_t *to, uint32_t size, uint32_t lo,
+                                            uint32_t hi, BigSm &sm)
+{
+    uint32_t kk[BK_IPT], vv[BK_IPT];
+    block_load<uint32_t, false, BK_NW, BK_IPT>(kk, vv, size, from, nullptr);
+    tables_clear<BK_NW, 256>(sm.s.tab);
+    __syncthreads();
+    block_sort<uint32_t, false, BK_NW, BK_IPT>(kk, vv, size, sm, true, lo, hi);
+    const int R = block_rows<BK_NW, BK_IPT>(size);
+#pragma unroll
+    for (int r = 0; r < BK_IPT; ++r) {
+        const uint32_t p = bpos(r, R);
+        if (r < R && p < size) to[p] = kk[r];
+    }
+}
+
 template <class K, bool HV>
 __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint32_t *VA, K *D, uint32_t *VD)
 {
@@ -1627,18 +1647,28 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                     }
                     wait_vmem();
                     __syncthreads();
-                    // radix passes, also for 32-bit keys without values: a bin
-                    // sort here would need another fallback for crowded bins
-                    // (heavy duplicates), and neither a radix sort beside it
-                    // (register spills) nor splitting such a part again (up to
-                    // eight more passes over it, serially) is cheap
-                    block_sort<K, HV, BK_NW, BK_IPT>(kk, vv, sg.size, sm, true, (K)sg.lo, (K)sg.hi);
+                    // 32-bit keys without values: bins, and a part with a
+                    // crowded bin by the radix passes of big_leaf_radix
+                    bool done = true;
+                    if constexpr (sizeof(K) == 4 && !HV) {
+                        uint32_t blo, nbin;
+                        int bsh;
+                        if (bin_sort<BK_NW, BK_IPT>(kk, sg.size, sm, blo, bsh, nbin, true, (uint32_t)sg.lo,
+                                                    (uint32_t)sg.hi) == 2) {
+                            big_leaf_radix(src + sb, D + sb, sg.size, (uint32_t)sg.lo, (uint32_t)sg.hi, sm);
+                            done = false;
+                        }
+                    } else {
+                        block_sort<K, HV, BK_NW, BK_IPT>(kk, vv, sg.size, sm, true, (K)sg.lo, (K)sg.hi);
+                    }
+                    if (done) {
 #pragma unroll
-                    for (int r = 0; r < BK_IPT; ++r) {
-                        const uint32_t p = bpos(r, R);
-                        if (r < R && p < sg.size) {
-                            D[sb + p] = kk[r];
-                            if (HV) VD[sb + p] = vv[r];
+                        for (int r = 0; r < BK_IPT; ++r) {
+                            const uint32_t p = bpos(r, R);
+                            if (r < R && p < sg.size) {
+                                D[sb + p] = kk[r];
+                                if (HV) VD[sb + p] = vv[r];
+                            }
                         }
                     }
                 }
