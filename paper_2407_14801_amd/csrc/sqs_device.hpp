@@ -663,4 +663,81 @@ __device__ void wave_sort(K (&k)[R], uint32_t (&v)[R], uint32_t count, WaveSmem<
         if (r < nrows) k[r] = (K)(k[r] + lo);
 }
 
+// Wave-level bin sort of up to 64*R 32-bit keys without values (positions
+// r*64 + lane), as bin_sort with the wave's own table space: at most 256
+// bins of about 4 keys, counts at the table's words [0, 256), starts at
+// [256, 512), lane l scanning bins 4l .. 4l+3 and sorting bins l, l+64,
+// l+128, l+192.  Returns 0 (nothing to sort), 1 (sorted: k, sm.buf = keys
+// minus lo, bin starts at wave_bin_starts(sm)) or 2 (a crowded bin, nothing
+// moved).  Either way the table is no longer clear: clear it
+// (wave_table_clear) before the next wave_sort.
+template <int R>
+__device__ inline uint32_t *wave_bin_starts(WaveSmem<R> &sm)
+{
+    return reinterpret_cast<uint32_t *>(&sm.tab) + 256;
+}
+
+template <int R>
+__device__ int wave_bin_sort(uint32_t (&k)[R], uint32_t count, WaveSmem<R> &sm, uint32_t &lo_out, int &sh_out,
+                             uint32_t &nbin_out)
+{
+    static_assert(512 * 4 <= (int)sizeof(RankTab<256>), "counts and starts fit the table");
+    const uint32_t l = lane_id();
+    const int nrows = (int)min((count + WAVE - 1) / WAVE, (uint32_t)R);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(&sm.tab);
+    uint32_t *st = cnt + 256;
+    uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < nrows && r * WAVE + l < count) { lo = min(lo, k[r]); hi = max(hi, k[r]); }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (count <= 1 || !(lo < hi)) return 0;
+    *reinterpret_cast<uint4 *>(&cnt[4 * l]) = make_uint4(0u, 0u, 0u, 0u);
+    const int nb = min(max(KeyT<uint32_t>::bitlen(count) - 2, 1), 8);
+    const int kb = KeyT<uint32_t>::bitlen(hi - lo);
+    const int sh = kb > nb ? kb - nb : 0;
+    const uint32_t nbin = ((hi - lo) >> sh) + 1u;
+    wave_lds_sync();
+    uint32_t rk[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < nrows && r * WAVE + l < count) rk[r] = atomicAdd(&cnt[(k[r] - lo) >> sh], 1u);
+    wave_lds_sync();
+    const uint4 c = *reinterpret_cast<const uint4 *>(&cnt[4 * l]);   // bins >= nbin hold 0
+    const bool big = c.x > (uint32_t)BIN_NET || c.y > (uint32_t)BIN_NET || c.z > (uint32_t)BIN_NET ||
+                     c.w > (uint32_t)BIN_NET;
+    if (sh > 0 && __ballot(big) != 0ull) return 2;   // uniform within the wave
+    const uint32_t s4 = c.x + c.y + c.z + c.w;
+    const uint32_t run = wave_incl_scan(s4) - s4;
+    *reinterpret_cast<uint4 *>(&st[4 * l]) = make_uint4(run, run + c.x, run + c.x + c.y, run + c.x + c.y + c.z);
+    wave_lds_sync();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (r < nrows && r * WAVE + l < count) {
+            const uint32_t x = k[r] - lo;
+            sm.buf[st[x >> sh] + rk[r]] = x;
+        }
+    wave_lds_sync();
+    if (sh > 0) {
+#pragma unroll 1
+        for (uint32_t bb = l; bb - l < nbin; bb += WAVE) {
+            const uint32_t cb = bb < nbin ? cnt[bb] : 0u;
+            const uint32_t s = bb < nbin ? st[bb] : 0u;
+            const uint32_t cm = wave_max(cb);
+            if (cm <= 1u) continue;
+            if (cm <= 4u) bin_net<4>(sm.buf, s, cb);
+            else if (cm <= 8u) bin_net<8>(sm.buf, s, cb);
+            else bin_net<16>(sm.buf, s, cb);
+        }
+        wave_lds_sync();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) k[r] = sm.buf[r * WAVE + l] + lo;   // every row: buf has 64*R words
+    lo_out = lo;
+    sh_out = sh;
+    nbin_out = nbin;
+    return 1;
+}
+
 }  // namespace sqs

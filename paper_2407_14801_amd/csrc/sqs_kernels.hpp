@@ -664,8 +664,28 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
         }
         K clo = (K)0;
         int passes = 0;
-        if (!sorted) {
+        // 32-bit keys without values: bins, then radix passes if a bin is
+        // crowded (the bin sort leaves the table to be cleared: at once for
+        // the radix passes, after the count when the bin starts serve it)
+        int binned = 2;
+        int rsh = 0;
+        uint32_t rlast = 255u;
+        if constexpr (sizeof(K) == 4 && !HV) {
+            if (!sorted) {
+                uint32_t blo = 0u, nbin = 0u;
+                binned = wave_bin_sort<WR>(kk, len, wsm[w], blo, rsh, nbin);
+                if (binned == 1) { clo = (K)blo; rlast = nbin - 1u; }
+                if (binned == 2) {                     // the radix passes need a clear table
+                    wave_table_clear(wsm[w].tab);
+                    wave_lds_sync();
+                }
+            }
+        }
+        if (!sorted && binned == 2) {
             wave_sort<K, HV, WR>(kk, vv, len, wsm[w], &clo, &passes);
+            rsh = 8 * (passes - 1);
+        }
+        if (!sorted) {
 #pragma unroll
             for (int r = 0; r < WR; ++r) {
                 const uint32_t p = r * WAVE + l;
@@ -679,8 +699,8 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
         // in the wave's buffer and the last pass's digit starts in its table;
         // the count searches there, each whole-column search narrowed to the
         // pivot's digit (as in k_colsort_big)
-        const bool fast = sizeof(K) == 4 && !HV && !sorted && passes > 0;
-        const int fsh = 8 * (passes - 1);
+        const bool fast = sizeof(K) == 4 && !HV && !sorted && (passes > 0 || binned == 1);
+        const uint32_t *rtab = binned == 1 ? wave_bin_starts(wsm[w]) : wsm[w].tab.off;
         wave_lds_sync();
         if (!fast) {
 #pragma unroll
@@ -699,10 +719,10 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
             a = 0;
             e = len;
             if (fast) {
-                const K d = (K)(p >> fsh);
-                if (d > (K)255) { a = len; return; }
-                a = min(wsm[w].tab.off[(uint32_t)d], len);
-                e = d < (K)255 ? min(wsm[w].tab.off[(uint32_t)d + 1], len) : len;
+                const K d = (K)(p >> rsh);
+                if (d > (K)rlast) { a = len; return; }
+                a = min(rtab[(uint32_t)d], len);
+                e = d < (K)rlast ? min(rtab[(uint32_t)d + 1], len) : len;
             }
         };
         // positions of the lane's first and last pivot over the column, the
@@ -762,7 +782,7 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
         }
         if (l == 0) { so[0] = 0; so[(uint64_t)nJ * m] = len; }
         wave_lds_sync();
-        if (sizeof(K) == 8) {                            // the column overlaid the table
+        if (sizeof(K) == 8 || binned == 1) {             // the column or the bins overlaid the table
             wave_table_clear(wsm[w].tab);
             wave_lds_sync();
         }
