@@ -1479,7 +1479,20 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_bucket_small(Batch<K> b, const
             kk[r] = p < e.size ? A[base + p] : (K)0;
             if (HV) vv[r] = p < e.size ? VA[base + p] : 0u;
         }
-        wave_sort<K, HV, WR>(kk, vv, e.size, wsm[w]);
+        // 32-bit keys without values: bins, radix passes for a crowded bin
+        // (after clearing the table the bin sort used)
+        bool radix = true;
+        if constexpr (sizeof(K) == 4 && !HV) {
+            uint32_t blo, nbin;
+            int bsh;
+            const int res = wave_bin_sort<WR>(kk, e.size, wsm[w], blo, bsh, nbin);
+            radix = res == 2;
+            if (radix) {
+                wave_table_clear(wsm[w].tab);
+                wave_lds_sync();
+            }
+        }
+        if (radix) wave_sort<K, HV, WR>(kk, vv, e.size, wsm[w]);
 #pragma unroll
         for (int r = 0; r < WR; ++r) {
             const uint32_t p = r * WAVE + l;
