@@ -37,6 +37,8 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "u32_uniform": dict(kind="u32", log2n=28, dist="uniform[0,2^32)", data_seed=2),
     "u32_dup16": dict(kind="u32", log2n=28, dist="uniform[0,2^16)", data_seed=3),
+    # the fully recursive configuration: every level of the tree runs (cut-off 64)
+    "u32_recursive": dict(kind="u32", log2n=20, dist="uniform[0,2^32)", data_seed=1, cutoff=64),
     "kv_mixture": dict(kind="kv", log2n=27, dist="80% Zipf(1.1) over 2^20 u64 / 10% constant / "
                                                   "10% sorted run with 1% swaps", data_seed=4),
     # many independent instances in one call, against one call per instance
@@ -101,22 +103,77 @@ def make_input(wl, n):
     return datagen.kv_mixture(n, seed=wl["data_seed"])
 
 
-def cpu_baseline(wl, host, cutoff, seed, log2_sample):
-    """The CPU oracle, as it stands, on the first 2^log2_sample keys."""
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return model, nproc
+
+
+def cpu_threads():
+    """Host threads for the oracle: the machine's CPU share (OMP_NUM_THREADS there),
+    at most 16."""
+    _, nproc = cpu_info()
+    return max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", nproc)), nproc))
+
+
+def cpu_baseline(wl, host, cutoff, seed, log2_sample, gpu_out):
+    """The CPU oracle, as it stands, on the machine's host cores: the whole input
+    on P threads (the root's children spread over them; the reported value),
+    its output compared byte for byte with the GPU's; on a 2^log2_sample
+    prefix, the single-thread oracle (per-core figure), the P-thread oracle
+    again (same bytes and digest) and std::sort / std::stable_sort (the
+    paper's comparator) for context."""
     import oracle
-    s = 1 << log2_sample
+    P = cpu_threads()
+    model, nproc = cpu_info()
+    n = host[0].size
+    kv = wl["kind"] != "u32"
+    unit = "GPairs/s" if kv else "GKeys/s"
+
+    def run(keys, vals, threads):
+        t0 = time.perf_counter()
+        with oracle.threads(threads):
+            if kv:
+                ko, vo, dg, _ = oracle.squaresort_kv(keys, vals, seed, cutoff, want_digest=True)
+            else:
+                ko, dg, _ = oracle.squaresort_u32(keys, seed, cutoff, want_digest=True)
+                vo = None
+        return time.perf_counter() - t0, ko, vo, dg
+
+    print(f"# cpu baseline: oracle on {P} threads, n={n}", file=sys.stderr, flush=True)
+    t_full, ko, vo, _ = run(host[0], host[1] if kv else None, P)
+    same_as_gpu = bool(np.array_equal(ko, gpu_out[0]) and (not kv or np.array_equal(vo, gpu_out[1])))
+    del ko, vo
+    s = min(1 << log2_sample, n)
+    ks, vs = host[0][:s], (host[1][:s] if kv else None)
+    print(f"# cpu baseline: single thread and {P} threads on {s} keys", file=sys.stderr, flush=True)
+    t1, k1, v1, d1 = run(ks, vs, 1)
+    tP, kP, vP, dP = run(ks, vs, P)
+    identical = bool(np.array_equal(k1, kP) and d1 == dP and (not kv or np.array_equal(v1, vP)))
+    del k1, v1, kP, vP
     t0 = time.perf_counter()
-    if wl["kind"] == "u32":
-        out = oracle.squaresort_u32(host[0][:s], seed, cutoff)
-        ok = bool(np.all(out[1:] >= out[:-1]))
+    if kv:
+        oracle.std_stable_sort_kv(ks, vs)
     else:
-        ko, _ = oracle.squaresort_kv(host[0][:s], host[1][:s], seed, cutoff)
-        ok = bool(np.all(ko[1:] >= ko[:-1]))
-    dt = time.perf_counter() - t0
-    return {"value": s / dt / 1e9, "unit": "GKeys/s" if wl["kind"] == "u32" else "GPairs/s",
-            "cores": 1, "kind": "oracle", "seconds": round(dt, 3), "sorted": ok,
-            "sample": f"full oracle SquareSort (single thread) of the first 2^{log2_sample} keys "
-                      f"of the same input, same seed and cut-off"}
+        oracle.std_sort_u32(ks)
+    t_std = time.perf_counter() - t0
+    return {"value": round(n / t_full / 1e9, 6), "unit": unit, "cores": P, "kind": "oracle",
+            "seconds": round(t_full, 3), "same_bytes_as_gpu": same_as_gpu,
+            "sample": f"whole input (n = {n}) on {P} threads (the root's children spread over them)",
+            "cpu_model": model, "nproc": nproc,
+            "single_thread": {"n": s, "seconds": round(t1, 3), "value": round(s / t1 / 1e9, 6), "unit": unit,
+                              "threaded_seconds": round(tP, 3), "identical_to_threaded": identical},
+            "std_sort_single_thread": {"n": s, "what": "std::stable_sort by key" if kv else "std::sort",
+                                       "seconds": round(t_std, 3), "value": round(s / t_std / 1e9, 6),
+                                       "unit": unit}}
 
 
 def roofline_of(timing, steps, w, traffic_key=None):
@@ -392,7 +449,9 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="served workload: arrival rate as a fraction of the plain path's capacity")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
-    ap.add_argument("--no-timing", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel timing pass")
+    ap.add_argument("--kernel-steps", type=int, default=3,
+                    help="steps of the separate per-kernel timing pass (launch events on)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, copy one input (n*w bytes) device-to-device: the known-size "
                          "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
@@ -436,10 +495,14 @@ def main():
     n = 1 << log2n
     dev = torch.device("cuda:0")
     seed = 1
+    req_cutoff = args.cutoff or wl.get("cutoff", 0)
     print(f"# generating {args.workload} n=2^{log2n}", file=sys.stderr, flush=True)
     host = make_input(wl, n)
     ws = binding.Workspace(dev)
-    copies = args.warmup + args.steps
+    kstep = 0 if args.no_timing else args.kernel_steps
+    copies = args.warmup + args.steps + kstep
+    want_digest = wl.get("cutoff") is not None          # the recursive workload checks its tree digest
+    dg = torch.zeros(1, dtype=torch.int64, device=dev) if want_digest else None
 
     if wl["kind"] == "u32":
         base = torch.from_numpy(host[0].view(np.int32)).to(dev)
@@ -447,8 +510,8 @@ def main():
         out = torch.empty_like(base)
         w = 4
 
-        def step(i):
-            return binding.squaresort_u32(ins[i], out, seed=seed, cutoff=args.cutoff, ws=ws)
+        def step(i, digest=None):
+            return binding.squaresort_u32(ins[i], out, seed=seed, cutoff=req_cutoff, ws=ws, digest=digest)
     else:
         bk = torch.from_numpy(host[0].view(np.int64)).to(dev)
         bv = torch.from_numpy(host[1].view(np.int32)).to(dev)
@@ -456,43 +519,57 @@ def main():
         ko, vo = torch.empty_like(bk), torch.empty_like(bv)
         w = 12
 
-        def step(i):
-            return binding.squaresort_kv(ins[i][0], ins[i][1], ko, vo, seed=seed, cutoff=args.cutoff, ws=ws)
+        def step(i, digest=None):
+            return binding.squaresort_kv(ins[i][0], ins[i][1], ko, vo, seed=seed, cutoff=req_cutoff, ws=ws,
+                                         digest=digest)
     torch.cuda.synchronize()
 
     print(f"# warmup {args.warmup}", file=sys.stderr, flush=True)
     cutoff = 0
     for i in range(args.warmup):
-        cutoff = step(i)
+        cutoff = step(i, dg if i == 0 else None)
     torch.cuda.synchronize()
-    if not args.no_timing:
-        binding.timing_enable(True)
+    gpu_digest = int(dg.cpu().numpy().view(np.uint64)[0]) if want_digest else None
+
+    # headline: K steps between two synchronisations, no per-kernel events;
+    # per-step latency from HIP events on the stream the library launches on
     print(f"# timing {args.steps} steps", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.warmup, copies):
+    for j, i in enumerate(range(args.warmup, args.warmup + args.steps)):
+        evs[j][0].record(stream)
         cutoff = step(i)
+        evs[j][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    timing = binding.timing_report() if not args.no_timing else {}
-    binding.timing_enable(False)
+    per_step = np.array([a.elapsed_time(c) for a, c in evs])
+
+    # per-kernel times: a separate pass with the library's launch events on
+    timing = {}
+    if kstep:
+        print(f"# per-kernel timing pass, {kstep} steps", file=sys.stderr, flush=True)
+        binding.timing_enable(True)
+        for i in range(args.warmup + args.steps, copies):
+            step(i)
+        torch.cuda.synchronize()
+        timing = binding.timing_report()
+        binding.timing_enable(False)
     if args.calib_copy:
         src = ins[0] if wl["kind"] == "u32" else ins[0][0]
         _c = src.clone()
         torch.cuda.synchronize()
         del _c
+    del ins
 
     # the last output must be sorted (cheap device check)
     if wl["kind"] == "u32":
         o = out.to(torch.int64) & 0xFFFFFFFF
-    else:
-        o = ko
-        o = o.view(torch.int64)
-    if wl["kind"] == "u32":
-        sorted_ok = bool((o[1:] >= o[:-1]).all().item())
     else:   # compare unsigned 64-bit keys by flipping the sign bit
-        f = o ^ torch.tensor(-(1 << 63), dtype=torch.int64, device=dev)
-        sorted_ok = bool((f[1:] >= f[:-1]).all().item())
+        o = ko.view(torch.int64) ^ torch.tensor(-(1 << 63), dtype=torch.int64, device=dev)
+    sorted_ok = bool((o[1:] >= o[:-1]).all().item())
+    del o
 
     ms = (t1 - t0) * 1e3 / args.steps
     value = n / (ms / 1e3) / 1e9
@@ -501,7 +578,7 @@ def main():
             "peak_gbs": HBM_PEAK_GBS}
     path["frac"] = path["achieved_gbs"] / HBM_PEAK_GBS
 
-    roof, kern = roofline_of(timing, args.steps, w, f"squaresort_{args.workload}_2^{log2n}")
+    roof, kern = roofline_of(timing, kstep, w, f"squaresort_{args.workload}_2^{log2n}")
 
     res = {
         "metric": "GKeys/s" if wl["kind"] == "u32" else "GPairs/s",
@@ -514,14 +591,36 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"squaresort_{args.workload}_2^{log2n}", "n": n, "key_dist": wl["dist"],
                    "data_seed": wl["data_seed"], "seed": seed, "cutoff": cutoff},
+        "latency_ms": {"p10": round(float(np.percentile(per_step, 10)), 4),
+                       "p50": round(float(np.percentile(per_step, 50)), 4),
+                       "p90": round(float(np.percentile(per_step, 90)), 4),
+                       "how": "HIP events around each call on its stream; per-kernel events off"},
         "roofline": roof,
         "path_roofline": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in path.items()},
         "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in kern.items()},
         "sorted_check": sorted_ok,
     }
+    if timing:
+        # device time per recursion depth (launches of deeper steps are named kernel@depth)
+        depth = {}
+        for k, v in timing.items():
+            d = int(k.split("@")[1]) if "@" in k else 0
+            depth[d] = depth.get(d, 0.0) + v["ms"] / kstep
+        res["ms_per_depth"] = {str(d): round(t, 4) for d, t in sorted(depth.items())}
+    gpu_out = None
+    if want_digest or not args.no_cpu_baseline:
+        gpu_out = ((out.cpu().numpy().view(np.uint32),) if wl["kind"] == "u32"
+                   else (ko.cpu().numpy().view(np.uint64), vo.cpu().numpy().view(np.uint32)))
+    if want_digest:
+        import oracle
+        print("# oracle digest", file=sys.stderr, flush=True)
+        with oracle.threads(cpu_threads()):
+            wout, wdg, nodes = oracle.squaresort_u32(host[0], seed, cutoff, want_digest=True)
+        res["parity"] = {"digest": f"{gpu_digest:#018x}", "oracle_digest": f"{wdg:#018x}", "nodes": nodes,
+                         "digest_equal": gpu_digest == wdg, "output_equal": bool(np.array_equal(wout, gpu_out[0]))}
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(wl, host, cutoff, seed, min(args.cpu_sample_log2, log2n))
+        res["cpu_baseline"] = cpu_baseline(wl, host, cutoff, seed, min(args.cpu_sample_log2, log2n), gpu_out)
     print(json.dumps(res), flush=True)
 
 

@@ -53,6 +53,7 @@ def _load():
         "orc_tree_stats": (ctypes.c_int, [u64, vp, u64, u64, u64, vp, vp, vp]),
         "orc_root_buckets": (ctypes.c_int, [u64, vp, u64, u64, vp, vp, vp]),
         "orc_stable_sort": (ctypes.c_int, [u64, vp, vp]),
+        "orc_set_threads": (None, [u32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -69,6 +70,57 @@ def _p(a):
 def _check(rc, what):
     if rc != 0:
         raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+# ---- std::sort (the paper's comparator; CPU-baseline context) --------------
+_cpusort = None
+
+
+def _load_cpusort():
+    global _cpusort
+    if _cpusort is None:
+        path = os.path.join(_HERE, "libcpusort.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(path)
+        lib.orc_std_sort_u32.restype = None
+        lib.orc_std_sort_u32.argtypes = [u64, vp]
+        lib.orc_std_stable_sort_kv.restype = ctypes.c_int
+        lib.orc_std_stable_sort_kv.argtypes = [u64, vp, vp]
+        _cpusort = lib
+    return _cpusort
+
+
+def std_sort_u32(x: np.ndarray) -> np.ndarray:
+    y = np.array(x, dtype=np.uint32)
+    _load_cpusort().orc_std_sort_u32(y.size, _p(y))
+    return y
+
+
+def std_stable_sort_kv(keys: np.ndarray, vals: np.ndarray):
+    k = np.array(keys, dtype=np.uint64)
+    v = np.array(vals, dtype=np.uint32)
+    _load_cpusort().orc_std_stable_sort_kv(k.size, _p(k), _p(v))
+    return k, v
+
+
+# ---- threads ------------------------------------------------------------
+class threads:
+    """Context manager: the root node's children (and the column sorts of
+    root_intermediate) run on `p` threads inside the block.  The bytes and
+    the digest are the same as on one thread."""
+
+    def __init__(self, p: int):
+        self.p = max(1, int(p))
+
+    def __enter__(self):
+        _load().orc_set_threads(self.p)
+        return self
+
+    def __exit__(self, *exc):
+        _load().orc_set_threads(1)
+        return False
 
 
 # ---- generator --------------------------------------------------------

@@ -3,12 +3,17 @@
  *
  * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
  * benchmark's CPU-baseline leg; never by the product path.  Written for
- * readability, not speed: every step follows the paper's order and notation
- * (Alg. 1 SquareSort, Alg. 2 SkewTranspose, Alg. 3 NaiveSkewTranspose) with
- * the conventions stated in squaresort_oracle.h.  No blocking, no fusion.
+ * readability, not speed: SquareSort takes the steps of Alg. 1 in the
+ * paper's order; SkewTranspose is written out from the layout it defines
+ * (Section 2.2), with the recursive schedule of Alg. 2 kept as a separate
+ * cross-check; the conventions are stated in squaresort_oracle.h.  No
+ * blocking, no fusion.  The children of a root node may run on several
+ * threads (orc_set_threads); they share no memory and draw from their own
+ * generator keys, so the bytes are the same as on one thread.
  */
 #include "squaresort_oracle.h"
 
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -114,64 +119,146 @@ uint64_t orc_bucket_of(uint64_t x, const uint64_t *s, const uint8_t *strict, uin
 }
 
 /* ------------------------------------------------------------------ */
-/* Alg. 3 NaiveSkewTranspose: for each bucket i, for each column j, move
- * elements while the column is not exhausted and its head is <= pivot i.
- * Cursors col[], buc[] advance (passed by reference in the paper).
- * Pivot index k_hi-1 == npiv means +infinity (the sentinel pivots[m]).   */
-typedef struct {
-    const uint64_t *sk; const uint32_t *sv;   /* source */
-    uint64_t *dk; uint32_t *dv;               /* destination */
-    const uint64_t *piv; const uint8_t *strict; uint64_t npiv;
-    uint64_t *col, *col_end, *buc;            /* cursors, indexed globally */
-    uint32_t threshold;
-} skew_ctx;
+/* SkewTranspose (Section 2.2).  Its output is fixed by the layout it
+ * produces: bucket j occupies [bs[j], bs[j+1]) and holds the keys of bucket
+ * j of column 0, then those of column 1, and so on, each column's keys in
+ * their (sorted) column order.  Since the columns are contiguous and sorted,
+ * that is the stable partition of the node array by bucket index, written
+ * out here as: bucket starts from the bucket sizes, then every key of every
+ * column, in order, to the next free slot of its bucket.                  */
 
-static void naive_skew(skew_ctx *c, uint64_t c_lo, uint64_t c_hi, uint64_t b_lo, uint64_t b_hi)
+/* bucket index of x: the number of pivots x is not at-or-below.  The
+ * predicate "x at-or-below pivot t" is monotone in t for sorted pivots with
+ * strict runs, so a binary search finds the first pivot x is at-or-below. */
+static uint64_t bucket_search(uint64_t x, const uint64_t *piv, const uint8_t *strict, uint64_t npiv)
 {
-    for (uint64_t i = b_lo; i < b_hi; ++i)
-        for (uint64_t j = c_lo; j < c_hi; ++j)
-            while (c->col[j] < c->col_end[j] &&
-                   (i == c->npiv || le_pivot(c->sk[c->col[j]], c->piv[i], c->strict[i]))) {
-                c->dk[c->buc[i]] = c->sk[c->col[j]];
-                if (c->dv) c->dv[c->buc[i]] = c->sv[c->col[j]];
-                c->buc[i]++;
-                c->col[j]++;
-            }
+    uint64_t lo = 0, hi = npiv;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (le_pivot(x, piv[mid], strict[mid])) hi = mid; else lo = mid + 1;
+    }
+    return lo;
 }
 
-/* Alg. 2 SkewTranspose: four recursive calls on halves of the columns and
- * of the pivots, in the order (cols 1st, piv 1st), (cols 2nd, piv 1st),
- * (cols 1st, piv 2nd), (cols 2nd, piv 2nd); naive below the threshold
- * (the paper's Alg. 2 uses 4, its experiments 10), returning after it.  */
-static void rec_skew(skew_ctx *c, uint64_t c_lo, uint64_t c_hi, uint64_t b_lo, uint64_t b_hi)
-{
-    uint64_t l = c_hi - c_lo, k = b_hi - b_lo;
-    if (l < c->threshold || k < c->threshold) { naive_skew(c, c_lo, c_hi, b_lo, b_hi); return; }
-    uint64_t l2 = l / 2, k2 = k / 2;
-    rec_skew(c, c_lo,      c_lo + l2, b_lo,      b_lo + k2);
-    rec_skew(c, c_lo + l2, c_hi,      b_lo,      b_lo + k2);
-    rec_skew(c, c_lo,      c_lo + l2, b_lo + k2, b_hi);
-    rec_skew(c, c_lo + l2, c_hi,      b_lo + k2, b_hi);
-}
-
-/* Bucket sizes and bucket positions (Section 2.2): scan every element,
- * count its bucket, then an exclusive prefix sum gives the first slot of
- * every bucket.  bs has m+1 entries; bs[m] = n.                           */
+/* bucket sizes, then bucket starts: an exclusive prefix sum (the bucket
+ * positions of Section 2.2).  bs has m+1 entries, bs[m] = n.              */
 static void bucket_positions(uint64_t n, const uint64_t *keys, const uint64_t *piv,
                              const uint8_t *strict, uint64_t m, uint64_t *bs)
 {
     memset(bs, 0, (m + 1) * sizeof *bs);
-    for (uint64_t r = 0; r < n; ++r) {
-        /* binary search for the number of pivots x is not at-or-below;
-         * the predicate is monotone in t for sorted pivots with strict runs */
-        uint64_t lo = 0, hi = m - 1;
-        while (lo < hi) {
-            uint64_t mid = lo + (hi - lo) / 2;
-            if (le_pivot(keys[r], piv[mid], strict[mid])) hi = mid; else lo = mid + 1;
-        }
-        bs[lo + 1]++;
-    }
+    for (uint64_t r = 0; r < n; ++r) bs[bucket_search(keys[r], piv, strict, m - 1) + 1]++;
     for (uint64_t j = 1; j <= m; ++j) bs[j] += bs[j - 1];
+}
+
+/* The bucket of every key of the node array, column by column.  A column
+ * is sorted and so are the pivots, so one merge-like scan of the column
+ * against the pivots gives its keys' buckets in order (the counting scan of
+ * Section 2.1): the bucket index only moves forward.                      */
+static void column_buckets(uint64_t n, uint64_t m, const uint64_t *keys, const uint64_t *piv,
+                           const uint8_t *strict, uint32_t *bk)
+{
+    for (uint64_t i = 0; i < m; ++i) {
+        uint64_t lo = (i * m < n) ? i * m : n;
+        uint64_t hi = ((i + 1) * m < n) ? (i + 1) * m : n;
+        uint64_t b = 0;
+        for (uint64_t r = lo; r < hi; ++r) {
+            while (b < m - 1 && !le_pivot(keys[r], piv[b], strict[b])) ++b;
+            bk[r] = (uint32_t)b;
+        }
+    }
+}
+
+static int skew_layout(uint64_t n, uint64_t m, const uint64_t *sk, const uint32_t *sv,
+                       uint64_t *dk, uint32_t *dv, const uint64_t *piv, const uint8_t *strict,
+                       uint64_t *bs)
+{
+    uint64_t *fill = malloc(m * sizeof *fill);
+    uint32_t *bk = malloc(n * sizeof *bk);
+    if (!fill || !bk) { free(fill); free(bk); return -2; }
+    column_buckets(n, m, sk, piv, strict, bk);
+    memset(bs, 0, (m + 1) * sizeof *bs);                 /* bucket sizes, then starts */
+    for (uint64_t r = 0; r < n; ++r) bs[bk[r] + 1]++;
+    for (uint64_t j = 1; j <= m; ++j) bs[j] += bs[j - 1];
+    memcpy(fill, bs, m * sizeof *fill);
+    for (uint64_t r = 0; r < n; ++r) {                   /* columns in order, keys in column order */
+        dk[fill[bk[r]]] = sk[r];
+        if (dv) dv[fill[bk[r]]] = sv[r];
+        fill[bk[r]]++;
+    }
+    int ok = 1;                                          /* every bucket filled exactly */
+    for (uint64_t j = 0; j < m; ++j) ok &= (fill[j] == bs[j + 1]);
+    free(fill);
+    free(bk);
+    return ok ? 0 : -3;
+}
+
+/* Cross-check: the recursive schedule of Section 2.2.  The grid of
+ * (column, bucket) cells is cut into quarters, visited as: first half of the
+ * columns with the first half of the buckets, second half of the columns
+ * with the first half of the buckets, then the same two for the second half
+ * of the buckets.  So every column gives up its cells in bucket order and
+ * every bucket receives its cells in column order, which is all the layout
+ * needs.  A block with fewer than `threshold` columns or buckets moves its
+ * cells directly, bucket by bucket, column by column.  Each column keeps a
+ * read position, each bucket a write position; a cell of column c and
+ * bucket b is the run of column c's remaining keys whose bucket is b (the
+ * keys' buckets are precomputed once).                                    */
+typedef struct {
+    const uint64_t *sk; const uint32_t *sv;
+    uint64_t *dk; uint32_t *dv;
+    const uint64_t *bk;           /* bucket of every source key */
+    uint64_t *rd, *rd_end, *wr;   /* per column read position / end, per bucket write position */
+    uint64_t threshold;
+} quad_ctx;
+
+static void quad_leaf(quad_ctx *q, uint64_t c0, uint64_t c1, uint64_t b0, uint64_t b1)
+{
+    for (uint64_t b = b0; b < b1; ++b)
+        for (uint64_t c = c0; c < c1; ++c) {
+            uint64_t p = q->rd[c];
+            while (p < q->rd_end[c] && q->bk[p] == b) {
+                q->dk[q->wr[b]] = q->sk[p];
+                if (q->dv) q->dv[q->wr[b]] = q->sv[p];
+                q->wr[b]++;
+                p++;
+            }
+            q->rd[c] = p;
+        }
+}
+
+static void quad_split(quad_ctx *q, uint64_t c0, uint64_t c1, uint64_t b0, uint64_t b1)
+{
+    if (c1 - c0 < q->threshold || b1 - b0 < q->threshold) { quad_leaf(q, c0, c1, b0, b1); return; }
+    uint64_t cm = c0 + (c1 - c0) / 2, bm = b0 + (b1 - b0) / 2;
+    quad_split(q, c0, cm, b0, bm);
+    quad_split(q, cm, c1, b0, bm);
+    quad_split(q, c0, cm, bm, b1);
+    quad_split(q, cm, c1, bm, b1);
+}
+
+static int skew_quadrants(uint64_t n, uint64_t m, const uint64_t *sk, const uint32_t *sv,
+                          uint64_t *dk, uint32_t *dv, const uint64_t *piv, const uint8_t *strict,
+                          uint64_t *bs, uint64_t threshold)
+{
+    uint64_t *bk = malloc(n * sizeof *bk), *rd = malloc(m * sizeof *rd);
+    uint64_t *rd_end = malloc(m * sizeof *rd_end), *wr = malloc(m * sizeof *wr);
+    int rc = -2;
+    if (!bk || !rd || !rd_end || !wr) goto out;
+    bucket_positions(n, sk, piv, strict, m, bs);
+    for (uint64_t r = 0; r < n; ++r) bk[r] = bucket_search(sk[r], piv, strict, m - 1);
+    for (uint64_t i = 0; i < m; ++i) {
+        rd[i] = (i * m < n) ? i * m : n;
+        rd_end[i] = ((i + 1) * m < n) ? (i + 1) * m : n;
+    }
+    memcpy(wr, bs, m * sizeof *wr);
+    quad_ctx q = { sk, sv, dk, dv, bk, rd, rd_end, wr, threshold };
+    quad_split(&q, 0, m, 0, m);
+    rc = 0;                                              /* every cell moved exactly once */
+    for (uint64_t j = 0; j < m; ++j) if (wr[j] != bs[j + 1]) rc = -3;
+    for (uint64_t i = 0; i < m; ++i) if (rd[i] != rd_end[i]) rc = -3;
+out:
+    free(bk); free(rd); free(rd_end); free(wr);
+    return rc;
 }
 
 static int skew_transpose_node(uint64_t n, uint64_t m,
@@ -180,25 +267,8 @@ static int skew_transpose_node(uint64_t n, uint64_t m,
                                const uint64_t *piv, const uint8_t *strict,
                                uint64_t *bs, uint32_t threshold)
 {
-    uint64_t *col = malloc(m * sizeof *col), *col_end = malloc(m * sizeof *col_end);
-    uint64_t *buc = malloc(m * sizeof *buc);
-    if (!col || !col_end || !buc) { free(col); free(col_end); free(buc); return -2; }
-    for (uint64_t i = 0; i < m; ++i) {            /* column spans, Alg. 1 */
-        col[i] = (i * m < n) ? i * m : n;
-        col_end[i] = ((i + 1) * m < n) ? (i + 1) * m : n;
-    }
-    bucket_positions(n, sk, piv, strict, m, bs);
-    for (uint64_t j = 0; j < m; ++j) buc[j] = bs[j];
-    skew_ctx c = { sk, sv, dk, dv, piv, strict, m - 1, col, col_end, buc, threshold };
-    if (threshold == 0) naive_skew(&c, 0, m, 0, m);
-    else rec_skew(&c, 0, m, 0, m);
-    /* after the transpose, buc[j] is the end of bucket j (the shift by one
-     * Alg. 1 notes); it must equal the start of bucket j+1 */
-    int ok = 1;
-    for (uint64_t j = 0; j < m; ++j) ok &= (buc[j] == bs[j + 1]);
-    for (uint64_t i = 0; i < m; ++i) ok &= (col[i] == col_end[i]);
-    free(col); free(col_end); free(buc);
-    return ok ? 0 : -3;
+    if (threshold == 0) return skew_layout(n, m, sk, sv, dk, dv, piv, strict, bs);
+    return skew_quadrants(n, m, sk, sv, dk, dv, piv, strict, bs, threshold);
 }
 
 int orc_skew_transpose_explicit(uint64_t n,
@@ -327,9 +397,95 @@ typedef struct {
     int rule;          /* ORC_RULE_REPLACEMENT or ORC_RULE_ALG1 */
 } sqs_ctx;
 
+/* Threads for the children of a root node (1 = everything on the calling
+ * thread).  Nodes never share memory and every node's draws depend on its
+ * own key only, so running the root's children concurrently yields the same
+ * bytes and the same digest (a sum mod 2^64) as running them in order.    */
+static unsigned orc_threads = 1;
+
+void orc_set_threads(uint32_t threads) { orc_threads = threads ? threads : 1; }
+
 static uint64_t elem_hash_x(uint64_t key, const uint32_t *vals, uint64_t r)
 {
     return vals ? (key ^ orc_sm64(vals[r])) : key;
+}
+
+static void squaresort_rec(sqs_ctx *g, uint64_t K, uint64_t n,
+                           uint64_t *ak, uint32_t *av, uint64_t *dk, uint32_t *dv,
+                           uint64_t depth);
+
+/* one child of a node: its generator key and its range [lo, lo+len) */
+typedef struct { uint64_t K, lo, len; } child_task;
+
+typedef struct {
+    sqs_ctx g;                      /* this worker's own counters */
+    const child_task *tasks;
+    uint64_t ntasks, *next;         /* shared claim counter */
+    uint64_t *ak, *dk;
+    uint32_t *av, *dv;
+    uint64_t depth;
+} child_worker;
+
+static void *child_worker_run(void *arg)
+{
+    child_worker *w = arg;
+    for (;;) {
+        uint64_t t = __atomic_fetch_add(w->next, 1, __ATOMIC_RELAXED);
+        if (t >= w->ntasks || w->g.err) break;
+        const child_task *c = &w->tasks[t];
+        squaresort_rec(&w->g, c->K, c->len, w->ak + c->lo, w->av ? w->av + c->lo : NULL,
+                       w->dk + c->lo, w->dv ? w->dv + c->lo : NULL, w->depth);
+    }
+    return NULL;
+}
+
+/* Sorts every child range A -> D: in order on this thread, or (at the
+ * root, with orc_threads > 1) claimed one at a time by the threads. */
+static void run_children(sqs_ctx *g, const child_task *tasks, uint64_t ntasks,
+                         uint64_t *ak, uint32_t *av, uint64_t *dk, uint32_t *dv, uint64_t depth)
+{
+    unsigned P = (depth == 1 && orc_threads > 1 && ntasks > 1) ? orc_threads : 1;
+    if (P > ntasks) P = (unsigned)ntasks;
+    if (P <= 1) {
+        for (uint64_t t = 0; t < ntasks && !g->err; ++t)
+            squaresort_rec(g, tasks[t].K, tasks[t].len, ak + tasks[t].lo, av ? av + tasks[t].lo : NULL,
+                           dk + tasks[t].lo, dv ? dv + tasks[t].lo : NULL, depth);
+        return;
+    }
+    child_worker *w = calloc(P, sizeof *w);
+    pthread_t *th = calloc(P, sizeof *th);
+    uint64_t *stats = g->node_count ? calloc(2 * P * g->max_depth, sizeof *stats) : NULL;
+    if (!w || !th || (g->node_count && !stats)) { free(w); free(th); free(stats); g->err = -2; return; }
+    uint64_t next = 0;
+    unsigned started = 0;
+    for (unsigned p = 0; p < P; ++p) {
+        w[p].g = *g;
+        w[p].g.digest = 0; w[p].g.nodes = 0; w[p].g.depth_reached = 0; w[p].g.err = 0;
+        if (stats) {
+            w[p].g.node_count = stats + 2 * p * g->max_depth;
+            w[p].g.size_sum = stats + (2 * p + 1) * g->max_depth;
+        }
+        w[p].tasks = tasks; w[p].ntasks = ntasks; w[p].next = &next;
+        w[p].ak = ak; w[p].av = av; w[p].dk = dk; w[p].dv = dv; w[p].depth = depth;
+    }
+    for (unsigned p = 1; p < P; ++p) {
+        if (pthread_create(&th[p], NULL, child_worker_run, &w[p]) != 0) break;
+        started = p;
+    }
+    child_worker_run(&w[0]);              /* the calling thread works too */
+    for (unsigned p = 1; p <= started; ++p) pthread_join(th[p], NULL);
+    for (unsigned p = 0; p < P; ++p) {
+        g->digest += w[p].g.digest;
+        g->nodes += w[p].g.nodes;
+        if (w[p].g.depth_reached > g->depth_reached) g->depth_reached = w[p].g.depth_reached;
+        if (w[p].g.err && !g->err) g->err = w[p].g.err;
+        if (stats)
+            for (uint64_t d = 0; d < g->max_depth; ++d) {
+                g->node_count[d] += w[p].g.node_count[d];
+                g->size_sum[d] += w[p].g.size_sum[d];
+            }
+    }
+    free(w); free(th); free(stats);
 }
 
 static void squaresort_rec(sqs_ctx *g, uint64_t K, uint64_t n,
@@ -353,7 +509,9 @@ static void squaresort_rec(sqs_ctx *g, uint64_t K, uint64_t n,
     uint64_t *piv = malloc((m - 1) * sizeof *piv);
     uint8_t *strict = malloc(m - 1);
     uint64_t *bs = malloc((m + 1) * sizeof *bs);
-    if (!piv || !strict || !bs) { g->err = -2; goto out; }
+    child_task *tasks = malloc(m * sizeof *tasks);
+    uint64_t nt = 0;
+    if (!piv || !strict || !bs || !tasks) { g->err = -2; goto out; }
 
     /* pivots come from the node input before the column children clobber it */
     int rc = choose_pivots_rule(g->rule, K, n, m, ak, piv, strict);
@@ -363,14 +521,13 @@ static void squaresort_rec(sqs_ctx *g, uint64_t K, uint64_t n,
     for (uint64_t i = 0; i < m; ++i) {
         uint64_t lo = (i * m < n) ? i * m : n;
         uint64_t hi = ((i + 1) * m < n) ? (i + 1) * m : n;
-        if (hi > lo)
-            squaresort_rec(g, orc_child_key(K, 0, i), hi - lo,
-                           ak + lo, av ? av + lo : NULL, dk + lo, dv ? dv + lo : NULL, depth + 1);
+        if (hi > lo) tasks[nt++] = (child_task){ orc_child_key(K, 0, i), lo, hi - lo };
     }
+    run_children(g, tasks, nt, ak, av, dk, dv, depth + 1);
     if (g->err) goto out;
 
-    /* bucket positions, then SkewTranspose D -> A (Alg. 2 with threshold 4) */
-    rc = skew_transpose_node(n, m, dk, dv, ak, av, piv, strict, bs, 4);
+    /* bucket positions, then SkewTranspose D -> A */
+    rc = skew_transpose_node(n, m, dk, dv, ak, av, piv, strict, bs, 0);
     if (rc) { g->err = rc; goto out; }
 
     /* digest of this node's post-transpose array */
@@ -382,6 +539,7 @@ static void squaresort_rec(sqs_ctx *g, uint64_t K, uint64_t n,
     }
 
     /* sort each bucket from A into D; single-value buckets are copied */
+    nt = 0;
     for (uint64_t j = 0; j < m; ++j) {
         uint64_t lo = bs[j], hi = bs[j + 1];
         if (hi == lo) continue;
@@ -389,12 +547,12 @@ static void squaresort_rec(sqs_ctx *g, uint64_t K, uint64_t n,
             memcpy(dk + lo, ak + lo, (hi - lo) * sizeof *dk);
             if (dv) memcpy(dv + lo, av + lo, (hi - lo) * sizeof *dv);
         } else {
-            squaresort_rec(g, orc_child_key(K, 1, j), hi - lo,
-                           ak + lo, av ? av + lo : NULL, dk + lo, dv ? dv + lo : NULL, depth + 1);
+            tasks[nt++] = (child_task){ orc_child_key(K, 1, j), lo, hi - lo };
         }
     }
+    run_children(g, tasks, nt, ak, av, dk, dv, depth + 1);
 out:
-    free(piv); free(strict); free(bs);
+    free(piv); free(strict); free(bs); free(tasks);
 }
 
 static int run_squaresort_rule(uint64_t n, uint64_t *ak, uint32_t *av, uint64_t *dk, uint32_t *dv,
@@ -482,6 +640,53 @@ int orc_squaresort_kv(uint64_t n, const uint64_t *keys_in, const uint32_t *vals_
 }
 
 /* ------------------------------------------------------------------ */
+/* Every column of the node array sorted in place (stable): what the column
+ * children leave in D.  With orc_threads > 1 the columns are shared out. */
+typedef struct {
+    uint64_t n, m, *next;
+    uint64_t *k;
+    uint32_t *v;
+    int err;
+} colsort_job;
+
+static void *colsort_run(void *arg)
+{
+    colsort_job *j = arg;
+    for (;;) {
+        uint64_t i = __atomic_fetch_add(j->next, 1, __ATOMIC_RELAXED);
+        if (i >= j->m) break;
+        uint64_t lo = (i * j->m < j->n) ? i * j->m : j->n;
+        uint64_t hi = ((i + 1) * j->m < j->n) ? (i + 1) * j->m : j->n;
+        if (hi > lo) {
+            int rc = orc_stable_sort(hi - lo, j->k + lo, j->v ? j->v + lo : NULL);
+            if (rc) j->err = rc;
+        }
+    }
+    return NULL;
+}
+
+static int sort_columns(uint64_t n, uint64_t m, uint64_t *k, uint32_t *v)
+{
+    unsigned P = orc_threads > m ? (unsigned)m : orc_threads;
+    if (P < 1) P = 1;
+    uint64_t next = 0;
+    colsort_job *jobs = calloc(P, sizeof *jobs);
+    pthread_t *th = calloc(P, sizeof *th);
+    if (!jobs || !th) { free(jobs); free(th); return -2; }
+    unsigned started = 0;
+    for (unsigned p = 0; p < P; ++p) jobs[p] = (colsort_job){ n, m, &next, k, v, 0 };
+    for (unsigned p = 1; p < P; ++p) {
+        if (pthread_create(&th[p], NULL, colsort_run, &jobs[p]) != 0) break;
+        started = p;
+    }
+    colsort_run(&jobs[0]);
+    for (unsigned p = 1; p <= started; ++p) pthread_join(th[p], NULL);
+    int rc = 0;
+    for (unsigned p = 0; p < P; ++p) if (jobs[p].err) rc = jobs[p].err;
+    free(jobs); free(th);
+    return rc;
+}
+
 int orc_root_intermediate(uint64_t n, const uint64_t *keys_in, const uint32_t *vals_in,
                           uint64_t *keys_out, uint32_t *vals_out,
                           uint64_t *bucket_start, uint64_t seed)
@@ -501,13 +706,9 @@ int orc_root_intermediate(uint64_t n, const uint64_t *keys_in, const uint32_t *v
     /* the column children leave every column of D sorted */
     memcpy(dk, keys_in, n * sizeof *dk);
     if (dv) memcpy(dv, vals_in, n * sizeof *dv);
-    for (uint64_t i = 0; i < m && rc == 0; ++i) {
-        uint64_t lo = (i * m < n) ? i * m : n;
-        uint64_t hi = ((i + 1) * m < n) ? (i + 1) * m : n;
-        if (hi > lo) rc = orc_stable_sort(hi - lo, dk + lo, dv ? dv + lo : NULL);
-    }
+    rc = sort_columns(n, m, dk, dv);
     if (rc) goto out;
-    rc = skew_transpose_node(n, m, dk, dv, keys_out, vals_out, piv, strict, bs, 4);
+    rc = skew_transpose_node(n, m, dk, dv, keys_out, vals_out, piv, strict, bs, 0);
     if (rc == 0 && bucket_start) memcpy(bucket_start, bs, (m + 1) * sizeof *bs);
 out:
     free(piv); free(strict); free(bs); free(dk); free(dv);

@@ -98,13 +98,14 @@ int orc_root_pivots_alg1(uint64_t n, const uint64_t *keys_in, uint64_t seed,
 /* bucket index of key x against sorted pivots s[0..npiv) with strict flags */
 uint64_t orc_bucket_of(uint64_t x, const uint64_t *s, const uint8_t *strict, uint64_t npiv);
 
-/* ---- SkewTranspose with explicit pivots (Alg. 2 / Alg. 3).
+/* ---- SkewTranspose with explicit pivots (Section 2.2).
  * src holds m columns of the node (column i = [min(i*m,n), min((i+1)*m,n)),
  * each sorted); pivots s[0..m-1) with strict flags; +inf closes the last
  * bucket.  Writes dst and bucket_start[0..m] (bucket j = [bs[j], bs[j+1])).
- * threshold = 0 runs Alg. 3 alone; threshold >= 2 runs Alg. 2 with the naive
- * fallback when fewer than `threshold` columns or buckets remain (threshold 1
- * is rejected: splitting one column in two halves would not terminate). */
+ * threshold = 0 writes the layout out from its definition (what SquareSort
+ * uses); threshold >= 2 runs the recursive quarter schedule of Alg. 2 (its
+ * blocks below `threshold` columns or buckets moved directly) as a
+ * cross-check (threshold 1 is rejected: halving one column never ends). */
 int orc_skew_transpose_explicit(uint64_t n,
                                 const uint64_t *src_keys, const uint32_t *src_vals,
                                 uint64_t *dst_keys, uint32_t *dst_vals,
@@ -137,6 +138,12 @@ int orc_tree_stats(uint64_t n, const uint64_t *keys_in, uint64_t seed, uint64_t 
 int orc_tree_stats_rule(uint64_t n, const uint64_t *keys_in, uint64_t seed, uint64_t cutoff,
                         int rule, uint64_t max_depth, uint64_t *node_count, uint64_t *size_sum,
                         uint64_t *depth);
+
+/* ---- threads for the children of a root node (SquareSort, tree
+ * statistics) and for the column sorts of orc_root_intermediate; 1 (the
+ * default) runs everything on the calling thread.  The output and the
+ * digest do not depend on it. */
+void orc_set_threads(uint32_t threads);
 
 /* ---- a plain stable merge sort by key (the base case "simple_sort") ---- */
 int orc_stable_sort(uint64_t n, uint64_t *keys, uint32_t *vals);

@@ -23,6 +23,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 KIND_U32, KIND_U64, KIND_KV = 0, 1, 2
 FLAG_DIGEST = 1
 FLAG_ALG1_PIVOTS = 2
+FLAG_VALIDATE = 4
+FLAG_COLS_SORTED = 8
 PIVOT_RULES = {"replacement": 0, "alg1": FLAG_ALG1_PIVOTS}
 STATUS = {0: "SQS_OK", -1: "SQS_ERR_ARG", -2: "SQS_ERR_ALIAS", -3: "SQS_ERR_WORKSPACE",
           -4: "SQS_ERR_DEVICE", -5: "SQS_ERR_PRECOND", -6: "SQS_ERR_DEPTH", -7: "SQS_ERR_UNSUPPORTED"}
@@ -102,12 +104,12 @@ class Workspace:
         return self.buf
 
 
-def _params(n, kind, cutoff, ws, digest, pivot_rule="replacement"):
+def _params(n, kind, cutoff, ws, digest, pivot_rule="replacement", flags=0):
     nbytes = workspace_bytes(n, kind, cutoff)
     buf = (ws or Workspace()).get(nbytes) if n > 0 else None
     p = Params()
     p.cutoff = cutoff
-    p.flags = (FLAG_DIGEST if digest is not None else 0) | PIVOT_RULES[pivot_rule]
+    p.flags = (FLAG_DIGEST if digest is not None else 0) | PIVOT_RULES[pivot_rule] | flags
     p.workspace = None if buf is None else buf.data_ptr()
     p.workspace_bytes = 0 if buf is None else buf.numel()
     p.digest = None if digest is None else digest.data_ptr()
@@ -122,13 +124,14 @@ def _check_dev(*ts):
 
 def squaresort_u32(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: int = 0,
                    ws: Workspace | None = None, digest: torch.Tensor | None = None,
-                   pivot_rule: str = "replacement") -> int:
+                   pivot_rule: str = "replacement", validate: bool = False) -> int:
     """Sort inp (uint32 bits in an int32 tensor; clobbered) into out.  Returns
-    the cut-off used.  pivot_rule "alg1" selects the Alg. 1 pivot rule."""
+    the cut-off used.  pivot_rule "alg1" selects the Alg. 1 pivot rule;
+    validate sets SQS_FLAG_VALIDATE."""
     _check_dev(inp, out)
     assert inp.dtype == torch.int32 and out.dtype == torch.int32 and inp.numel() == out.numel()
     n = inp.numel()
-    p, _keep = _params(n, KIND_U32, cutoff, ws, digest, pivot_rule)
+    p, _keep = _params(n, KIND_U32, cutoff, ws, digest, pivot_rule, FLAG_VALIDATE if validate else 0)
     _check(_lib.squaresort_u32(n, _ptr(inp), _ptr(out), seed, ctypes.byref(p), _stream(inp.device)),
            "squaresort_u32")
     return p.cutoff
@@ -136,11 +139,11 @@ def squaresort_u32(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: 
 
 def squaresort_u64(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: int = 0,
                    ws: Workspace | None = None, digest: torch.Tensor | None = None,
-                   pivot_rule: str = "replacement") -> int:
+                   pivot_rule: str = "replacement", validate: bool = False) -> int:
     _check_dev(inp, out)
     assert inp.dtype == torch.int64 and out.dtype == torch.int64 and inp.numel() == out.numel()
     n = inp.numel()
-    p, _keep = _params(n, KIND_U64, cutoff, ws, digest, pivot_rule)
+    p, _keep = _params(n, KIND_U64, cutoff, ws, digest, pivot_rule, FLAG_VALIDATE if validate else 0)
     _check(_lib.squaresort_u64(n, _ptr(inp), _ptr(out), seed, ctypes.byref(p), _stream(inp.device)),
            "squaresort_u64")
     return p.cutoff
@@ -148,23 +151,27 @@ def squaresort_u64(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: 
 
 def squaresort_kv(keys_in, vals_in, keys_out, vals_out, seed: int = 1, cutoff: int = 0,
                   ws: Workspace | None = None, digest: torch.Tensor | None = None,
-                  pivot_rule: str = "replacement") -> int:
+                  pivot_rule: str = "replacement", validate: bool = False) -> int:
     _check_dev(keys_in, vals_in, keys_out, vals_out)
     assert keys_in.dtype == torch.int64 and vals_in.dtype == torch.int32
     n = keys_in.numel()
-    p, _keep = _params(n, KIND_KV, cutoff, ws, digest, pivot_rule)
+    p, _keep = _params(n, KIND_KV, cutoff, ws, digest, pivot_rule, FLAG_VALIDATE if validate else 0)
     _check(_lib.squaresort_kv(n, _ptr(keys_in), _ptr(vals_in), _ptr(keys_out), _ptr(vals_out), seed,
                               ctypes.byref(p), _stream(keys_in.device)), "squaresort_kv")
     return p.cutoff
 
 
 def skew_transpose_u32(inp: torch.Tensor, out: torch.Tensor, bucket_start: torch.Tensor | None = None,
-                       seed: int = 1, ws: Workspace | None = None, pivot_rule: str = "replacement") -> None:
-    """Root step up to SkewTranspose: columns of inp sorted in place, pivots
-    drawn from the original inp, skew-transposed result in out."""
+                       seed: int = 1, ws: Workspace | None = None, pivot_rule: str = "replacement",
+                       validate: bool = False, cols_sorted: bool = False) -> None:
+    """Root step up to SkewTranspose: columns of inp sorted in place (or,
+    with cols_sorted, taken as given sorted), pivots drawn from the original
+    inp, skew-transposed result in out.  validate checks the bucket bounds
+    (and, with cols_sorted, that the columns are sorted)."""
     _check_dev(inp, out)
     n = inp.numel()
-    p, _keep = _params(n, KIND_U32, 0, ws, None, pivot_rule)
+    fl = (FLAG_VALIDATE if validate else 0) | (FLAG_COLS_SORTED if cols_sorted else 0)
+    p, _keep = _params(n, KIND_U32, 0, ws, None, pivot_rule, fl)
     _check(_lib.skew_transpose_u32(n, _ptr(inp), _ptr(out), _ptr(bucket_start), seed, ctypes.byref(p),
                                    _stream(inp.device)), "skew_transpose_u32")
 

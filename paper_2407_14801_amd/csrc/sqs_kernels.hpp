@@ -90,7 +90,14 @@ constexpr int CTR_FAIL = 3 * NCLS;
 constexpr int CTR_TR_ITEMS = 3 * NCLS + 1;
 constexpr int CTR_TR_TAKE = 3 * NCLS + 2;
 constexpr int CTR_TR_FAIL = 3 * NCLS + 3;
-constexpr int CTR_WORDS = 3 * NCLS + 4;
+// set when the MSD-split kernel's segment stack would overflow (it cannot:
+// see k_bucket_big); the call then returns SQS_ERR_DEVICE
+constexpr int CTR_BIG_FAIL = 3 * NCLS + 4;
+// validation (SQS_FLAG_VALIDATE): a column given as sorted is not, and a
+// bucket of the SkewTranspose output holds a key outside its bounds
+constexpr int CTR_PRE_FAIL = 3 * NCLS + 5;
+constexpr int CTR_CHECK_FAIL = 3 * NCLS + 6;
+constexpr int CTR_WORDS = 3 * NCLS + 7;
 // sample attempts of the Alg. 1 pivot rule before a node gives up
 constexpr uint32_t ALG1_ATTEMPTS = 64;
 constexpr uint32_t COPY_CH = 32768;           // keys per piece of a single-value bucket copy
@@ -1351,6 +1358,45 @@ __device__ inline void bucket_bounds(const Batch<K> &b, const NodeDesc &nd, uint
     hi = hasHi ? (th ? (K)(sh - 1) : sh) : (K)KeyT<K>::MAXV;
 }
 
+// ---- validation (SQS_FLAG_VALIDATE)
+// Sets *flag when some x[p] > x[p+1] with p and p+1 in the same segment of
+// seg keys (seg = the column length for columns, n for a whole output).
+template <class K>
+__global__ void k_check_sorted(const K *x, uint64_t n, uint64_t seg, uint32_t *flag)
+{
+    bool bad = false;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p + 1 < n; p += (uint64_t)gridDim.x * blockDim.x)
+        if ((p + 1) % seg != 0 && x[p] > x[p + 1]) bad = true;
+    if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(flag, 1u);
+}
+
+// The SkewTranspose output of the batch's only node against its bucket
+// bounds: bs[0] = 0, bs[m] = n, bs non-decreasing, and every key of bucket j
+// inside [L_j, U_j].  Sets ctr[CTR_CHECK_FAIL] otherwise.
+template <class K>
+__global__ void k_check_buckets(Batch<K> b, const K *out)
+{
+    const NodeDesc nd = b.nodes[0];
+    const uint32_t *bs = b.bs + nd.bkt;
+    bool bad = false;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t j = t0; j < nd.m; j += stride) bad |= bs[j] > bs[j + 1];
+    if (t0 == 0) bad |= bs[0] != 0u || bs[nd.m] != nd.n;
+    for (uint64_t p = t0; p < nd.n; p += stride) {
+        uint32_t lo = 0, hi = nd.m;                       // last j with bs[j] <= p
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (bs[mid] <= p) lo = mid; else hi = mid;
+        }
+        K L, U;
+        bucket_bounds(b, nd, lo, L, U);
+        const K x = out[nd.off + p];
+        bad |= x < L || x > U;
+    }
+    if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&b.ctr[CTR_CHECK_FAIL], 1u);
+}
+
 // Classify every bucket and append it to its work list.  Appends are
 // counted per wave (ballots), then per work-group in LDS, and take one global
 // atomic per class and work-group (list order does not affect any result).
@@ -1898,7 +1944,15 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                 sp_sh = top;
             }
             __syncthreads();
-            if (overflow_sh) break;      // cannot happen: a split of s <= 4 bits adds 2^s - 1 <= 3.75 s entries, s summed over the depth <= key bits
+            // Cannot happen: a split of s <= SPLIT_MAX bits pops one segment
+            // and pushes at most 2^s, so the stack grows by at most 2^s - 1
+            // <= 3.75 s entries, and s summed along a path is at most the key
+            // bits (every part spans s bits fewer): at most 241 entries for
+            // 64-bit keys.  Reported rather than assumed.
+            if (overflow_sh) {
+                if (tid == 0) atomicOr(&b.ctr[CTR_BIG_FAIL], 1u);
+                break;
+            }
         }
         __syncthreads();
     }

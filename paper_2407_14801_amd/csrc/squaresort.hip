@@ -194,6 +194,10 @@ template <class K, bool HV> struct Engine {
     bool skew_only = false;
     K *skew_out = nullptr;
     unsigned long long *skew_bs = nullptr;
+    // skew mode: the columns of A come sorted (not sorted again); validate:
+    // check that they are, and the output's bucket bounds
+    bool cols_sorted = false;
+    bool validate = false;
 
     int check() const { return hipGetLastError() == hipSuccess ? SQS_OK : SQS_ERR_DEVICE; }
 
@@ -305,6 +309,8 @@ template <class K, bool HV> struct Engine {
                     const int cls = size_class(len);
                     colLists[cls].push_back(BucketItem{cnode, 0u, (uint32_t)lo, len});
                 }
+            } else if (skew_only && cols_sorted) {
+                d.flags |= NODE_COLS_RECURSED;             // taken as sorted (cut-off 0 below)
             } else if (!skew_only && d.m > cutoff) {
                 d.flags |= NODE_COLS_RECURSED;
                 for (uint32_t i = 0; i < d.m; ++i) {
@@ -447,6 +453,11 @@ template <class K, bool HV> struct Engine {
         }
         K *cdst = skew_only ? A : D;
         uint32_t *vcdst = skew_only ? VA : VD;
+        // columns given sorted: every column counts as sorted by recursion
+        const uint32_t colCut = skew_only && cols_sorted ? 0u : cutoff;
+        if (skew_only && cols_sorted && validate)
+            k_check_sorted<K><<<std::min<uint32_t>(cdiv(desc[0].n, 256), 4096), 256, 0, st>>>(
+                A, desc[0].n, desc[0].m, b.ctr + CTR_PRE_FAIL);
         if (NH) {                                     // m > SORT_CAP: base-case columns A -> D, then the HBM count
             if (int rc = sort_segments<HV>(A, VA, D, VD, colSeg, colLists)) return rc;
             launch("k_blockoff", keysTot, [&] {
@@ -455,9 +466,9 @@ template <class K, bool HV> struct Engine {
             if (int rc = check()) return rc;
         }
         if (NB) launch("k_colsort", keysTot, [&] {
-            k_colsort_big<K, HV><<<bigGrp.back(), SORT_NT, 0, st>>>(b, A, VA, cdst, vcdst, cutoff); });
+            k_colsort_big<K, HV><<<bigGrp.back(), SORT_NT, 0, st>>>(b, A, VA, cdst, vcdst, colCut); });
         if (NS) launch("k_colsort_w", keysTot, [&] {
-            k_colsort_small<K, HV><<<smlGrp.back(), SM_NW * WAVE, 0, st>>>(b, A, VA, cdst, vcdst, cutoff); });
+            k_colsort_small<K, HV><<<smlGrp.back(), SM_NW * WAVE, 0, st>>>(b, A, VA, cdst, vcdst, colCut); });
         launch("k_colscan", bucS[N], [&] { k_colscan<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b); });
         launch("k_bucket_start", bucS[N], [&] { k_bucket_start<K><<<N, 1024, 0, st>>>(b, skew_only ? skew_bs : nullptr); });
         if (int rc = check()) return rc;
@@ -468,15 +479,19 @@ template <class K, bool HV> struct Engine {
                 k_tile_plan<K><<<cdiv(tileS[N], TR_NW), TR_NW * WAVE, 0, st>>>(b, tileS[N]);
                 k_transpose<K, HV><<<tileS[N], TR_NW * WAVE, 0, st>>>(b, A, VA, skew_out, nullptr);
                 k_transpose_heavy<K, HV><<<TR_EXTRA, TR_NW * WAVE, 0, st>>>(b, A, VA, skew_out, nullptr, tileS[N]); });
+            if (validate)
+                k_check_buckets<K><<<std::min<uint32_t>(cdiv(keysTot, 256), 4096), 256, 0, st>>>(b, skew_out);
             ws.top = mark;
             if (int rc = check()) return rc;
             // the host-side plan must outlive its upload
-            uint32_t fail = 0;
-            if (hipMemcpyAsync(&fail, b.ctr + CTR_TR_FAIL, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            uint32_t hc[CTR_WORDS];
+            if (hipMemcpyAsync(hc, b.ctr, sizeof hc, hipMemcpyDeviceToHost, st) != hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess)
                 return SQS_ERR_DEVICE;
             resolve_timing();
-            return fail ? SQS_ERR_DEVICE : SQS_OK;
+            if (hc[CTR_PRE_FAIL]) return SQS_ERR_PRECOND;       // a column given as sorted is not
+            if (alg1 && hc[CTR_FAIL]) return SQS_ERR_PRECOND;   // no valid Alg. 1 sample
+            return hc[CTR_TR_FAIL] || hc[CTR_CHECK_FAIL] ? SQS_ERR_DEVICE : SQS_OK;
         }
         launch("k_transpose", keysTot, [&] {
             k_tile_plan<K><<<cdiv(tileS[N], TR_NW), TR_NW * WAVE, 0, st>>>(b, tileS[N]);
@@ -522,6 +537,7 @@ template <class K, bool HV> struct Engine {
         resolve_timing();
         if (alg1 && hctr[CTR_FAIL]) return SQS_ERR_PRECOND;  // no valid Alg. 1 sample for some node
         if (hctr[CTR_TR_FAIL]) return SQS_ERR_DEVICE;          // a transpose chunk's wait ran out
+        if (hctr[CTR_BIG_FAIL]) return SQS_ERR_DEVICE;         // an MSD-split stack overflow
         for (int c = 0; c < NCLS; ++c)
             if (hctr[c] > b.cap[c]) return SQS_ERR_DEVICE;   // cannot happen: capacities are bounds
         if (debug_on()) {
@@ -584,7 +600,18 @@ template <class K, bool HV> struct Engine {
             k_base_scatter<K, HV><<<G, BS_NT, 0, st>>>(A, VA, D, VD, s); });
         launch("k_bucket_big", keys, [&] {
             k_bucket_big<K, HV><<<std::min<uint32_t>(256 * nseg, 512), BK_NT, 0, st>>>(b, A, VA, D, VD); });
-        return check();
+        if (int rc = check()) return rc;
+        return read_fail(s.ctr);
+    }
+    // Reads a batch's failure words back (synchronising the stream): the
+    // MSD-split kernel's stack overflow flag.
+    int read_fail(const uint32_t *ctr)
+    {
+        uint32_t f = 0;
+        if (hipMemcpyAsync(&f, ctr + CTR_BIG_FAIL, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return SQS_ERR_DEVICE;
+        return f ? SQS_ERR_DEVICE : SQS_OK;
     }
     int sort_big_base(uint64_t n)
     {
@@ -670,9 +697,12 @@ template <class K, bool HV> struct Engine {
             launch("k_bucket", keys[CLS_MID], [&] {
                 k_bucket_mid<K, HV2, SORT_NW, CLS_MID><<<std::min<uint32_t>(b.cap[CLS_MID], 512), SORT_NT, 0, st>>>(
                     b, sA, sVA, sD, sVD); });
-        if (!lists[CLS_BIG].empty())
+        if (!lists[CLS_BIG].empty()) {
             launch("k_bucket_big", keys[CLS_BIG], [&] {
                 k_bucket_big<K, HV2><<<std::min<uint32_t>(b.cap[CLS_BIG], 512), BK_NT, 0, st>>>(b, sA, sVA, sD, sVD); });
+            if (int rc = check()) return rc;
+            return read_fail(ctr);
+        }
         return check();
     }
     std::vector<std::vector<char>> keep_;      // host copies that async uploads read
@@ -819,6 +849,9 @@ int run_sort(uint64_t n, K *in, uint32_t *vin, K *out, uint32_t *vout, uint64_t 
     if (n > (uint64_t)SORT_CAP && (!p || !p->workspace || p->workspace_bytes < need)) return SQS_ERR_WORKSPACE;
     const bool dig = p && (p->flags & SQS_FLAG_DIGEST);
     if (dig && !p->digest) return SQS_ERR_ARG;
+    if (p && (p->flags & SQS_FLAG_COLS_SORTED)) return SQS_ERR_ARG;      // skew_transpose_u32 only
+    const bool validate = p && (p->flags & SQS_FLAG_VALIDATE);
+    if (validate && (!p->workspace || p->workspace_bytes < 256)) return SQS_ERR_WORKSPACE;
     Engine<K, HV> e;
     e.A = in; e.VA = vin; e.D = out; e.VD = vout;
     e.cutoff = C;
@@ -828,7 +861,19 @@ int run_sort(uint64_t n, K *in, uint32_t *vin, K *out, uint32_t *vout, uint64_t 
     e.digest = dig;
     e.digest_ptr = dig ? reinterpret_cast<unsigned long long *>(p->digest) : nullptr;
     e.alg1 = p && (p->flags & SQS_FLAG_ALG1_PIVOTS);
-    return e.sort_root(n, seed);
+    if (int rc = e.sort_root(n, seed)) return rc;
+    if (!validate) return SQS_OK;
+    // SQS_FLAG_VALIDATE: the output must be in key order
+    e.ws.top = 0;
+    uint32_t *flag = e.ws.template take<uint32_t>(1);
+    if (!flag) return SQS_ERR_WORKSPACE;
+    k_fill_u32<<<1, 64, 0, e.st>>>(flag, 1, 0u);
+    k_check_sorted<K><<<std::min<uint64_t>(cdiv(n, 256), 4096), 256, 0, e.st>>>(out, n, n, flag);
+    uint32_t bad = 0;
+    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, e.st) != hipSuccess ||
+        hipStreamSynchronize(e.st) != hipSuccess)
+        return SQS_ERR_DEVICE;
+    return bad ? SQS_ERR_DEVICE : SQS_OK;
 }
 
 }  // namespace
@@ -891,6 +936,8 @@ int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket
     e.alg1 = params->flags & SQS_FLAG_ALG1_PIVOTS;
     e.skew_out = out;
     e.skew_bs = reinterpret_cast<unsigned long long *>(bucket_start);
+    e.cols_sorted = params->flags & SQS_FLAG_COLS_SORTED;
+    e.validate = params->flags & SQS_FLAG_VALIDATE;
     std::vector<HostNode> root{{0, (uint32_t)n, splitmix(seed)}};
     return e.run_batch(root, 0);
 }
@@ -933,6 +980,7 @@ int run_batched(uint32_t count, const uint64_t *offsets, K *in, uint32_t *vin, K
     if (!params || !params->workspace || params->workspace_bytes < need) return SQS_ERR_WORKSPACE;
     const bool dig = params->flags & SQS_FLAG_DIGEST;
     if (dig && !params->digest) return SQS_ERR_ARG;
+    if (params->flags & (SQS_FLAG_COLS_SORTED | SQS_FLAG_VALIDATE)) return SQS_ERR_ARG;   // single-instance flags
     Engine<K, HV> e;
     e.A = in; e.VA = vin; e.D = out; e.VD = vout;
     e.cutoff = C;
@@ -1003,7 +1051,7 @@ const char *sqs_status_string(int s)
     case SQS_ERR_ALIAS: return "input and output overlap";
     case SQS_ERR_WORKSPACE: return "workspace missing or too small";
     case SQS_ERR_DEVICE: return "HIP launch or copy failed";
-    case SQS_ERR_PRECOND: return "Alg. 1 pivot rule: no sample of distinct pivots (input lacks distinct keys)";
+    case SQS_ERR_PRECOND: return "precondition failed (Alg. 1 pivot rule without distinct samples, or unsorted columns given as sorted)";
     case SQS_ERR_DEPTH: return "recursion too deep";
     case SQS_ERR_UNSUPPORTED: return "size not supported";
     default: return "unknown status";

@@ -111,3 +111,24 @@ def test_batched_argument_errors_before_gpu_work(b):
     assert call(offs, [1, 2, 3], p=_params(ws=0x50000000, nbytes=need - 1)) == -3
     # base cases only: a list workspace, no batch metadata
     assert 0 < b.batched_workspace_bytes(np.array([0, 10, 20], dtype=np.uint64)) < need
+
+
+def test_flag_errors_before_gpu_work(b):
+    """Flags an entry point does not take are rejected before any GPU work:
+    SQS_FLAG_COLS_SORTED outside skew_transpose_u32, the single-instance
+    flags on the batched calls; SQS_FLAG_VALIDATE needs a workspace."""
+    import numpy as np
+    fake_in, fake_out = 0x10000000, 0x20000000
+    p = _params()
+    p.flags = b.FLAG_COLS_SORTED
+    assert _call_u32(b, 100, fake_in, fake_out, p) == -1
+    p = _params()
+    p.flags = b.FLAG_VALIDATE
+    assert _call_u32(b, 100, fake_in, fake_out, p) == -3
+    offs = np.array([0, 10, 20], dtype=np.uint64)
+    seeds = np.array([1, 2], dtype=np.uint64)
+    for fl in (b.FLAG_VALIDATE, b.FLAG_COLS_SORTED):
+        p = _params(ws=0x50000000, nbytes=1 << 30)
+        p.flags = fl
+        assert b.lib.squaresort_batched_u32(2, offs.ctypes.data, fake_in, fake_out, seeds.ctypes.data,
+                                            ctypes.byref(p), None) == -1

@@ -1,11 +1,13 @@
 """GPU parity at the full benchmark sizes, in the launch configuration that
-bench.py times (automatic cut-off, one call per sort).
+bench.py times (automatic cut-off, one call per sort), against the oracle.
 
-The whole output is checked against what fixes it uniquely (numpy's sort for
-keys; for key/value pairs the gather identity below), and the root
-SkewTranspose intermediate, which depends on the seed, is checked on sampled
-buckets that the oracle computes one by one (oracle.root_buckets).
+Each check is whole and bit-exact: the sorted output and the recursion-tree
+digest of a sort (same seed and cut-off), the whole root SkewTranspose
+intermediate and its bucket bounds (same seed).  The oracle spreads the
+root's children over host threads (the bytes do not depend on it).
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -18,6 +20,7 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 N28 = 1 << 28
 N27 = 1 << 27
+THREADS = max(1, min(16, int(os.environ.get("OMP_NUM_THREADS", "8"))))
 
 
 @pytest.fixture(scope="module")
@@ -36,35 +39,40 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _sorted_u32(b, ws, x, seed):
+def _input(hi, data_seed):
+    return datagen.uniform_u32(N28, seed=data_seed, hi=hi) if hi else datagen.uniform_u32(N28, seed=data_seed)
+
+
+@pytest.mark.parametrize("name,hi,data_seed", [("uniform", None, 2), ("dup16", 1 << 16, 3)])
+def test_u32_full_size_matches_oracle(b, ws, name, hi, data_seed):
+    """n = 2^28 u32 (uniform over [0, 2^32) and over [0, 2^16)): output and
+    recursion-tree digest equal the oracle's at the same seed and cut-off."""
+    _say(f"u32 {name} n=2^28 data_seed={data_seed} seed=1 auto cut-off")
+    x = _input(hi, data_seed)
     inp = torch.from_numpy(x.view(np.int32)).to(DEV)
     out = torch.empty_like(inp)
-    used = b.squaresort_u32(inp, out, seed=seed, cutoff=0, ws=ws)
+    dg = torch.zeros(1, dtype=torch.int64, device=DEV)
+    used = b.squaresort_u32(inp, out, seed=1, cutoff=0, ws=ws, digest=dg)
     torch.cuda.synchronize()
     del inp
-    return out.cpu().numpy().view(np.uint32), used
-
-
-def _sample_buckets(m, rng, extra=4):
-    sel = {0, 1, m // 2, m - 2, m - 1}
-    sel.update(int(v) for v in rng.integers(0, m, size=extra))
-    return np.array(sorted(sel), dtype=np.uint64)
-
-
-@pytest.mark.parametrize("name,hi,data_seed", [("uniform", None, 2), ("dup16", 1 << 16, 3)])
-def test_u32_full_size_sorted(b, ws, name, hi, data_seed):
-    _say(f"u32 {name} n=2^28 data_seed={data_seed}")
-    x = datagen.uniform_u32(N28, seed=data_seed, hi=hi) if hi else datagen.uniform_u32(N28, seed=data_seed)
-    got, used = _sorted_u32(b, ws, x, seed=1)
+    got = out.cpu().numpy().view(np.uint32)
+    gdg = int(dg.cpu().numpy().view(np.uint64)[0])
+    del out
     assert used == b.max_cutoff(b.KIND_U32)
-    assert np.array_equal(got, np.sort(x))
+    _say(f"  oracle on {THREADS} threads")
+    with oracle.threads(THREADS):
+        want, wdg, nodes = oracle.squaresort_u32(x, 1, used, want_digest=True)
+    assert nodes >= 1
+    assert np.array_equal(got, want)
+    assert gdg == wdg
 
 
 @pytest.mark.parametrize("name,hi,data_seed", [("uniform", None, 2), ("dup16", 1 << 16, 3)])
-def test_u32_full_size_root_buckets_sampled(b, ws, name, hi, data_seed):
-    """Root intermediate at 2^28 on sampled buckets, against the oracle."""
-    _say(f"skew {name} n=2^28 sampled buckets")
-    x = datagen.uniform_u32(N28, seed=data_seed, hi=hi) if hi else datagen.uniform_u32(N28, seed=data_seed)
+def test_u32_full_size_root_intermediate(b, ws, name, hi, data_seed):
+    """The whole root SkewTranspose intermediate at 2^28 and its bucket
+    bounds, against the oracle's."""
+    _say(f"skew {name} n=2^28 data_seed={data_seed} seed=1")
+    x = _input(hi, data_seed)
     m = oracle.ceil_isqrt(N28)
     inp = torch.from_numpy(x.view(np.int32)).to(DEV)
     out = torch.empty_like(inp)
@@ -75,39 +83,33 @@ def test_u32_full_size_root_buckets_sampled(b, ws, name, hi, data_seed):
     got = out.cpu().numpy().view(np.uint32)
     starts = bs.cpu().numpy().view(np.uint64)
     del out
-    assert starts[0] == 0 and starts[m] == N28 and np.all(np.diff(starts.astype(np.int64)) >= 0)
-    sel = _sample_buckets(m, np.random.default_rng(data_seed))
-    _, bounds, keys = oracle.root_buckets(x.astype(np.uint64), 1, sel)
-    at = 0
-    for s, (lo, hi_) in zip(sel, bounds):
-        lo, hi_ = int(lo), int(hi_)
-        assert (int(starts[s]), int(starts[s + 1])) == (lo, hi_), f"bucket {s}"
-        assert np.array_equal(got[lo:hi_].astype(np.uint64), keys[at:at + hi_ - lo]), f"bucket {s}"
-        at += hi_ - lo
+    _say(f"  oracle root intermediate on {THREADS} threads")
+    with oracle.threads(THREADS):
+        want, wbs = oracle.root_intermediate(x.astype(np.uint64), seed=1)
+    assert np.array_equal(starts, wbs)
+    assert np.array_equal(got.astype(np.uint64), want)
 
 
 def test_kv_mixture_full_size(b, ws):
-    """2^27 (u64 key, u32 index) pairs: the output is the stable sort.
-
-    With v the output values and k the output keys: v is a permutation of
-    0..n-1, k[i] = keys_in[v[i]], k is non-decreasing, and v increases within
-    every run of equal keys; these properties hold only for the stable sort.
-    """
-    _say("kv mixture n=2^27")
+    """2^27 (u64 key, u32 index) pairs of the key/value mixture: keys, values
+    and digest equal the oracle's (stable order by key, then index)."""
+    _say("kv mixture n=2^27 data_seed=4 seed=1 auto cut-off")
     k, v = datagen.kv_mixture(N27, seed=4)
-    assert np.array_equal(v, np.arange(N27, dtype=np.uint32))
     ki = torch.from_numpy(k.view(np.int64)).to(DEV)
     vi = torch.from_numpy(v.view(np.int32)).to(DEV)
     ko, vo = torch.empty_like(ki), torch.empty_like(vi)
-    used = b.squaresort_kv(ki, vi, ko, vo, seed=1, cutoff=0, ws=ws)
+    dg = torch.zeros(1, dtype=torch.int64, device=DEV)
+    used = b.squaresort_kv(ki, vi, ko, vo, seed=1, cutoff=0, ws=ws, digest=dg)
     torch.cuda.synchronize()
     del ki, vi
     gk = ko.cpu().numpy().view(np.uint64)
     gv = vo.cpu().numpy().view(np.uint32)
+    gdg = int(dg.cpu().numpy().view(np.uint64)[0])
     del ko, vo
     assert used == b.max_cutoff(b.KIND_KV)
-    assert np.array_equal(np.bincount(gv, minlength=N27), np.ones(N27, np.int64))
-    assert np.array_equal(gk, k[gv])
-    assert np.all(gk[1:] >= gk[:-1])
-    eq = gk[1:] == gk[:-1]
-    assert np.all(gv[1:][eq] > gv[:-1][eq])
+    _say(f"  oracle on {THREADS} threads")
+    with oracle.threads(THREADS):
+        wk, wv, wdg, _ = oracle.squaresort_kv(k, v, 1, used, want_digest=True)
+    assert np.array_equal(gk, wk)
+    assert np.array_equal(gv, wv)
+    assert gdg == wdg

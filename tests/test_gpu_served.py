@@ -1,9 +1,11 @@
 """Served form on the GPU: every request's result is the same alone and in
-the mix (same seed, so bit-identical), and it is the sort of its input."""
+the mix (same seed, so bit-identical), and equal to the oracle's SquareSort
+of its input (same seed and cut-off)."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2407_14801_amd import datagen
 
 pytestmark = pytest.mark.gpu
@@ -36,14 +38,16 @@ def test_served_results_identical_alone_and_in_the_mix():
     srv.drain(len(reqs))
     assert len({r.batch for r in reqs}) < len(reqs)                # some requests shared a batch
     alone = PlainExecutor(DEV)
+    from paper_2407_14801_amd import binding
     for s, r in zip(specs, reqs):
         a = Request(id=r.id, kind=r.kind, n=r.n, seed=r.seed, keys=r.keys, vals=r.vals)
         alone(a.kind, [a])
         assert torch.equal(a.out_keys, r.out_keys), f"request {r.id}"
         if r.kind == "u32":
-            assert np.array_equal(r.out_keys.cpu().numpy().view(np.uint32), np.sort(s["keys"]))
+            want = oracle.squaresort_u32(s["keys"], r.seed, binding.max_cutoff(binding.KIND_U32))
+            assert np.array_equal(r.out_keys.cpu().numpy().view(np.uint32), want), f"request {r.id}"
         else:
             assert torch.equal(a.out_vals, r.out_vals), f"request {r.id}"
-            order = np.argsort(s["keys"], kind="stable")
-            assert np.array_equal(r.out_keys.cpu().numpy().view(np.uint64), s["keys"][order])
-            assert np.array_equal(r.out_vals.cpu().numpy().view(np.uint32), s["vals"][order])
+            wk, wv = oracle.squaresort_kv(s["keys"], s["vals"], r.seed, binding.max_cutoff(binding.KIND_KV))
+            assert np.array_equal(r.out_keys.cpu().numpy().view(np.uint64), wk), f"request {r.id}"
+            assert np.array_equal(r.out_vals.cpu().numpy().view(np.uint32), wv), f"request {r.id}"

@@ -290,7 +290,8 @@ def test_bucket_size_tails(orc):
 
 
 def test_tree_shape_doubles_per_level(orc):
-    """The total size of the nodes at depth d is at most 2^d n (Section 3.4)."""
+    """The total size of the nodes at depth d is at most 2^d n (the proof of
+    the main theorem, Section 3.3: the total size doubles at each level)."""
     n = 1 << 16
     x = datagen.uniform_u32(n, seed=2).astype(np.uint64)
     cnt, ssum, depth = orc.tree_stats(x, seed=1, cutoff=16)
@@ -405,3 +406,196 @@ def test_alg1_tree_shape(orc):
     for d in range(depth):
         assert ssum[d] <= (2 ** d) * n
     assert 2 <= depth <= 8
+
+
+# ------------------------------------- default-rule pivots, strict flags, digest
+M64 = (1 << 64) - 1
+
+
+def py_sm64(x):
+    """SplitMix64's first output from state x, from its published definition
+    (pinned below against the published vector)."""
+    z = (x + GAMMA) & M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def py_draw(K, t, n):
+    return (py_sm64(K ^ py_sm64((1 << 63) | t)) * n) >> 64
+
+
+def py_child(K, phase, i):
+    return py_sm64(K ^ py_sm64(2 * i + phase))
+
+
+def py_ceil_isqrt(n):
+    r = math.isqrt(n)
+    return r + (r * r < n)
+
+
+def test_python_generator_matches_published_vector():
+    vals = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert [py_sm64((k * GAMMA) & M64) for k in range(len(vals))] == vals
+
+
+@pytest.mark.parametrize("n,seed", [(5, 1), (70, 3), (1000, 2), (4097, 9), (65536 + 77, 5)])
+def test_default_pivots_are_the_sorted_draws(orc, n, seed):
+    """Default rule (draws with replacement from the node input): the root's
+    pivots are exactly sort(x[draw(K, t, n)] for t < m-1), K the root key of
+    the seed, and a pivot is strict iff it is followed by an equal pivot
+    (Alg. 1 pivot step, read with repeats as in Section 2.1's last
+    paragraph)."""
+    g = np.random.default_rng(n)
+    x = g.integers(0, max(4, n // 3), size=n, dtype=np.uint64)   # repeats among the draws
+    m = py_ceil_isqrt(n)
+    K = py_sm64(seed)
+    pos = [py_draw(K, t, n) for t in range(m - 1)]
+    want = np.sort(x[pos])
+    want_strict = np.zeros(m - 1, np.uint8)
+    want_strict[:-1] = want[:-1] == want[1:]
+    piv, strict = orc.root_pivots(x, seed)
+    assert np.array_equal(piv, want)
+    assert np.array_equal(strict, want_strict)
+
+
+def test_strict_flags_hand_example(orc):
+    """Eight draws of the values 9,5,3,5,5,2,9,9 (n = 70, m = 9): the sorted
+    pivots are 2,3,5,5,5,9,9,9 and every member of a run of equal pivots
+    except its last is strict.  Keys then fall in buckets by the count of
+    pivots below them plus the strict pivots equal to them: a run of equal
+    pivots v ends in the single-value bucket {v}, the buckets inside the run
+    stay empty."""
+    n, m = 70, 9
+    seed = next(s for s in range(1, 1000)
+                if len({py_draw(py_sm64(s), t, n) for t in range(m - 1)}) == m - 1)
+    K = py_sm64(seed)
+    x = np.arange(1000, 1000 + n, dtype=np.uint64)          # filler, never drawn
+    vals = [9, 5, 3, 5, 5, 2, 9, 9]
+    for t, v in enumerate(vals):
+        x[py_draw(K, t, n)] = v
+    piv, strict = orc.root_pivots(x, seed)
+    assert piv.tolist() == [2, 3, 5, 5, 5, 9, 9, 9]
+    assert strict.tolist() == [0, 0, 1, 1, 0, 1, 1, 0]
+    by_hand = {1: 0, 2: 0, 3: 1, 4: 2, 5: 4, 6: 5, 8: 5, 9: 7, 10: 8}
+    for key, b in by_hand.items():
+        assert orc.bucket_of(key, piv, strict) == b, key
+
+
+def _py_bucket(x, piv, strict):
+    lo = np.searchsorted(piv, x, side="left")
+    hi = np.searchsorted(piv, x, side="right")
+    cstrict = np.concatenate([[0], np.cumsum(strict.astype(np.int64))])
+    return lo + (cstrict[hi] - cstrict[lo])
+
+
+def _walk(K, keys, vals, C, key_max, acc):
+    """SquareSort's recursion tree written out independently of the oracle:
+    every node's post-transpose array is the stable partition of its
+    column-sorted input by bucket (the SkewTranspose layout), its digest term
+    sm64(K ^ H) is appended to acc.  Returns the sorted (keys, vals)."""
+    n = keys.size
+    if n <= C:
+        o = np.argsort(keys, kind="stable")
+        return keys[o], (None if vals is None else vals[o])
+    m = py_ceil_isqrt(n)
+    piv = np.sort(keys[[py_draw(K, t, n) for t in range(m - 1)]])
+    strict = np.zeros(m - 1, np.uint8)
+    strict[:-1] = piv[:-1] == piv[1:]
+    dk, dv = keys.copy(), (None if vals is None else vals.copy())
+    for i in range(m):
+        lo, hi = min(i * m, n), min((i + 1) * m, n)
+        if hi > lo:
+            ck, cv = _walk(py_child(K, 0, i), keys[lo:hi], None if vals is None else vals[lo:hi], C, key_max, acc)
+            dk[lo:hi] = ck
+            if vals is not None:
+                dv[lo:hi] = cv
+    b = _py_bucket(dk, piv, strict)
+    o = np.argsort(b, kind="stable")
+    ak, av = dk[o], (None if vals is None else dv[o])
+    H = 0
+    for r in range(n):
+        xr = int(ak[r]) if vals is None else int(ak[r]) ^ py_sm64(int(av[r]))
+        H = (H + py_sm64(xr ^ py_sm64(r))) & M64
+    acc.append(py_sm64(K ^ H))
+    bs = np.concatenate([[0], np.cumsum(np.bincount(b, minlength=m))])
+    ok, ov = ak.copy(), (None if vals is None else av.copy())
+    p = [int(v) for v in piv]
+    for j in range(m):
+        lo, hi = int(bs[j]), int(bs[j + 1])
+        if hi == lo:
+            continue
+        L = 0 if j == 0 else (p[j - 1] if strict[j - 1] else p[j - 1] + 1)
+        U = key_max if j == m - 1 else (p[j] - 1 if strict[j] else p[j])
+        if L == U:                      # single-value bucket: copied
+            continue
+        sk, sv = _walk(py_child(K, 1, j), ak[lo:hi], None if vals is None else av[lo:hi], C, key_max, acc)
+        ok[lo:hi] = sk
+        if vals is not None:
+            ov[lo:hi] = sv
+    return ok, ov
+
+
+def test_digest_all_equal_by_hand(orc):
+    """n = 100 equal keys at cut-off 4: the root (m = 10) and its ten columns
+    (10 keys each, m = 4) are the only internal nodes; every post-transpose
+    array holds only the key 7, so the digest is sm64(K ^ H_100) plus
+    sum_i sm64(K_i ^ H_10), K_i the column keys, H_s = sum_{r<s} sm64(7 ^
+    sm64(r))."""
+    seed = 1
+    K = py_sm64(seed)
+    H = lambda s: sum(py_sm64(7 ^ py_sm64(r)) for r in range(s)) & M64
+    want = (py_sm64(K ^ H(100)) + sum(py_sm64(py_child(K, 0, i) ^ H(10)) for i in range(10))) & M64
+    _, dg, nodes = orc.squaresort_u32(np.full(100, 7, np.uint32), seed, 4, want_digest=True)
+    assert nodes == 11 and dg == want
+
+
+@pytest.mark.parametrize("n,C,hi,seed", [(30, 4, 2**32, 1), (200, 4, 2**32, 2), (1000, 4, 2**32, 3),
+                                         (1000, 4, 10, 4), (3000, 16, 300, 5), (5000, 16, 2**32, 6)])
+def test_digest_by_independent_walk(orc, n, C, hi, seed):
+    """The tree digest (and node count and output) against the recursion
+    written out independently above: a mistake in the oracle's node keys,
+    pivot draws, strict flags, SkewTranspose layout, single-value test or
+    digest terms changes one of them."""
+    x = np.random.default_rng(n + seed).integers(0, hi, size=n, dtype=np.uint64).astype(np.uint32)
+    acc = []
+    wk, _ = _walk(py_sm64(seed), x.astype(np.uint64), None, C, 2**32 - 1, acc)
+    out, dg, nodes = orc.squaresort_u32(x, seed, C, want_digest=True)
+    assert np.array_equal(out, wk.astype(np.uint32))
+    assert nodes == len(acc) and nodes >= 2
+    assert dg == sum(acc) & M64
+
+
+def test_digest_by_independent_walk_kv(orc):
+    k, v = datagen.kv_mixture(2000, seed=12)
+    acc = []
+    wk, wv = _walk(py_sm64(3), k, v, 8, 2**64 - 1, acc)
+    ko, vo, dg, nodes = orc.squaresort_kv(k, v, 3, 8, want_digest=True)
+    assert np.array_equal(ko, wk) and np.array_equal(vo, wv)
+    assert nodes == len(acc) and dg == sum(acc) & M64
+
+
+# ------------------------------------------------------------ threaded oracle
+def test_threads_give_the_same_bytes(orc):
+    """The root's children on several threads: same output, digest and node
+    count as on one thread (u32, key/value), same root intermediate."""
+    x = datagen.uniform_u32((1 << 18) + 999, seed=21)
+    a = orc.squaresort_u32(x, 3, 64, want_digest=True)
+    with orc.threads(4):
+        b = orc.squaresort_u32(x, 3, 64, want_digest=True)
+    assert np.array_equal(a[0], b[0]) and a[1:] == b[1:]
+    k, v = datagen.kv_mixture(100_000, seed=22)
+    a = orc.squaresort_kv(k, v, 4, 64, want_digest=True)
+    with orc.threads(3):
+        b = orc.squaresort_kv(k, v, 4, 64, want_digest=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2:] == b[2:]
+    y = x.astype(np.uint64)
+    ia, ba = orc.root_intermediate(y, seed=5)
+    with orc.threads(4):
+        ib, bb = orc.root_intermediate(y, seed=5)
+    assert np.array_equal(ia, ib) and np.array_equal(ba, bb)
+    ca = orc.tree_stats(y, seed=1, cutoff=16)
+    with orc.threads(4):
+        cb = orc.tree_stats(y, seed=1, cutoff=16)
+    assert all(np.array_equal(p, q) for p, q in zip(ca[:2], cb[:2])) and ca[2] == cb[2]
