@@ -11,8 +11,8 @@
  * Ownership: every buffer pointer is a DEVICE pointer owned by the caller,
  * except the offsets and seeds arrays of the batched calls (HOST arrays, read
  * before the call returns).  No call allocates memory: scratch comes from the
- * caller's workspace.  Calls are re-entrant when they use distinct
- * workspaces.
+ * caller's workspace (squaresort_u32_noalloc: from a static array the library
+ * holds per GPU).  Calls are re-entrant when they use distinct workspaces.
  *
  * Streams: every call enqueues its work on `stream` (a hipStream_t, or null
  * for the default stream).  A sort with n above the cut-off synchronises
@@ -173,6 +173,26 @@ int squaresort_kv(uint64_t n, uint64_t *keys_in, uint32_t *vals_in,
  * Synchronises `stream` once. */
 int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket_start,
                        uint64_t seed, sqs_params *params, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sort as squaresort_u32, with its scratch in a library-owned static device
+ * array of SQS_STATIC_SCRATCH_BYTES bytes on each GPU (held until the
+ * process ends) instead of the caller's workspace.  The call itself
+ * allocates nothing.  params may be null; its workspace fields are ignored;
+ * cutoff, SQS_FLAG_DIGEST (with digest), SQS_FLAG_ALG1_PIVOTS and
+ * SQS_FLAG_VALIDATE work as in squaresort_u32.  The scratch of the CURRENT
+ * device is used and a non-null stream must belong to that device
+ * (SQS_ERR_ARG otherwise).  A size whose scratch need,
+ * squaresort_workspace_bytes(n, SQS_KIND_U32, cutoff), exceeds
+ * SQS_STATIC_SCRATCH_BYTES returns SQS_ERR_WORKSPACE before any work (at the
+ * automatic cut-off every n <= 2^24 fits).  All calls on one GPU share its
+ * array and every call rewrites what it needs, so calls that overlap on one
+ * GPU (two host threads, or two streams without ordering between them)
+ * race: the caller must order them.  Other errors as squaresort_u32. */
+#define SQS_STATIC_SCRATCH_BYTES (32ull << 20)
+int squaresort_u32_noalloc(uint64_t n, uint32_t *in, uint32_t *out, uint64_t seed,
+                           sqs_params *params, void *stream);
 
 /* Batched form: many independent SquareSorts (Alg. 1 on each instance) in
  * one launch sequence.  `count` independent uint32 instances packed back to

@@ -26,6 +26,7 @@ FLAG_ALG1_PIVOTS = 2
 FLAG_VALIDATE = 4
 FLAG_COLS_SORTED = 8
 PIVOT_RULES = {"replacement": 0, "alg1": FLAG_ALG1_PIVOTS}
+STATIC_SCRATCH_BYTES = 32 << 20          # SQS_STATIC_SCRATCH_BYTES
 STATUS = {0: "SQS_OK", -1: "SQS_ERR_ARG", -2: "SQS_ERR_ALIAS", -3: "SQS_ERR_WORKSPACE",
           -4: "SQS_ERR_DEVICE", -5: "SQS_ERR_PRECOND", -6: "SQS_ERR_DEPTH", -7: "SQS_ERR_UNSUPPORTED"}
 
@@ -46,6 +47,7 @@ _SIGS = {
     "squaresort_u64": (_i, [_u64, _vp, _vp, _u64, _P, _vp]),
     "squaresort_kv": (_i, [_u64, _vp, _vp, _vp, _vp, _u64, _P, _vp]),
     "skew_transpose_u32": (_i, [_u64, _vp, _vp, _vp, _u64, _P, _vp]),
+    "squaresort_u32_noalloc": (_i, [_u64, _vp, _vp, _u64, _P, _vp]),
     "squaresort_batched_workspace_bytes": (_u64, [ctypes.c_uint32, _vp, _i, _u64]),
     "squaresort_batched_u32": (_i, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _P, _vp]),
     "squaresort_batched_kv": (_i, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _P, _vp]),
@@ -134,6 +136,22 @@ def squaresort_u32(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: 
     p, _keep = _params(n, KIND_U32, cutoff, ws, digest, pivot_rule, FLAG_VALIDATE if validate else 0)
     _check(_lib.squaresort_u32(n, _ptr(inp), _ptr(out), seed, ctypes.byref(p), _stream(inp.device)),
            "squaresort_u32")
+    return p.cutoff
+
+
+def squaresort_u32_noalloc(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: int = 0,
+                           digest: torch.Tensor | None = None, pivot_rule: str = "replacement",
+                           validate: bool = False) -> int:
+    """squaresort_u32 with the library's static per-GPU scratch instead of a
+    workspace (the call allocates nothing).  Returns the cut-off used."""
+    _check_dev(inp, out)
+    assert inp.dtype == torch.int32 and out.dtype == torch.int32 and inp.numel() == out.numel()
+    p = Params()
+    p.cutoff = cutoff
+    p.flags = (FLAG_DIGEST if digest is not None else 0) | PIVOT_RULES[pivot_rule] | (FLAG_VALIDATE if validate else 0)
+    p.digest = None if digest is None else digest.data_ptr()
+    _check(_lib.squaresort_u32_noalloc(inp.numel(), _ptr(inp), _ptr(out), seed, ctypes.byref(p),
+                                       _stream(inp.device)), "squaresort_u32_noalloc")
     return p.cutoff
 
 

@@ -831,6 +831,38 @@ bool overlap(const void *a, uint64_t abytes, const void *b, uint64_t bbytes)
     return x < y + bbytes && y < x + abytes;
 }
 
+// ------------------------------------------------------------ static scratch
+// Scratch of squaresort_u32_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels get the device address that
+// hipGetSymbolAddress returns, looked up once per device with that device
+// current and kept in scratch_ptr.
+__device__ __align__(256) unsigned char scratch[SQS_STATIC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES];
+
+// Device address of the current device's scratch.  The stream (if not null)
+// must belong to the current device: the array is per device.
+int static_scratch(hipStream_t stream, void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return SQS_ERR_DEVICE;
+    if (stream) {
+        hipDevice_t sdev = -1;
+        if (hipStreamGetDevice(stream, &sdev) != hipSuccess) return SQS_ERR_DEVICE;
+        if (sdev != dev) return SQS_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SQS_ERR_DEVICE;
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return SQS_OK;
+}
+
 template <class K, bool HV>
 int run_sort(uint64_t n, K *in, uint32_t *vin, K *out, uint32_t *vout, uint64_t seed, sqs_params *p,
              void *stream, int kind)
@@ -940,6 +972,24 @@ int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket
     e.validate = params->flags & SQS_FLAG_VALIDATE;
     std::vector<HostNode> root{{0, (uint32_t)n, splitmix(seed)}};
     return e.run_batch(root, 0);
+}
+
+int squaresort_u32_noalloc(uint64_t n, uint32_t *in, uint32_t *out, uint64_t seed, sqs_params *params,
+                           void *stream)
+{
+    sqs_params local{};
+    if (params) local = *params;
+    uint32_t C;
+    if (int rc = resolve_cutoff(SQS_KIND_U32, &local, &C)) return rc;
+    // sizes whose scratch exceeds the static array are rejected up front
+    if (n > (uint64_t)SORT_CAP && workspace_bound(n, C, 4) > SQS_STATIC_SCRATCH_BYTES) return SQS_ERR_WORKSPACE;
+    void *scr = nullptr;
+    if (int rc = static_scratch((hipStream_t)stream, &scr)) return rc;
+    local.workspace = scr;
+    local.workspace_bytes = SQS_STATIC_SCRATCH_BYTES;
+    const int rc = run_sort<uint32_t, false>(n, in, nullptr, out, nullptr, seed, &local, stream, SQS_KIND_U32);
+    if (params) params->cutoff = local.cutoff;
+    return rc;
 }
 
 uint64_t squaresort_batched_workspace_bytes(uint32_t count, const uint64_t *offsets, int kind, uint64_t cutoff)

@@ -132,3 +132,17 @@ def test_flag_errors_before_gpu_work(b):
         p.flags = fl
         assert b.lib.squaresort_batched_u32(2, offs.ctypes.data, fake_in, fake_out, seeds.ctypes.data,
                                             ctypes.byref(p), None) == -1
+
+
+def test_noalloc_argument_errors_before_gpu_work(b):
+    """squaresort_u32_noalloc rejects a bad cut-off, and sizes whose scratch
+    exceeds the static array, before it touches the GPU."""
+    fake_in, fake_out = 0x10000000, 0x80000000
+    lim = b.STATIC_SCRATCH_BYTES
+    assert b.lib.squaresort_u32_noalloc(10, fake_in, fake_out, 1, ctypes.byref(_params(cutoff=3)), None) == -1
+    assert b.workspace_bytes(1 << 24, b.KIND_U32, 0) <= lim < b.workspace_bytes(1 << 26, b.KIND_U32, 0)
+    assert b.lib.squaresort_u32_noalloc(1 << 26, fake_in, fake_out, 1, ctypes.byref(_params()), None) == -3
+    assert b.workspace_bytes(1 << 20, b.KIND_U32, 64) > lim
+    assert b.lib.squaresort_u32_noalloc(1 << 20, fake_in, fake_out, 1, ctypes.byref(_params(cutoff=64)), None) == -3
+    # params may be null (automatic cut-off): still rejected by size
+    assert b.lib.squaresort_u32_noalloc(1 << 26, fake_in, fake_out, 1, None, None) == -3
