@@ -507,10 +507,69 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
             }
         };
         // Each pivot's position in the sorted column (keys at or below it).
-        // The slice's first and last pivot are searched over the whole
-        // column (or their digit's range), the others inside that bracket;
-        // the searches of one step are independent, so their LDS reads
-        // overlap.
+        bool counted = false;
+        if constexpr (sizeof(K) == 4 && !HV) {
+            if (binned == 1) {
+                // Sorted by bins: the position is the start of the pivot's bin
+                // plus the keys of that bin at or below it.  A bin of a sort
+                // that succeeded holds at most BIN_NET = 16 keys (or, with
+                // bins of width one, keys of one value only), so five fixed
+                // halving steps find them; the steps of the 16 pivots are
+                // independent, so their LDS reads overlap.
+                static_assert(BIN_NET <= 16, "five halving steps cover a bin");
+                const uint32_t *bst = bin_starts(sm);
+                const uint32_t nbin = rlast + 1u, c0 = (uint32_t)clo;
+                const uint32_t nq = t0 < npiv ? min((uint32_t)PPT, npiv - t0) : 0u;
+                uint32_t la[PPT], le[PPT], lx[PPT];
+#pragma unroll
+                for (int q = 0; q < PPT; ++q) {
+                    const uint32_t p = (uint32_t)piv_of<K>(praw, q);
+                    const bool s = strict_of(sraw, q);
+                    uint32_t a = 0u, e = 0u, xe = 0u;          // below every key: position 0
+                    if (p > c0 || (p == c0 && !s)) {
+                        const uint32_t x = p - c0, d = x >> rsh;
+                        if (d >= nbin) {                     // at or above every key
+                            a = len;
+                            e = len;
+                        } else {
+                            a = bst[d];
+                            e = d + 1u < nbin ? bst[d + 1] : len;
+                            if (rsh == 0) {                  // a bin of the one value x
+                                a = s ? a : e;
+                                e = a;
+                            }
+                            xe = x - (s ? 1u : 0u);          // keys <= xe are at or below p
+                        }
+                    }
+                    la[q] = a;
+                    le[q] = e;
+                    lx[q] = xe;
+                }
+#pragma unroll
+                for (int stp = 16; stp >= 1; stp >>= 1) {
+#pragma unroll
+                    for (int q = 0; q < PPT; ++q) {
+                        const uint32_t mid = la[q] + (uint32_t)stp;
+                        const uint32_t v = sm.s.buf[min(mid, max(le[q], 1u)) - 1u];
+                        if (mid <= le[q] && v <= lx[q]) la[q] = mid;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < PPT; ++q) {
+                    if (q < (int)nq) {
+                        const uint32_t t = t0 + q;
+                        P[q] += la[q];
+                        if ((t + 1) % TB == 0) b.srcOff[nd.src + (uint64_t)((t + 1) / TB) * m + i] = la[q];
+                    }
+                }
+                counted = true;
+            }
+        }
+        // Otherwise the slice's first and last pivot are searched over the
+        // whole column (or their last-pass digit's range), the others inside
+        // that bracket; the searches of one step are independent, so their
+        // LDS reads overlap.
+        if (!counted) {
 #pragma unroll
         for (int h = 0; h < PPT / PH; ++h) {
             const uint32_t th = t0 + h * PH;
@@ -569,6 +628,7 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
                     }
                 }
             }
+        }
         }
         if (threadIdx.x == 0) {
             b.srcOff[nd.src + i] = 0;
