@@ -175,6 +175,7 @@ template <int NW, int IPT> struct SortSmem {
         struct {
             RankTab<256> tab[NW];
             uint32_t buf[CAP];
+            uint32_t pad[16];        // the bin sort's all-ones words after the last key
         } s;
         uint64_t k64[CAP];
         uint32_t k32[2 * CAP];
@@ -406,13 +407,18 @@ __device__ inline void oddeven_regs(uint32_t (&x)[N])
     }
 }
 
-// sorts the c <= N keys at buf[s ..) (lanes with c < 2 leave theirs alone)
+// Sorts the c <= N keys at buf[s ..), the keys of one bin (lanes with c < 2
+// leave theirs alone).  It reads N words from s on without a bounds test:
+// the words past the bin hold keys of later bins (sorted or not yet) or the
+// all-ones words the bin sort put after the last key, all at least as large
+// as the bin's keys, so the first c outputs of the network are the bin's
+// keys in order; only those are written back.
 template <int N>
 __device__ inline void bin_net(uint32_t *buf, uint32_t s, uint32_t c)
 {
     uint32_t x[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j) x[j] = (uint32_t)j < c ? buf[s + j] : 0xffffffffu;
+    for (int j = 0; j < N; ++j) x[j] = buf[s + j];
     oddeven_regs<N>(x);
 #pragma unroll
     for (int j = 0; j < N; ++j)
@@ -421,6 +427,7 @@ __device__ inline void bin_net(uint32_t *buf, uint32_t s, uint32_t c)
 
 constexpr int BIN_NET = 16;                  // largest bin sorted in registers (a 32-key
                                              // network needs twice the registers)
+static_assert(BIN_NET <= 16, "the pad words of SortSmem and WaveSmem cover a network's reads");
 
 // Sort of `count` 32-bit keys without values (block_rows / bpos layout) by
 // bins of the key range: bin = (key - lo) >> sh for the fewest bins of equal
@@ -513,6 +520,7 @@ __device__ int bin_sort(uint32_t (&k)[IPT], uint32_t count, SortSmem<NW, IPT> &s
         if (BPT * t + q < nbin) st[BPT * t + q] = run;
         run += c[q];
     }
+    if (t < (uint32_t)BIN_NET) sm.s.buf[count + t] = 0xffffffffu;   // above every key (minus lo)
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < IPT; ++r)
@@ -592,6 +600,7 @@ __device__ inline void lds_sort(K (&k)[IPT], uint32_t (&v)[IPT], uint32_t count,
 template <int R> struct WaveSmem {
     RankTab<256> tab;
     uint32_t buf[R * WAVE];
+    uint32_t pad[16];                // the bin sort's all-ones words after the last key
 };
 
 template <class K, bool HV, int R>
@@ -711,6 +720,7 @@ __device__ int wave_bin_sort(uint32_t (&k)[R], uint32_t count, WaveSmem<R> &sm, 
     const uint32_t s4 = c.x + c.y + c.z + c.w;
     const uint32_t run = wave_incl_scan(s4) - s4;
     *reinterpret_cast<uint4 *>(&st[4 * l]) = make_uint4(run, run + c.x, run + c.x + c.y, run + c.x + c.y + c.z);
+    if (l < (uint32_t)BIN_NET) sm.buf[count + l] = 0xffffffffu;      // above every key (minus lo)
     wave_lds_sync();
 #pragma unroll
     for (int r = 0; r < R; ++r)

@@ -512,54 +512,57 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
             if (binned == 1) {
                 // Sorted by bins: the position is the start of the pivot's bin
                 // plus the keys of that bin at or below it.  A bin of a sort
-                // that succeeded holds at most BIN_NET = 16 keys (or, with
-                // bins of width one, keys of one value only), so five fixed
-                // halving steps find them; the steps of the 16 pivots are
-                // independent, so their LDS reads overlap.
+                // that succeeded holds at most BIN_NET = 16 keys (bins of
+                // width one: keys of one value only, so their start or end is
+                // the position), and every key after the bin is larger than
+                // the pivot, so five halving steps over the 16 words from the
+                // bin's start (reads clamped to the column's last key, the
+                // result to the column's length) find it without the bin's
+                // end; the steps of the 16 pivots are independent, so their
+                // LDS reads overlap.
                 static_assert(BIN_NET <= 16, "five halving steps cover a bin");
                 const uint32_t *bst = bin_starts(sm);
-                const uint32_t nbin = rlast + 1u, c0 = (uint32_t)clo;
+                const uint32_t nbin = rlast + 1u, c0 = (uint32_t)clo, last = len - 1u;
                 const uint32_t nq = t0 < npiv ? min((uint32_t)PPT, npiv - t0) : 0u;
-                uint32_t la[PPT], le[PPT], lx[PPT];
+                uint32_t la[PPT], lx[PPT];
+                bool lsr[PPT];
 #pragma unroll
                 for (int q = 0; q < PPT; ++q) {
                     const uint32_t p = (uint32_t)piv_of<K>(praw, q);
                     const bool s = strict_of(sraw, q);
-                    uint32_t a = 0u, e = 0u, xe = 0u;          // below every key: position 0
+                    uint32_t a = 0u, xe = 0u;               // below every key: position 0
+                    bool sr = false;
                     if (p > c0 || (p == c0 && !s)) {
                         const uint32_t x = p - c0, d = x >> rsh;
-                        if (d >= nbin) {                     // at or above every key
-                            a = len;
-                            e = len;
-                        } else {
+                        if (d >= nbin) a = len;              // above every key
+                        else if (rsh == 0) a = s ? bst[d] : (d + 1u < nbin ? bst[d + 1] : len);
+                        else {
                             a = bst[d];
-                            e = d + 1u < nbin ? bst[d + 1] : len;
-                            if (rsh == 0) {                  // a bin of the one value x
-                                a = s ? a : e;
-                                e = a;
-                            }
                             xe = x - (s ? 1u : 0u);          // keys <= xe are at or below p
+                            sr = true;
                         }
                     }
                     la[q] = a;
-                    le[q] = e;
                     lx[q] = xe;
+                    lsr[q] = sr;
                 }
+                if (rsh > 0) {
 #pragma unroll
-                for (int stp = 16; stp >= 1; stp >>= 1) {
+                    for (int stp = 16; stp >= 1; stp >>= 1) {
 #pragma unroll
-                    for (int q = 0; q < PPT; ++q) {
-                        const uint32_t mid = la[q] + (uint32_t)stp;
-                        const uint32_t v = sm.s.buf[min(mid, max(le[q], 1u)) - 1u];
-                        if (mid <= le[q] && v <= lx[q]) la[q] = mid;
+                        for (int q = 0; q < PPT; ++q) {
+                            const uint32_t v = sm.s.buf[min(la[q] + (uint32_t)(stp - 1), last)];
+                            if (lsr[q] && v <= lx[q]) la[q] += (uint32_t)stp;
+                        }
                     }
                 }
 #pragma unroll
                 for (int q = 0; q < PPT; ++q) {
                     if (q < (int)nq) {
                         const uint32_t t = t0 + q;
-                        P[q] += la[q];
-                        if ((t + 1) % TB == 0) b.srcOff[nd.src + (uint64_t)((t + 1) / TB) * m + i] = la[q];
+                        const uint32_t a = min(la[q], len);
+                        P[q] += a;
+                        if ((t + 1) % TB == 0) b.srcOff[nd.src + (uint64_t)((t + 1) / TB) * m + i] = a;
                     }
                 }
                 counted = true;
