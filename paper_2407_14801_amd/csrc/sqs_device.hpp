@@ -183,6 +183,9 @@ template <int NW, int IPT> struct SortSmem {
     uint32_t wsum[NW];
     uint32_t red32[2 * NW];
     unsigned long long red64[2 * NW];
+    // the bin sort's per-wave list of bins of more than 8 keys (start, size)
+    static constexpr int BLW = NW >= 16 ? 64 : 32;
+    uint2 bl[NW][BLW];
 };
 
 template <int NW, int IPT>
@@ -529,17 +532,58 @@ __device__ int bin_sort(uint32_t (&k)[IPT], uint32_t count, SortSmem<NW, IPT> &s
             sm.s.buf[st[x >> sh] + rk[r]] = x;
         }
     __syncthreads();
+    // Bins of at most 8 keys (all but about 2% for uniform keys) by 4- or
+    // 8-key networks, as large as the wave's largest such bin needs; the
+    // wave's larger bins are then listed and sorted together, one per lane,
+    // by 16-key networks (or, past the list's room, iteration by iteration).
+    // A network sized by every bin of the wave would mostly be the 16-key one.
+    uint32_t bigit = 0u;                           // iterations whose bin holds more than 8 keys
+    if (sh > 0) {
 #pragma unroll 1
-    for (int it = 0; it < BPT; ++it) {
-        if ((uint32_t)it * NT >= nbin) break;         // no bin left (uniform)
-        const uint32_t bb = t + (uint32_t)it * NT;
-        const uint32_t cb = bb < nbin ? cnt[bb] : 0u;
-        const uint32_t s = bb < nbin ? st[bb] : 0u;
-        const uint32_t cm = sh > 0 ? wave_max(cb) : 0u; // uniform within the wave
-        if (cm <= 1u) continue;
-        if (cm <= 4u) bin_net<4>(sm.s.buf, s, cb);
-        else if (cm <= 8u) bin_net<8>(sm.s.buf, s, cb);
-        else bin_net<16>(sm.s.buf, s, cb);
+        for (int it = 0; it < BPT; ++it) {
+            if ((uint32_t)it * NT >= nbin) break;     // no bin left (uniform)
+            const uint32_t bb = t + (uint32_t)it * NT;
+            const uint32_t cb = bb < nbin ? cnt[bb] : 0u;
+            const uint32_t s = bb < nbin ? st[bb] : 0u;
+            const bool big = cb > 8u;
+            bigit |= (big ? 1u : 0u) << it;
+            const uint32_t cs = big ? 0u : cb;
+            const uint32_t cm = wave_max(cs);        // uniform within the wave
+            if (cm <= 1u) continue;
+            if (cm <= 4u) bin_net<4>(sm.s.buf, s, cs);
+            else bin_net<8>(sm.s.buf, s, cs);
+        }
+        const uint32_t nbig = (uint32_t)__popc(bigit);
+        const uint32_t incl = wave_incl_scan(nbig);
+        const uint32_t tot = __shfl(incl, WAVE - 1, WAVE);
+        if (tot > 0u) {
+            constexpr int BLW = SortSmem<NW, IPT>::BLW;
+            if (tot <= (uint32_t)BLW) {
+                uint2 *bl = sm.bl[w];
+                uint32_t o = incl - nbig;
+#pragma unroll 1
+                for (int it = 0; it < BPT; ++it) {
+                    if ((bigit >> it) & 1u) {
+                        const uint32_t bb = t + (uint32_t)it * NT;
+                        bl[o++] = make_uint2(st[bb], cnt[bb]);
+                    }
+                }
+                wave_lds_sync();
+                const uint32_t l = lane_id();
+                if (l < tot) {
+                    const uint2 e = bl[l];
+                    bin_net<16>(sm.s.buf, e.x, e.y);
+                }
+            } else {
+#pragma unroll 1
+                for (int it = 0; it < BPT; ++it) {
+                    if (__ballot((bigit >> it) & 1u) == 0ull) continue;
+                    const uint32_t bb = t + (uint32_t)it * NT;
+                    const bool big = (bigit >> it) & 1u;
+                    bin_net<16>(sm.s.buf, big ? st[bb] : 0u, big ? cnt[bb] : 0u);
+                }
+            }
+        }
     }
     __syncthreads();
     // every row (positions past count read stale words of the buffer, which
