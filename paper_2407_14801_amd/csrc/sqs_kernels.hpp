@@ -2021,6 +2021,246 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
     }
 }
 
+// ---- Small nodes sorted on chip.  A node of at most SN_CAP 32-bit keys
+// whose columns are base cases (ceil(sqrt n) <= cut-off) is processed with
+// its whole subtree by one work-group: every bucket of such a node is smaller
+// and has the same property, so no recursion step leaves the work-group.  The
+// steps are Alg. 1's, on the node's range of A and D in global memory:
+//   pivots     m-1 draws from the node input at the node key's positions,
+//              sorted, strict flags (as the batch kernels)
+//   columns    D[column i] = sort(A[column i]): each column (at most 64 keys)
+//              sorted by one wave with a bitonic network across its lanes
+//   transpose  SkewTranspose D -> A: a stable pass by bucket index, which is
+//              the layout of Section 2.2 (bucket j, then column order)
+//   buckets    a base-case bucket of at most 64 keys sorted by one wave
+//              (bitonic), a single-value bucket copied, a larger base-case
+//              bucket (cut-offs above 64) taken from a stable sort of the
+//              node's A' by key (buckets are key ranges in order); every
+//              other bucket pushed on a work-group stack as a node of its
+//              own (child key of phase 1), processed the same way later
+// The pending nodes are disjoint ranges of more than `cutoff` >= 4 keys, so
+// the stack never holds more than SN_CAP / 5 of them.
+constexpr int SN_NW = 4;
+constexpr int SN_IPT = 16;
+constexpr int SN_NT = SN_NW * WAVE;
+constexpr uint32_t SN_CAP = SN_NW * WAVE * SN_IPT;   // 4096 keys
+constexpr uint32_t SN_STACK = SN_CAP / 5 + 1;
+constexpr uint32_t SN_MMAX = 64;                      // ceil(sqrt(SN_CAP))
+using SnSm = SortSmem<SN_NW, SN_IPT>;
+
+struct SmallNode {
+    unsigned long long off;
+    uint32_t n, pad;
+    unsigned long long key;
+};
+struct SnFrame {
+    uint16_t off, n;          // relative to the work-group's root node
+    uint32_t pad;
+    unsigned long long key;
+};
+
+// ascending bitonic sort of one key per lane across the 64 lanes of a wave
+__device__ inline uint32_t wave_bitonic64(uint32_t x)
+{
+    const uint32_t l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= WAVE; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t y = __shfl_xor(x, j, WAVE);
+            const bool keep_min = ((l & (uint32_t)j) == 0) == ((l & (uint32_t)k) == 0);
+            x = keep_min ? min(x, y) : max(x, y);
+        }
+    }
+    return x;
+}
+
+// One stable radix pass by the digits dg (< 256; rows past count must hold
+// 255): keys move to their ranks, as one pass of block_sort.  The tables must
+// be clear; they are clear again on return.  Wave 0's offsets (the first
+// position of every digit) stay in sm.s.tab[0].off until the tables are used
+// again.
+template <int NW, int IPT>
+__device__ void digit_pass(uint32_t (&k)[IPT], const uint32_t (&dg)[IPT], uint32_t count, SortSmem<NW, IPT> &sm)
+{
+    const int R = block_rows<NW, IPT>(count);
+    const int nrows = wave_rows_of(count, R);
+    RankTab<256> &tab = sm.s.tab[wave_id()];
+    uint32_t pos[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (r < nrows) pos[r] = rank_row(tab, dg[r]);
+    __syncthreads();
+    scan_tables<NW, 256>(sm.s.tab, sm.wsum);
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (r < nrows) pos[r] += tab.off[dg[r]];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (r < nrows) sm.s.buf[pos[r]] = k[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r)
+        if (r < nrows) k[r] = sm.s.buf[bpos(r, R)];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(SN_NT) void k_small_nodes(const SmallNode *roots, uint32_t count, uint32_t *A,
+                                                        uint32_t *D, uint32_t cutoff,
+                                                        unsigned long long *digest)
+{
+    __shared__ SnSm sm;
+    __shared__ SnFrame stack[SN_STACK];
+    __shared__ uint32_t piv[SN_MMAX], pivs[SN_MMAX];
+    __shared__ uint8_t pst[SN_MMAX], cls[SN_MMAX];
+    __shared__ uint32_t bsl[SN_MMAX + 1];
+    __shared__ unsigned long long hred[SN_NW];
+    __shared__ uint32_t sp_sh, bigbase_sh;
+    enum : uint8_t { B_SORT = 0, B_COPY = 1, B_NODE = 2, B_BIG = 3, B_EMPTY = 4 };
+    const uint32_t tid = threadIdx.x, l = lane_id(), w = wave_id();
+    tables_clear<SN_NW, 256>(sm.s.tab);
+    for (uint32_t ri = blockIdx.x; ri < count; ri += gridDim.x) {
+        const SmallNode root = roots[ri];
+        if (tid == 0) {
+            stack[0] = SnFrame{0, (uint16_t)root.n, 0u, root.key};
+            sp_sh = 1;
+        }
+        __syncthreads();
+        while (true) {
+            const uint32_t sp = sp_sh;
+            if (sp == 0) break;
+            const SnFrame fr = stack[sp - 1];
+            __syncthreads();
+            if (tid == 0) { sp_sh = sp - 1; bigbase_sh = 0u; }
+            const uint64_t off = root.off + fr.off;
+            const uint32_t n = fr.n;
+            const uint64_t K = fr.key;
+            uint32_t m = 1;
+            while (m * m < n) ++m;                      // ceil(sqrt n), n <= SN_CAP
+            const uint32_t npiv = m - 1;
+            const int R = block_rows<SN_NW, SN_IPT>(n);
+            const int nrows = wave_rows_of(n, R);
+            // ---- pivots: m-1 draws from the node input (A, not yet overwritten)
+            if (tid < npiv) piv[tid] = A[off + pivot_draw(K, tid, n)];
+            // ---- columns (m <= 64 keys each): one wave per column, bitonic
+            for (uint32_t i = w; i < m; i += SN_NW) {
+                const uint32_t c0 = i * m, len = c0 < n ? min(m, n - c0) : 0u;
+                if (len == 0) break;                     // the later columns are empty too
+                uint32_t x = l < len ? A[off + c0 + l] : 0xFFFFFFFFu;
+                x = wave_bitonic64(x);
+                if (l < len) sm.s.buf[c0 + l] = x;
+            }
+            __syncthreads();
+            if (tid < npiv) {                           // rank sort of the draws
+                const uint32_t x = piv[tid];
+                uint32_t rk = 0;
+                for (uint32_t u = 0; u < npiv; ++u) {
+                    const uint32_t y = piv[u];
+                    rk += (y < x || (y == x && u < tid)) ? 1u : 0u;
+                }
+                pivs[rk] = x;
+            }
+            uint32_t kk[SN_IPT], dg[SN_IPT];
+#pragma unroll
+            for (int r = 0; r < SN_IPT; ++r)
+                if (r < nrows) kk[r] = sm.s.buf[bpos(r, R)];          // D, column-major
+            __syncthreads();
+            if (tid < npiv) pst[tid] = (tid + 1 < npiv && pivs[tid] == pivs[tid + 1]) ? 1 : 0;
+            __syncthreads();
+            // ---- SkewTranspose: bucket of every key, then a stable pass by bucket
+#pragma unroll
+            for (int r = 0; r < SN_IPT; ++r) {
+                if (r < nrows) {
+                    uint32_t lo = 0, hi = npiv;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (le_pivot(kk[r], pivs[mid], pst[mid] != 0)) hi = mid; else lo = mid + 1;
+                    }
+                    dg[r] = bpos(r, R) < n ? lo : 255u;
+                }
+            }
+            digit_pass<SN_NW, SN_IPT>(kk, dg, n, sm);
+            // bucket starts from wave 0's digit offsets (read before the tables are used again)
+            if (tid < m) bsl[tid] = sm.s.tab[0].off[tid];
+            if (tid == 0) bsl[m] = n;
+            unsigned long long h = 0;
+#pragma unroll
+            for (int r = 0; r < SN_IPT; ++r) {
+                const uint32_t p = bpos(r, R);
+                if (r < nrows && p < n) {
+                    A[off + p] = kk[r];
+                    sm.s.buf[p] = kk[r];                // A' for the bucket sorts
+                    if (digest) h += splitmix((uint64_t)kk[r] ^ splitmix((uint64_t)p));
+                }
+            }
+            if (digest) {                               // the node's tree-digest term
+                h = wave_sum_u64(h);
+                if (l == 0) hred[w] = h;
+            }
+            __syncthreads();
+            if (digest && tid == 0) {
+                unsigned long long hs = 0;
+                for (int q = 0; q < SN_NW; ++q) hs += hred[q];
+                atomicAdd(digest, (unsigned long long)splitmix(K ^ hs));
+            }
+            // ---- buckets: classes, internal ones pushed
+            if (tid < m) {
+                const uint32_t j = tid, nj = bsl[j + 1] - bsl[j];
+                const uint64_t L = j == 0 ? 0ull : (pst[j - 1] ? (uint64_t)pivs[j - 1] : (uint64_t)pivs[j - 1] + 1);
+                const int64_t U = j == npiv ? (int64_t)0xFFFFFFFFu
+                                            : (pst[j] ? (int64_t)pivs[j] - 1 : (int64_t)pivs[j]);
+                const bool mono = nj > 0 && (int64_t)L == U;
+                uint8_t c = B_SORT;
+                if (nj == 0) c = B_EMPTY;
+                else if (mono) c = B_COPY;
+                else if (nj > cutoff) c = B_NODE;
+                else if (nj > (uint32_t)WAVE) c = B_BIG;
+                cls[j] = c;
+                if (c == B_BIG) bigbase_sh = 1u;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t top = sp_sh;
+                for (uint32_t j = m; j-- > 0;) {
+                    if (cls[j] != B_NODE) continue;
+                    stack[top++] = SnFrame{(uint16_t)(fr.off + bsl[j]), (uint16_t)(bsl[j + 1] - bsl[j]), 0u,
+                                           node_child_key(K, 1, j)};
+                }
+                sp_sh = top;
+            }
+            for (uint32_t j = w; j < m; j += SN_NW) {   // one wave per bucket
+                const uint8_t c = cls[j];
+                const uint32_t b0 = bsl[j], nj = bsl[j + 1] - b0;
+                if (c == B_SORT) {
+                    uint32_t x = l < nj ? sm.s.buf[b0 + l] : 0xFFFFFFFFu;
+                    x = wave_bitonic64(x);
+                    if (l < nj) D[off + b0 + l] = x;
+                } else if (c == B_COPY) {
+                    for (uint32_t q = l; q < nj; q += WAVE) D[off + b0 + q] = sm.s.buf[b0 + q];
+                }
+            }
+            if (bigbase_sh) {                           // base cases above 64 keys (cut-offs above 64)
+                uint32_t vv[SN_IPT];
+                __syncthreads();                        // buf: the bucket waves are done with it
+                block_sort<uint32_t, false, SN_NW, SN_IPT>(kk, vv, n, sm);
+#pragma unroll
+                for (int r = 0; r < SN_IPT; ++r) {
+                    const uint32_t p = bpos(r, R);
+                    if (r < nrows && p < n) {
+                        uint32_t lo = 0, hi = m;        // bucket of position p
+                        while (hi - lo > 1) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (bsl[mid] <= p) lo = mid; else hi = mid;
+                        }
+                        if (cls[lo] == B_BIG) D[off + p] = kk[r];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ---- Base-case segments larger than one LDS sort (a whole array, or the
 // instances of a batch when they are too few to fill the chip), on the whole
 // grid.  One MSD split of each segment by the top 8 bits of x - min runs over

@@ -160,6 +160,9 @@ uint64_t batch_bound(uint64_t S, uint64_t C, uint64_t key_bytes)
            S / 8 + 32 * 256;
 }
 
+// the on-chip node list of a batch of total size S (nodes of more than C keys)
+uint64_t small_list_bytes(uint64_t S, uint64_t C) { return align_up(sizeof(SmallNode) * (S / (C + 1) + 2), 256); }
+
 uint64_t workspace_bound(uint64_t n, uint64_t C, uint64_t key_bytes)
 {
     // n <= C needs no batch; the skew-transpose entry point still runs the
@@ -174,7 +177,7 @@ uint64_t workspace_bound(uint64_t n, uint64_t C, uint64_t key_bytes)
     // nested batches: a chain of column recursions, each at most the size of n
     uint64_t chain = 1;
     for (uint64_t s = ceil_isqrt_host(n); s > C && chain < 8; s = ceil_isqrt_host(s)) ++chain;
-    return chain * batch_bound(n, C, key_bytes) + (1 << 20);
+    return chain * (batch_bound(n, C, key_bytes) + small_list_bytes(n, C)) + (1 << 20);
 }
 
 // ------------------------------------------------------------ engine
@@ -245,12 +248,53 @@ template <class K, bool HV> struct Engine {
         return names.back()->c_str();
     }
 
-    int run_batch(const std::vector<HostNode> &nodes, int depth)
+    // Nodes that one work-group sorts with their whole subtree on chip (32-bit
+    // keys without values, the default pivot rule, at most SN_CAP keys and
+    // columns that are base cases): one launch of k_small_nodes; the others
+    // are returned in rest.  The node list is taken from the workspace above
+    // ws.top (the caller's frame releases it).
+    int run_small(const std::vector<HostNode> &in, std::vector<HostNode> &rest)
+    {
+        rest.clear();
+        if (!(sizeof(K) == 4 && !HV) || alg1 || skew_only) { rest = in; return SQS_OK; }
+        std::vector<SmallNode> sn;
+        uint64_t keys = 0;
+        for (const HostNode &h : in) {
+            if (h.n <= SN_CAP && ceil_isqrt_host(h.n) <= cutoff) {
+                sn.push_back(SmallNode{h.off, h.n, 0u, h.key});
+                keys += h.n;
+            } else {
+                rest.push_back(h);
+            }
+        }
+        if (sn.empty()) return SQS_OK;
+        SmallNode *dsn = ws.take<SmallNode>(sn.size());
+        if (ws.overflow) return SQS_ERR_WORKSPACE;
+        keep_.emplace_back(sn.size() * sizeof(SmallNode));
+        memcpy(keep_.back().data(), sn.data(), sn.size() * sizeof(SmallNode));
+        if (hipMemcpyAsync(dsn, keep_.back().data(), sn.size() * sizeof(SmallNode), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+            return SQS_ERR_DEVICE;
+        const uint32_t cnt = (uint32_t)sn.size();
+        launch("k_small_nodes", keys, [&] {
+            k_small_nodes<<<std::min<uint32_t>(cnt, 2048), SN_NT, 0, st>>>(
+                dsn, cnt, reinterpret_cast<uint32_t *>(A), reinterpret_cast<uint32_t *>(D), cutoff,
+                digest ? digest_ptr : nullptr); });
+        return check();
+    }
+
+    int run_batch(const std::vector<HostNode> &nodes_in, int depth)
     {
         if (depth >= SQS_MAX_DEPTH) return SQS_ERR_DEPTH;
         cur_depth = depth;
-        const uint32_t N = (uint32_t)nodes.size();
         const uint64_t mark = ws.top;
+        std::vector<HostNode> nodes;
+        if (int rc = run_small(nodes_in, nodes)) return rc;
+        if (nodes.empty()) {
+            ws.top = mark;                  // stream-ordered: later work may reuse the list's memory
+            return SQS_OK;
+        }
+        const uint32_t N = (uint32_t)nodes.size();
 
         // ---- plan the batch on the host
         std::vector<NodeDesc> desc(N);
@@ -631,7 +675,17 @@ template <class K, bool HV> struct Engine {
             return check();
         }
         std::vector<HostNode> root{{0, (uint32_t)n, splitmix(seed)}};
-        return run_batch(root, 0);
+        return finish(run_batch(root, 0));
+    }
+    // a call whose last step left host copies that async uploads read (the
+    // on-chip node list) waits for them before the copies are freed
+    int finish(int rc)
+    {
+        if (!keep_.empty()) {
+            if (hipStreamSynchronize(st) != hipSuccess && rc == SQS_OK) rc = SQS_ERR_DEVICE;
+            keep_.clear();
+        }
+        return rc;
     }
 
     // Sorts independent segments src -> dst with the base-case kernels.  pn
@@ -767,7 +821,7 @@ template <class K, bool HV> struct Engine {
             resolve_timing();
             ws.top = mark;
         }
-        if (!roots.empty()) return run_batch(roots, 0);
+        if (!roots.empty()) return finish(run_batch(roots, 0));
         return SQS_OK;
     }
 };
@@ -791,7 +845,7 @@ uint64_t batched_workspace_bound(uint32_t count, const uint64_t *offs, uint64_t 
     if (S == 0) return leaves;
     uint64_t chain = 1;
     for (uint64_t s = ceil_isqrt_host(big); s > C && chain < 8; s = ceil_isqrt_host(s)) ++chain;
-    return std::max(leaves, chain * batch_bound(S, C, key_bytes) + (1 << 20));
+    return std::max(leaves, chain * (batch_bound(S, C, key_bytes) + small_list_bytes(S, C)) + (1 << 20));
 }
 
 constexpr uint64_t key_bytes_of(int kind) { return kind == SQS_KIND_U32 ? 4 : 8; }
