@@ -221,6 +221,38 @@ int squaresort_batched_kv(uint32_t count, const uint64_t *offsets, uint64_t *key
                           uint64_t *keys_out, uint32_t *vals_out, const uint64_t *seeds,
                           sqs_params *params, void *stream);
 
+/* Batched form as a planned graph (the batched form of the survey's build
+ * plan: many instances in one launch sequence, captured once and replayed;
+ * the cut-off experiment of Section 4.2 is the precedent for choosing the
+ * cut-off ahead of the data).  Planning takes the arguments of
+ * squaresort_batched_u32 plus a device status word, does the host-side work
+ * of the call once (the plan of every recursion step that depends only on
+ * the instance sizes, uploaded synchronously into the workspace), and
+ * captures the call's launches into a HIP graph; sqs_plan_launch replays
+ * that graph on `stream` (asynchronously, no host work, no allocation),
+ * sorting whatever the instances of `in` hold at that time into `out` -- the
+ * buffers, sizes, seeds, cut-off, workspace, digest and status pointers are
+ * bound at planning time.  A replay never waits for the device: the
+ * internal buckets of every recursion step are finished on chip with their
+ * subtrees (buckets of at most 4096 keys whose columns are base cases); a
+ * bucket beyond that sets bit 1 of *status (SQS_STATUS_UNFINISHED: `out`
+ * is then incomplete, the call that does so needs squaresort_batched_u32),
+ * a device failure sets bit 2 (SQS_STATUS_DEVICE).  Every replay clears
+ * *status first; with SQS_FLAG_DIGEST (the only flag taken) every replay
+ * ADDS its digest.  The workspace (at least
+ * squaresort_batched_graph_workspace_bytes) belongs to the plan until it is
+ * destroyed.  Instances up to 2^28 keys.  Replays of one plan must not
+ * overlap.  Planning allocates host-side objects (a stream, the graph);
+ * errors as squaresort_batched_u32, plus SQS_ERR_ARG for a null status or
+ * plan pointer. */
+typedef struct sqs_plan sqs_plan;
+enum { SQS_STATUS_UNFINISHED = 1u, SQS_STATUS_DEVICE = 2u };
+uint64_t squaresort_batched_graph_workspace_bytes(uint32_t count, const uint64_t *offsets, uint64_t cutoff);
+int squaresort_batched_graph_u32(uint32_t count, const uint64_t *offsets, uint32_t *in, uint32_t *out,
+                                 const uint64_t *seeds, sqs_params *params, uint32_t *status, sqs_plan **plan);
+int sqs_plan_launch(sqs_plan *plan, void *stream);
+int sqs_plan_destroy(sqs_plan *plan);
+
 /* Measurement support (not part of the sort): while enabled, every launch is
  * bracketed by HIP events on its stream and the elapsed times are summed per
  * kernel.  sqs_timing_enable clears the table.  sqs_timing_report writes a

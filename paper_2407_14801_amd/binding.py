@@ -51,6 +51,10 @@ _SIGS = {
     "squaresort_batched_workspace_bytes": (_u64, [ctypes.c_uint32, _vp, _i, _u64]),
     "squaresort_batched_u32": (_i, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _P, _vp]),
     "squaresort_batched_kv": (_i, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _P, _vp]),
+    "squaresort_batched_graph_workspace_bytes": (_u64, [ctypes.c_uint32, _vp, _u64]),
+    "squaresort_batched_graph_u32": (_i, [ctypes.c_uint32, _vp, _vp, _vp, _vp, _P, _vp, ctypes.POINTER(_vp)]),
+    "sqs_plan_launch": (_i, [_vp, _vp]),
+    "sqs_plan_destroy": (_i, [_vp]),
     "sqs_status_string": (ctypes.c_char_p, [_i]),
     "sqs_timing_enable": (_i, [_i]),
     "sqs_timing_report": (ctypes.c_int64, [ctypes.c_char_p, _u64]),
@@ -256,6 +260,63 @@ def squaresort_batched_kv(keys_in, vals_in, keys_out, vals_out, offsets, seeds, 
                                       _ptr(vals_out), sd.ctypes.data, ctypes.byref(p), _stream(keys_in.device)),
            "squaresort_batched_kv")
     return p.cutoff
+
+
+STATUS_UNFINISHED, STATUS_DEVICE = 1, 2
+
+
+def batched_graph_workspace_bytes(offsets, cutoff: int = 0) -> int:
+    import numpy as np
+    offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+    return _lib.squaresort_batched_graph_workspace_bytes(offs.size - 1, offs.ctypes.data, cutoff)
+
+
+class BatchedGraph:
+    """squaresort_batched_graph_u32: the batched call planned once and
+    captured into a HIP graph; launch() replays it on the current stream
+    (sorting what inp holds then into out).  The buffers, workspace, digest
+    and status tensors are bound to the plan and kept alive here."""
+
+    def __init__(self, inp: torch.Tensor, out: torch.Tensor, offsets, seeds, cutoff: int = 0,
+                 digest: torch.Tensor | None = None):
+        import numpy as np
+        _check_dev(inp, out)
+        assert inp.dtype == torch.int32 and out.dtype == torch.int32 and inp.numel() == out.numel()
+        self.offs = np.ascontiguousarray(offsets, dtype=np.uint64)
+        self.seeds = np.ascontiguousarray(seeds, dtype=np.uint64)
+        count = self.offs.size - 1
+        assert self.seeds.size == count and int(self.offs[-1]) == inp.numel()
+        self.inp, self.out, self.digest = inp, out, digest
+        self.ws = torch.empty(max(batched_graph_workspace_bytes(self.offs, cutoff), 1), dtype=torch.uint8,
+                              device=inp.device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=inp.device)
+        p = Params()
+        p.cutoff = cutoff
+        p.flags = FLAG_DIGEST if digest is not None else 0
+        p.workspace = self.ws.data_ptr()
+        p.workspace_bytes = self.ws.numel()
+        p.digest = None if digest is None else digest.data_ptr()
+        torch.cuda.synchronize(inp.device)        # inputs and buffers ready before planning
+        h = ctypes.c_void_p()
+        _check(_lib.squaresort_batched_graph_u32(count, self.offs.ctypes.data, _ptr(inp), _ptr(out),
+                                                 self.seeds.ctypes.data, ctypes.byref(p),
+                                                 _ptr(self.status), ctypes.byref(h)), "squaresort_batched_graph_u32")
+        self.handle = h
+        self.cutoff = p.cutoff
+
+    def launch(self) -> None:
+        _check(_lib.sqs_plan_launch(self.handle, _stream(self.inp.device)), "sqs_plan_launch")
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            _lib.sqs_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def timing_enable(on: bool = True) -> None:

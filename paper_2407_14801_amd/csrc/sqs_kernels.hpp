@@ -2105,22 +2105,30 @@ __device__ void digit_pass(uint32_t (&k)[IPT], const uint32_t (&dg)[IPT], uint32
     __syncthreads();
 }
 
-__global__ __launch_bounds__(SN_NT) void k_small_nodes(const SmallNode *roots, uint32_t count, uint32_t *A,
-                                                        uint32_t *D, uint32_t cutoff,
-                                                        unsigned long long *digest)
+struct SnShared {
+    SnSm sm;
+    SnFrame stack[SN_STACK];
+    uint32_t piv[SN_MMAX], pivs[SN_MMAX];
+    uint8_t pst[SN_MMAX], cls[SN_MMAX];
+    uint32_t bsl[SN_MMAX + 1];
+    unsigned long long hred[SN_NW];
+    uint32_t sp_sh, bigbase_sh;
+};
+
+// The whole subtree of one on-chip node (the caller has cleared sh.sm's
+// tables once; they are clear again on return).  Ends with a barrier.
+__device__ void small_subtree(SnShared &sh, const SmallNode root, uint32_t *A, uint32_t *D, uint32_t cutoff,
+                              unsigned long long *digest)
 {
-    __shared__ SnSm sm;
-    __shared__ SnFrame stack[SN_STACK];
-    __shared__ uint32_t piv[SN_MMAX], pivs[SN_MMAX];
-    __shared__ uint8_t pst[SN_MMAX], cls[SN_MMAX];
-    __shared__ uint32_t bsl[SN_MMAX + 1];
-    __shared__ unsigned long long hred[SN_NW];
-    __shared__ uint32_t sp_sh, bigbase_sh;
+    SnSm &sm = sh.sm;
+    SnFrame *stack = sh.stack;
+    uint32_t *piv = sh.piv, *pivs = sh.pivs, *bsl = sh.bsl;
+    uint8_t *pst = sh.pst, *cls = sh.cls;
+    unsigned long long *hred = sh.hred;
+    uint32_t &sp_sh = sh.sp_sh, &bigbase_sh = sh.bigbase_sh;
     enum : uint8_t { B_SORT = 0, B_COPY = 1, B_NODE = 2, B_BIG = 3, B_EMPTY = 4 };
     const uint32_t tid = threadIdx.x, l = lane_id(), w = wave_id();
-    tables_clear<SN_NW, 256>(sm.s.tab);
-    for (uint32_t ri = blockIdx.x; ri < count; ri += gridDim.x) {
-        const SmallNode root = roots[ri];
+    {
         if (tid == 0) {
             stack[0] = SnFrame{0, (uint16_t)root.n, 0u, root.key};
             sp_sh = 1;
@@ -2259,6 +2267,67 @@ __global__ __launch_bounds__(SN_NT) void k_small_nodes(const SmallNode *roots, u
             __syncthreads();
         }
     }
+    __syncthreads();                                    // every thread has seen the empty stack
+}
+
+__global__ __launch_bounds__(SN_NT) void k_small_nodes(const SmallNode *roots, uint32_t count, uint32_t *A,
+                                                        uint32_t *D, uint32_t cutoff,
+                                                        unsigned long long *digest)
+{
+    __shared__ SnShared sh;
+    tables_clear<SN_NW, 256>(sh.sm.s.tab);
+    for (uint32_t ri = blockIdx.x; ri < count; ri += gridDim.x) small_subtree(sh, roots[ri], A, D, cutoff, digest);
+}
+
+// status bits a call that does not synchronise (a planned graph) reports in
+// its device status word
+constexpr uint32_t ST_UNFINISHED = 1u;   // an internal bucket needs a recursion step the device cannot take
+constexpr uint32_t ST_DEVICE = 2u;       // a device failure word (bounded wait, stack) or a list overflow
+
+// The internal buckets of a batch (its CLS_INTERNAL list) sorted on chip,
+// each with its subtree, when they are on-chip nodes; any other one is
+// reported as ST_UNFINISHED.  Used where the host does not read the list.
+__global__ __launch_bounds__(SN_NT) void k_internal_nodes(Batch<uint32_t> b, uint32_t *A, uint32_t *D,
+                                                           uint32_t cutoff, unsigned long long *digest,
+                                                           uint32_t *status)
+{
+    __shared__ SnShared sh;
+    tables_clear<SN_NW, 256>(sh.sm.s.tab);
+    const uint32_t cnt = min(b.ctr[CLS_INTERNAL], b.cap[CLS_INTERNAL]);
+    for (uint32_t it = blockIdx.x; it < cnt; it += gridDim.x) {
+        const BucketItem e = b.list[CLS_INTERNAL][it];
+        const NodeDesc nd = b.nodes[e.node];
+        uint32_t m = 1;
+        while (m * m < e.size && m <= SN_MMAX) ++m;
+        if (e.size <= SN_CAP && m <= cutoff) {
+            small_subtree(sh, SmallNode{nd.off + e.lo, e.size, 0u, node_child_key(nd.key, 1, e.j)}, A, D, cutoff,
+                          digest);
+        } else if (threadIdx.x == 0) {
+            atomicOr(status, ST_UNFINISHED);
+        }
+    }
+}
+
+// a batch's failure words (and, for a recursion step, its list overflows)
+// into the status word
+template <class K>
+__global__ void k_status(Batch<K> b, uint32_t *status, int step)
+{
+    if (threadIdx.x != 0) return;
+    uint32_t f = 0;
+    if (b.ctr[CTR_BIG_FAIL]) f |= ST_DEVICE;
+    if (step) {
+        if (b.ctr[CTR_TR_FAIL] || b.ctr[CTR_FAIL]) f |= ST_DEVICE;
+        for (int c = 0; c < NCLS; ++c)
+            if (b.ctr[c] > b.cap[c]) f |= ST_DEVICE;
+    }
+    if (f) atomicOr(status, f);
+}
+
+// a copy of n words (the pristine initial counters of a planned call)
+__global__ void k_copy_u32(uint32_t *dst, const uint32_t *src, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
 
 // ---- Base-case segments larger than one LDS sort (a whole array, or the

@@ -201,14 +201,42 @@ template <class K, bool HV> struct Engine {
     // check that they are, and the output's bucket bounds
     bool cols_sorted = false;
     bool validate = false;
+    // planned-graph mode: the launches are being captured into a graph that
+    // is replayed later, so nothing may wait for the device: host data go up
+    // synchronously at planning time (into workspace that is never reused),
+    // counters that kernels change are restored by a kernel from a pristine
+    // copy, failure words go to the device status word, and the internal
+    // buckets of a step are finished on chip (k_internal_nodes)
+    bool graph = false;
+    uint32_t *status_ptr = nullptr;
+    hipStream_t up = nullptr;          // planned graphs: the upload stream
+    int upload(void *dst, const void *src, size_t bytes)
+    {
+        if (graph) {                     // on a stream of its own, outside the capture, waited for at once
+            hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, up);
+            if (e == hipSuccess) e = hipStreamSynchronize(up);
+            if (e != hipSuccess && debug_on()) fprintf(stderr, "[sqs] plan upload: %s\n", hipGetErrorString(e));
+            return e == hipSuccess ? SQS_OK : SQS_ERR_DEVICE;
+        }
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess ? SQS_OK : SQS_ERR_DEVICE;
+    }
+    void release(uint64_t mark)
+    {
+        if (!graph) ws.top = mark;   // a graph replays every phase: nothing is reused
+    }
 
-    int check() const { return hipGetLastError() == hipSuccess ? SQS_OK : SQS_ERR_DEVICE; }
+    int check() const
+    {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess && debug_on()) fprintf(stderr, "[sqs] launch: %s\n", hipGetErrorString(e));
+        return e == hipSuccess ? SQS_OK : SQS_ERR_DEVICE;
+    }
 
     // launch f() on st, bracketed by timing events when timing is enabled
     int cur_depth = 0;
     template <class F> void launch(const char *name0, uint64_t units, F f)
     {
-        if (!g_timing.on) { f(); return; }
+        if (!g_timing.on || graph) { f(); return; }
         // kernels of deeper recursion steps are reported as name@d
         static thread_local std::string tmp;
         tmp = name0;
@@ -272,9 +300,7 @@ template <class K, bool HV> struct Engine {
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         keep_.emplace_back(sn.size() * sizeof(SmallNode));
         memcpy(keep_.back().data(), sn.data(), sn.size() * sizeof(SmallNode));
-        if (hipMemcpyAsync(dsn, keep_.back().data(), sn.size() * sizeof(SmallNode), hipMemcpyHostToDevice, st) !=
-            hipSuccess)
-            return SQS_ERR_DEVICE;
+        if (int rc = upload(dsn, keep_.back().data(), sn.size() * sizeof(SmallNode))) return rc;
         const uint32_t cnt = (uint32_t)sn.size();
         launch("k_small_nodes", keys, [&] {
             k_small_nodes<<<std::min<uint32_t>(cnt, 2048), SN_NT, 0, st>>>(
@@ -291,7 +317,7 @@ template <class K, bool HV> struct Engine {
         std::vector<HostNode> nodes;
         if (int rc = run_small(nodes_in, nodes)) return rc;
         if (nodes.empty()) {
-            ws.top = mark;                  // stream-ordered: later work may reuse the list's memory
+            release(mark);                  // stream-ordered: later work may reuse the list's memory
             return SQS_OK;
         }
         const uint32_t N = (uint32_t)nodes.size();
@@ -459,10 +485,8 @@ template <class K, bool HV> struct Engine {
         b.digStart = dIdx + 3 * (N + 1);
         b.bigIdx = dIdx + oBigIdx; b.bigGrp = dIdx + oBigGrp; b.NB = NB;
         b.smlIdx = dIdx + oSmlIdx; b.smlGrp = dIdx + oSmlGrp; b.NS = NS;
-        if (hipMemcpyAsync(dDesc, desc.data(), N * sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess)
-            return SQS_ERR_DEVICE;
-        if (hipMemcpyAsync(dIdx, idx.data(), idx.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess)
-            return SQS_ERR_DEVICE;
+        if (int rc = upload(dDesc, desc.data(), N * sizeof(NodeDesc))) return rc;
+        if (int rc = upload(dIdx, idx.data(), idx.size() * 4)) return rc;
 
         // ---- pivots (drawn from the node inputs before any child clobbers them)
         // counters (list sizes, take counters, key totals, the pivot-rule flag)
@@ -565,6 +589,16 @@ template <class K, bool HV> struct Engine {
         if (int rc = check()) return rc;
 
         // ---- internal buckets form the next batch
+        if (graph) {                                     // finished on chip, or reported
+            if constexpr (sizeof(K) == 4 && !HV) {
+                launch("k_internal_nodes", keysTot, [&] {
+                    k_internal_nodes<<<std::min<uint32_t>(std::max<uint32_t>(capInt, 1), 2048), SN_NT, 0, st>>>(
+                        b, reinterpret_cast<uint32_t *>(A), reinterpret_cast<uint32_t *>(D), cutoff,
+                        digest ? digest_ptr : nullptr, status_ptr); });
+            }
+            k_status<K><<<1, 64, 0, st>>>(b, status_ptr, 1);
+            return check();
+        }
         std::vector<uint32_t> hctr(CTR_WORDS);
         std::vector<BucketItem> hint(capInt);
         if (hipMemcpyAsync(hctr.data(), b.ctr, CTR_WORDS * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -608,7 +642,7 @@ template <class K, bool HV> struct Engine {
         next.reserve(hint.size());
         for (const BucketItem &e : hint)
             next.push_back({desc[e.node].off + e.lo, e.size, node_child_key(desc[e.node].key, 1, e.j)});
-        ws.top = mark;
+        release(mark);
         if (!next.empty()) return run_batch(next, depth + 1);
         return SQS_OK;
     }
@@ -631,7 +665,7 @@ template <class K, bool HV> struct Engine {
         s.cnt = ws.take<uint32_t>(256 * (uint64_t)G);
         s.items = ws.take<Span<K>>(256 * (uint64_t)nseg);
         s.ctr = ws.take<uint32_t>(CTR_WORDS);
-        ws.top = mark;                     // stream-ordered: later work on this stream may reuse it
+        release(mark);                     // stream-ordered: later work on this stream may reuse it
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         Batch<K> b{};
         b.span[CLS_BIG] = s.items; b.cap[CLS_BIG] = 256 * nseg;
@@ -651,6 +685,12 @@ template <class K, bool HV> struct Engine {
     // MSD-split kernel's stack overflow flag.
     int read_fail(const uint32_t *ctr)
     {
+        if (graph) {                                     // reported through the status word
+            Batch<K> sb{};
+            sb.ctr = const_cast<uint32_t *>(ctr);
+            k_status<K><<<1, 64, 0, st>>>(sb, status_ptr, 0);
+            return check();
+        }
         uint32_t f = 0;
         if (hipMemcpyAsync(&f, ctr + CTR_BIG_FAIL, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
@@ -681,7 +721,7 @@ template <class K, bool HV> struct Engine {
     // on-chip node list) waits for them before the copies are freed
     int finish(int rc)
     {
-        if (!keep_.empty()) {
+        if (!keep_.empty() && !graph) {
             if (hipStreamSynchronize(st) != hipSuccess && rc == SQS_OK) rc = SQS_ERR_DEVICE;
             keep_.clear();
         }
@@ -711,14 +751,18 @@ template <class K, bool HV> struct Engine {
         keep_.emplace_back(CTR_WORDS * 4, 0);
         uint32_t *hctr = reinterpret_cast<uint32_t *>(keep_.back().data());
         for (int c = CLS_SMALL; c <= CLS_BIG; ++c) hctr[c] = (uint32_t)lists[c].size();
-        if (hipMemcpyAsync(dDesc, pn.data(), pn.size() * sizeof(NodeDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipMemcpyAsync(ctr, hctr, CTR_WORDS * 4, hipMemcpyHostToDevice, st) != hipSuccess)
-            return SQS_ERR_DEVICE;
+        if (int rc = upload(dDesc, pn.data(), pn.size() * sizeof(NodeDesc))) return rc;
+        if (graph) {                                     // the take counters change: restored every replay
+            uint32_t *pctr = ws.take<uint32_t>(CTR_WORDS);
+            if (ws.overflow) return SQS_ERR_WORKSPACE;
+            if (int rc = upload(pctr, hctr, CTR_WORDS * 4)) return rc;
+            k_copy_u32<<<1, 64, 0, st>>>(ctr, pctr, CTR_WORDS);
+        } else if (int rc = upload(ctr, hctr, CTR_WORDS * 4)) {
+            return rc;
+        }
         for (int c = CLS_SMALL; c <= CLS_BIG; ++c)
-            if (!lists[c].empty() &&
-                hipMemcpyAsync(b.list[c], lists[c].data(), lists[c].size() * sizeof(BucketItem),
-                               hipMemcpyHostToDevice, st) != hipSuccess)
-                return SQS_ERR_DEVICE;
+            if (!lists[c].empty())
+                if (int rc = upload(b.list[c], lists[c].data(), lists[c].size() * sizeof(BucketItem))) return rc;
         // the sorted classes read resolved spans (one-bucket nodes: the whole key range)
         for (int c = CLS_MID4; c <= CLS_BIG; ++c) {
             if (lists[c].empty()) continue;
@@ -731,7 +775,7 @@ template <class K, bool HV> struct Engine {
             }
             b.span[c] = ws.take<Span<K>>(lists[c].size());
             if (ws.overflow) return SQS_ERR_WORKSPACE;
-            if (hipMemcpyAsync(b.span[c], hs, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return SQS_ERR_DEVICE;
+            if (int rc = upload(b.span[c], hs, bytes)) return rc;
         }
         b.nodes = dDesc;
         b.N = (uint32_t)pn.size();
@@ -810,16 +854,15 @@ template <class K, bool HV> struct Engine {
                 }
                 char *dSeg = ws.take<char>(keep_.back().size());
                 if (ws.overflow) return SQS_ERR_WORKSPACE;
-                if (hipMemcpyAsync(dSeg, hb, keep_.back().size(), hipMemcpyHostToDevice, st) != hipSuccess)
-                    return SQS_ERR_DEVICE;
+                if (int rc = upload(dSeg, hb, keep_.back().size())) return rc;
                 const uint64_t *dOff = reinterpret_cast<const uint64_t *>(dSeg);
                 const uint32_t *dN = reinterpret_cast<const uint32_t *>(dSeg + ns * 8);
                 if (int rc = split_segments(ns, hCh[ns], 0, dOff, dN, dN + ns, keys)) return rc;
             }
-            if (hipStreamSynchronize(st) != hipSuccess) return SQS_ERR_DEVICE;   // host lists outlive the uploads
+            if (!graph && hipStreamSynchronize(st) != hipSuccess) return SQS_ERR_DEVICE;   // host lists outlive the uploads
             keep_.clear();
             resolve_timing();
-            ws.top = mark;
+            release(mark);
         }
         if (!roots.empty()) return finish(run_batch(roots, 0));
         return SQS_OK;
@@ -1114,6 +1157,115 @@ int squaresort_batched_kv(uint32_t count, const uint64_t *offsets, uint64_t *key
 {
     return run_batched<uint64_t, true>(count, offsets, keys_in, vals_in, keys_out, vals_out, seeds, params,
                                        stream, SQS_KIND_KV);
+}
+
+// ------------------------------------------------------------ planned graphs
+struct sqs_plan {
+    hipStream_t cs = nullptr, up = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+uint64_t squaresort_batched_graph_workspace_bytes(uint32_t count, const uint64_t *offsets, uint64_t cutoff)
+{
+    if (!offsets) return 0;
+    if (cutoff == 0) cutoff = max_cutoff_of(SQS_KIND_U32);
+    if (cutoff < 4) cutoff = 4;
+    for (uint32_t i = 0; i < count; ++i) if (offsets[i + 1] < offsets[i]) return 0;
+    // every phase keeps its workspace (a replay runs all of them): at most
+    // the base-case lists plus the recursion steps, each within the
+    // batched bound
+    return 2 * batched_workspace_bound(count, offsets, cutoff, 4);
+}
+
+int squaresort_batched_graph_u32(uint32_t count, const uint64_t *offsets, uint32_t *in, uint32_t *out,
+                                 const uint64_t *seeds, sqs_params *params, uint32_t *status, sqs_plan **plan)
+{
+    if (!plan) return SQS_ERR_ARG;
+    *plan = nullptr;
+    uint32_t C;
+    if (int rc = resolve_cutoff(SQS_KIND_U32, params, &C)) return rc;
+    if (count == 0 || !offsets || !seeds || offsets[0] != 0 || !status || !params) return SQS_ERR_ARG;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (offsets[i + 1] < offsets[i]) return SQS_ERR_ARG;
+        // columns within one LDS sort: no recursion step through HBM counts
+        if (offsets[i + 1] - offsets[i] > max_n_lds(SQS_KIND_U32)) return SQS_ERR_UNSUPPORTED;
+    }
+    const uint64_t total = offsets[count];
+    if (total == 0 || total > 0xFFFFFFFFull) return total == 0 ? SQS_ERR_ARG : SQS_ERR_UNSUPPORTED;
+    if (!in || !out) return SQS_ERR_ARG;
+    if (overlap(in, total * 4, out, total * 4)) return SQS_ERR_ALIAS;
+    if (params->flags & ~(uint32_t)SQS_FLAG_DIGEST) return SQS_ERR_ARG;
+    const bool dig = params->flags & SQS_FLAG_DIGEST;
+    if (dig && !params->digest) return SQS_ERR_ARG;
+    const uint64_t need = squaresort_batched_graph_workspace_bytes(count, offsets, C);
+    if (!params->workspace || params->workspace_bytes < need) return SQS_ERR_WORKSPACE;
+    sqs_plan *pl = new sqs_plan;
+    hipError_t se = hipStreamCreateWithFlags(&pl->cs, hipStreamNonBlocking);
+    if (se == hipSuccess) se = hipStreamCreateWithFlags(&pl->up, hipStreamNonBlocking);
+    if (se != hipSuccess) {
+        if (debug_on()) fprintf(stderr, "[sqs] plan: stream %s\n", hipGetErrorString(se));
+        sqs_plan_destroy(pl);
+        return SQS_ERR_DEVICE;
+    }
+    const hipError_t be = hipStreamBeginCapture(pl->cs, hipStreamCaptureModeRelaxed);
+    if (be != hipSuccess) {
+        if (debug_on()) fprintf(stderr, "[sqs] plan: begin capture %s\n", hipGetErrorString(be));
+        sqs_plan_destroy(pl);
+        return SQS_ERR_DEVICE;
+    }
+    k_fill_u32<<<1, 64, 0, pl->cs>>>(status, 1, 0u);
+    int rc;
+    {
+        Engine<uint32_t, false> e;
+        e.A = in; e.VA = nullptr; e.D = out; e.VD = nullptr;
+        e.cutoff = C;
+        e.st = pl->cs;
+        e.ws.base = static_cast<char *>(params->workspace);
+        e.ws.size = params->workspace_bytes;
+        e.digest = dig;
+        e.digest_ptr = dig ? reinterpret_cast<unsigned long long *>(params->digest) : nullptr;
+        e.graph = true;
+        e.status_ptr = status;
+        e.up = pl->up;
+        rc = e.sort_many(count, offsets, seeds);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(pl->cs, &g);
+    if (debug_on()) fprintf(stderr, "[sqs] plan: engine %d, end capture %s\n", rc, hipGetErrorString(ce));
+    if (rc == SQS_OK && (ce != hipSuccess || !g)) rc = SQS_ERR_DEVICE;
+    pl->graph = g;
+    if (rc == SQS_OK) {
+        const hipError_t ie = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            if (debug_on()) fprintf(stderr, "[sqs] plan: instantiate %s\n", hipGetErrorString(ie));
+            rc = SQS_ERR_DEVICE;
+        }
+    }
+    if (rc != SQS_OK) {
+        sqs_plan_destroy(pl);
+        return rc;
+    }
+    *plan = pl;
+    return SQS_OK;
+}
+
+int sqs_plan_launch(sqs_plan *plan, void *stream)
+{
+    if (!plan || !plan->exec) return SQS_ERR_ARG;
+    return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? SQS_OK : SQS_ERR_DEVICE;
+}
+
+int sqs_plan_destroy(sqs_plan *plan)
+{
+    if (!plan) return SQS_OK;
+    int rc = SQS_OK;
+    if (plan->exec && hipGraphExecDestroy(plan->exec) != hipSuccess) rc = SQS_ERR_DEVICE;
+    if (plan->graph && hipGraphDestroy(plan->graph) != hipSuccess) rc = SQS_ERR_DEVICE;
+    if (plan->cs && hipStreamDestroy(plan->cs) != hipSuccess) rc = SQS_ERR_DEVICE;
+    if (plan->up && hipStreamDestroy(plan->up) != hipSuccess) rc = SQS_ERR_DEVICE;
+    delete plan;
+    return rc;
 }
 
 int sqs_timing_enable(int on)

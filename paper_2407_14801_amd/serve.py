@@ -35,6 +35,7 @@ class Request:
     admitted: float = 0.0
     done: float = 0.0
     batch: int = -1           # id of the batch that served it
+    ready: object = None      # event on the submitting thread's stream after the inputs were written
 
     @property
     def latency(self) -> float:
@@ -75,8 +76,16 @@ class Server:
         return self
 
     def submit(self, r: Request):
+        """Queue a request.  Its inputs may still be in flight on the caller's
+        current stream: an event recorded there now is waited for before they
+        are read.  Its outputs are complete once it is done; a consumer that
+        uses them on another stream must record_stream them there."""
         if device_bytes(r) > self.budget_bytes:
             raise ValueError(f"request {r.id} needs more than the whole budget")
+        if r.keys is not None and getattr(r.keys, "is_cuda", False):
+            import torch
+            r.ready = torch.cuda.Event()
+            r.ready.record(torch.cuda.current_stream(r.keys.device))
         with self._lock:
             r.arrival = self.clock()
             self._pending.append(r)
@@ -167,6 +176,9 @@ class GpuExecutor:
         torch, b = self.torch, self.b
         import numpy as np
         st = self.streams[kind]
+        for r in batch:                       # inputs written on the submitters' streams
+            if r.ready is not None:
+                st.wait_event(r.ready)
         with torch.cuda.stream(st):
             sizes = [r.n for r in batch]
             offs = b.batched_offsets(sizes)
@@ -212,6 +224,9 @@ class PlainExecutor:
     def __call__(self, kind, batch):
         torch, b = self.torch, self.b
         with self._mu, torch.cuda.stream(self.stream):
+            for r in batch:                   # inputs written on the submitters' streams
+                if r.ready is not None:
+                    self.stream.wait_event(r.ready)
             for r in batch:
                 if r.kind == "u32":
                     src = r.keys.clone()

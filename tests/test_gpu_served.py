@@ -34,7 +34,10 @@ def test_served_results_identical_alone_and_in_the_mix():
     print("served: 48 mixed requests", flush=True)
     specs, reqs = _requests(48, seed=21)
     srv = Server(GpuExecutor(DEV)).start()
-    replay(srv, reqs, [0.0005 * i for i in range(len(reqs))])      # arrive while others run
+    # a burst: every request after the first arrives within 0.5 ms, while
+    # the first batch is still on the device (each batch takes longer than
+    # the gap between arrivals), so later ones join shared batches
+    replay(srv, reqs, [0.0] + [0.002 + 0.00001 * i for i in range(len(reqs) - 1)])
     srv.drain(len(reqs))
     assert len({r.batch for r in reqs}) < len(reqs)                # some requests shared a batch
     alone = PlainExecutor(DEV)
