@@ -46,6 +46,8 @@ WORKLOADS = {
                         data_seed=5),
     # Poisson request stream served with admission and continuous batching
     "served": dict(kind="served", lo=1 << 12, hi=1 << 24, data_seed=6, budget_gb=64),
+    # the arrays in pinned host memory (SQS_FLAG_HOST_ARRAYS): sorted over the host link
+    "u32_host": dict(kind="host", log2n=28, dist="uniform[0,2^32)", data_seed=2),
     # distinct keys under the Alg. 1 pivot rule, against the default rule
     "u32_perm_alg1": dict(kind="alg1", log2n=28, dist="permutation of 0..n-1 times an odd constant", data_seed=8),
 }
@@ -462,6 +464,53 @@ def bench_alg1(args, wl):
     print(json.dumps(res), flush=True)
 
 
+def bench_host(args, wl):
+    """n = 2^28 uniform u32 keys in pinned host memory, sorted there by the
+    GPU (SQS_FLAG_HOST_ARRAYS; the workspace in HBM).  The input is restored
+    from a pristine host copy before each step (untimed); HIP events around
+    each call."""
+    import torch
+    from paper_2407_14801_amd import binding
+    dev = torch.device("cuda:0")
+    log2n = args.log2n or wl["log2n"]
+    n = 1 << log2n
+    print(f"# generating u32_host n=2^{log2n}", file=sys.stderr, flush=True)
+    from paper_2407_14801_amd import datagen
+    x = datagen.uniform_u32(n, seed=wl["data_seed"])
+    pristine = torch.from_numpy(x.view(np.int32))
+    inp = torch.empty(n, dtype=torch.int32).pin_memory()
+    out = torch.empty(n, dtype=torch.int32).pin_memory()
+    ws = binding.Workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+    ms = []
+    for r in range(args.warmup + args.steps):
+        inp.copy_(pristine)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        cutoff = binding.squaresort_u32(inp, out, seed=1, cutoff=args.cutoff, ws=ws, host_arrays=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r >= args.warmup:
+            ms.append(e0.elapsed_time(e1))
+    o = out.numpy().view(np.uint32)
+    sorted_ok = bool(np.all(o[1:] >= o[:-1]))
+    med = float(np.median(ms))
+    link = 6 * 4 * n                                   # 3 passes, each reading and writing the array
+    res = {"metric": "GKeys/s", "value": round(n / (med / 1e3) / 1e9, 4), "unit": "GKeys/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(med, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": f"squaresort_u32_host_2^{log2n}", "n": n, "key_dist": wl["dist"],
+                      "data_seed": wl["data_seed"], "seed": 1, "cutoff": cutoff,
+                      "arrays": "pinned host memory (SQS_FLAG_HOST_ARRAYS); workspace in HBM"},
+           "latency_ms": {"p10": round(float(np.percentile(ms, 10)), 3), "p50": round(med, 3),
+                          "p90": round(float(np.percentile(ms, 90)), 3)},
+           "host_link": {"bytes_alg": link, "achieved_gbs": round(link / (med / 1e3) / 1e9, 2),
+                         "how": "6 * 4 * n bytes: three passes each reading and writing the array"},
+           "sorted_check": sorted_ok}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -519,6 +568,8 @@ def main():
         return bench_served(args, wl)
     if wl["kind"] == "alg1":
         return bench_alg1(args, wl)
+    if wl["kind"] == "host":
+        return bench_host(args, wl)
     log2n = args.log2n or wl["log2n"]
     n = 1 << log2n
     dev = torch.device("cuda:0")

@@ -85,7 +85,17 @@ enum {
     /* skew_transpose_u32 only: the caller's columns are already sorted (the
      * state Alg. 1 reaches before SkewTranspose), so they are counted but not
      * sorted again.  Other entry points reject it (SQS_ERR_ARG). */
-    SQS_FLAG_COLS_SORTED = 8u
+    SQS_FLAG_COLS_SORTED = 8u,
+    /* squaresort_u32/u64/kv only: in, out (and the value arrays) are PINNED
+     * HOST memory (hipHostMalloc'd: mapped into the device's address space),
+     * not device memory -- the analogue of the paper's external-memory
+     * experiment (Section 4.3), with host memory in the place of the file and
+     * HBM holding only the per-level metadata (the workspace stays device
+     * memory).  Every pass reads and writes the arrays over the host link in
+     * contiguous runs; nothing of the arrays is staged in HBM.  A pointer
+     * that is not pinned host memory is SQS_ERR_ARG.  Other entry points
+     * reject the flag (SQS_ERR_ARG). */
+    SQS_FLAG_HOST_ARRAYS = 16u
 };
 
 #define SQS_MAX_DEPTH 64

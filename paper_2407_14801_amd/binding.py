@@ -25,6 +25,7 @@ FLAG_DIGEST = 1
 FLAG_ALG1_PIVOTS = 2
 FLAG_VALIDATE = 4
 FLAG_COLS_SORTED = 8
+FLAG_HOST_ARRAYS = 16
 PIVOT_RULES = {"replacement": 0, "alg1": FLAG_ALG1_PIVOTS}
 STATIC_SCRATCH_BYTES = 32 << 20          # SQS_STATIC_SCRATCH_BYTES
 STATUS = {0: "SQS_OK", -1: "SQS_ERR_ARG", -2: "SQS_ERR_ALIAS", -3: "SQS_ERR_WORKSPACE",
@@ -122,23 +123,32 @@ def _params(n, kind, cutoff, ws, digest, pivot_rule="replacement", flags=0):
     return p, buf
 
 
-def _check_dev(*ts):
+def _check_dev(*ts, host=False):
     for t in ts:
-        if not t.is_cuda or not t.is_contiguous():
+        if host:
+            if t.is_cuda or not t.is_pinned() or not t.is_contiguous():
+                raise ValueError("host_arrays: tensors must be contiguous pinned host tensors")
+        elif not t.is_cuda or not t.is_contiguous():
             raise ValueError("tensors must be contiguous device tensors")
+
+
+def _stream_of(t):
+    return _stream(t.device if t.is_cuda else torch.device("cuda", torch.cuda.current_device()))
 
 
 def squaresort_u32(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: int = 0,
                    ws: Workspace | None = None, digest: torch.Tensor | None = None,
-                   pivot_rule: str = "replacement", validate: bool = False) -> int:
+                   pivot_rule: str = "replacement", validate: bool = False, host_arrays: bool = False) -> int:
     """Sort inp (uint32 bits in an int32 tensor; clobbered) into out.  Returns
     the cut-off used.  pivot_rule "alg1" selects the Alg. 1 pivot rule;
-    validate sets SQS_FLAG_VALIDATE."""
-    _check_dev(inp, out)
+    validate sets SQS_FLAG_VALIDATE; host_arrays (SQS_FLAG_HOST_ARRAYS): inp
+    and out are pinned host tensors, sorted in place there by the GPU."""
+    _check_dev(inp, out, host=host_arrays)
     assert inp.dtype == torch.int32 and out.dtype == torch.int32 and inp.numel() == out.numel()
     n = inp.numel()
-    p, _keep = _params(n, KIND_U32, cutoff, ws, digest, pivot_rule, FLAG_VALIDATE if validate else 0)
-    _check(_lib.squaresort_u32(n, _ptr(inp), _ptr(out), seed, ctypes.byref(p), _stream(inp.device)),
+    fl = (FLAG_VALIDATE if validate else 0) | (FLAG_HOST_ARRAYS if host_arrays else 0)
+    p, _keep = _params(n, KIND_U32, cutoff, ws, digest, pivot_rule, fl)
+    _check(_lib.squaresort_u32(n, _ptr(inp), _ptr(out), seed, ctypes.byref(p), _stream_of(inp)),
            "squaresort_u32")
     return p.cutoff
 
@@ -173,13 +183,14 @@ def squaresort_u64(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: 
 
 def squaresort_kv(keys_in, vals_in, keys_out, vals_out, seed: int = 1, cutoff: int = 0,
                   ws: Workspace | None = None, digest: torch.Tensor | None = None,
-                  pivot_rule: str = "replacement", validate: bool = False) -> int:
-    _check_dev(keys_in, vals_in, keys_out, vals_out)
+                  pivot_rule: str = "replacement", validate: bool = False, host_arrays: bool = False) -> int:
+    _check_dev(keys_in, vals_in, keys_out, vals_out, host=host_arrays)
     assert keys_in.dtype == torch.int64 and vals_in.dtype == torch.int32
     n = keys_in.numel()
-    p, _keep = _params(n, KIND_KV, cutoff, ws, digest, pivot_rule, FLAG_VALIDATE if validate else 0)
+    fl = (FLAG_VALIDATE if validate else 0) | (FLAG_HOST_ARRAYS if host_arrays else 0)
+    p, _keep = _params(n, KIND_KV, cutoff, ws, digest, pivot_rule, fl)
     _check(_lib.squaresort_kv(n, _ptr(keys_in), _ptr(vals_in), _ptr(keys_out), _ptr(vals_out), seed,
-                              ctypes.byref(p), _stream(keys_in.device)), "squaresort_kv")
+                              ctypes.byref(p), _stream_of(keys_in)), "squaresort_kv")
     return p.cutoff
 
 

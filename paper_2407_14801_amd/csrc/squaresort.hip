@@ -960,6 +960,23 @@ int static_scratch(hipStream_t stream, void **out)
     return SQS_OK;
 }
 
+// The device address of pinned host memory (hipHostMalloc'd, so mapped into
+// the device's address space); SQS_ERR_ARG for any other pointer.
+template <class T> int host_array(T *&ptr)
+{
+    if (!ptr) return SQS_OK;
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+        (void)hipGetLastError();                 // clear the sticky error of an unknown pointer
+        return SQS_ERR_ARG;
+    }
+    if (at.type != hipMemoryTypeHost) return SQS_ERR_ARG;
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, ptr, 0) != hipSuccess || !d) return SQS_ERR_ARG;
+    ptr = static_cast<T *>(d);
+    return SQS_OK;
+}
+
 template <class K, bool HV>
 int run_sort(uint64_t n, K *in, uint32_t *vin, K *out, uint32_t *vout, uint64_t seed, sqs_params *p,
              void *stream, int kind)
@@ -968,6 +985,12 @@ int run_sort(uint64_t n, K *in, uint32_t *vin, K *out, uint32_t *vout, uint64_t 
     if (int rc = resolve_cutoff(kind, p, &C)) return rc;
     if (n == 0) return SQS_OK;
     if (!in || !out || (HV && (!vin || !vout))) return SQS_ERR_ARG;
+    if (p && (p->flags & SQS_FLAG_HOST_ARRAYS)) {        // the arrays stay in host memory
+        if (int rc = host_array(in)) return rc;
+        if (int rc = host_array(out)) return rc;
+        if (int rc = host_array(vin)) return rc;
+        if (int rc = host_array(vout)) return rc;
+    }
     if (n > max_n_of(kind)) return SQS_ERR_UNSUPPORTED;
     if (overlap(in, n * sizeof(K), out, n * sizeof(K))) return SQS_ERR_ALIAS;
     if (HV && (overlap(vin, n * 4, vout, n * 4) || overlap(vin, n * 4, in, n * sizeof(K)) ||
@@ -1045,6 +1068,7 @@ int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket
     uint32_t C;
     if (int rc = resolve_cutoff(SQS_KIND_U32, params, &C)) return rc;
     if (n < 2 || !in || !out) return SQS_ERR_ARG;
+    if (params && (params->flags & SQS_FLAG_HOST_ARRAYS)) return SQS_ERR_ARG;   // single sorts only
     if (n > max_n_lds(SQS_KIND_U32)) return SQS_ERR_UNSUPPORTED;
     if (overlap(in, n * 4, out, n * 4)) return SQS_ERR_ALIAS;
     const uint64_t m = ceil_isqrt_host(n);
@@ -1076,6 +1100,7 @@ int squaresort_u32_noalloc(uint64_t n, uint32_t *in, uint32_t *out, uint64_t see
 {
     sqs_params local{};
     if (params) local = *params;
+    if (local.flags & SQS_FLAG_HOST_ARRAYS) return SQS_ERR_ARG;         // device arrays only
     uint32_t C;
     if (int rc = resolve_cutoff(SQS_KIND_U32, &local, &C)) return rc;
     // sizes whose scratch exceeds the static array are rejected up front
@@ -1127,7 +1152,8 @@ int run_batched(uint32_t count, const uint64_t *offsets, K *in, uint32_t *vin, K
     if (!params || !params->workspace || params->workspace_bytes < need) return SQS_ERR_WORKSPACE;
     const bool dig = params->flags & SQS_FLAG_DIGEST;
     if (dig && !params->digest) return SQS_ERR_ARG;
-    if (params->flags & (SQS_FLAG_COLS_SORTED | SQS_FLAG_VALIDATE)) return SQS_ERR_ARG;   // single-instance flags
+    if (params->flags & (SQS_FLAG_COLS_SORTED | SQS_FLAG_VALIDATE | SQS_FLAG_HOST_ARRAYS))
+        return SQS_ERR_ARG;                                  // single-instance flags
     Engine<K, HV> e;
     e.A = in; e.VA = vin; e.D = out; e.VD = vout;
     e.cutoff = C;
