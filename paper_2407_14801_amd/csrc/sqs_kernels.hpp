@@ -2059,20 +2059,41 @@ struct SnFrame {
     unsigned long long key;
 };
 
-// ascending bitonic sort of one key per lane across the 64 lanes of a wave
-__device__ inline uint32_t wave_bitonic64(uint32_t x)
+// ascending bitonic sort of one key per lane within every aligned segment of
+// S lanes of a wave (S a power of two, 2 <= S <= 64): the partners of every
+// step lie in the same segment, and the last merge runs ascending in all
+template <int S> __device__ inline uint32_t seg_bitonic(uint32_t x)
 {
     const uint32_t l = lane_id();
 #pragma unroll
-    for (int k = 2; k <= WAVE; k <<= 1) {
+    for (int k = 2; k <= S; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
             const uint32_t y = __shfl_xor(x, j, WAVE);
-            const bool keep_min = ((l & (uint32_t)j) == 0) == ((l & (uint32_t)k) == 0);
+            const bool up = k == S || (l & (uint32_t)k) == 0;
+            const bool keep_min = ((l & (uint32_t)j) == 0) == up;
             x = keep_min ? min(x, y) : max(x, y);
         }
     }
     return x;
+}
+// the same for a wave-uniform segment size S in {4, 8, 16, 32, 64}
+__device__ inline uint32_t seg_bitonic_rt(uint32_t x, uint32_t S)
+{
+    switch (S) {
+    case 4: return seg_bitonic<4>(x);
+    case 8: return seg_bitonic<8>(x);
+    case 16: return seg_bitonic<16>(x);
+    case 32: return seg_bitonic<32>(x);
+    default: return seg_bitonic<64>(x);
+    }
+}
+// smallest power of two >= x, at least 4 (x <= 64)
+__device__ inline uint32_t seg_of(uint32_t x)
+{
+    uint32_t S = 4;
+    while (S < x) S <<= 1;
+    return S;
 }
 
 // One stable radix pass by the digits dg (< 256; rows past count must hold
@@ -2117,7 +2138,7 @@ struct SnShared {
 
 // The whole subtree of one on-chip node (the caller has cleared sh.sm's
 // tables once; they are clear again on return).  Ends with a barrier.
-__device__ void small_subtree(SnShared &sh, const SmallNode root, uint32_t *A, uint32_t *D, uint32_t cutoff,
+__device__ __forceinline__ void small_subtree(SnShared &sh, const SmallNode root, uint32_t *A, uint32_t *D, uint32_t cutoff,
                               unsigned long long *digest)
 {
     SnSm &sm = sh.sm;
@@ -2150,13 +2171,17 @@ __device__ void small_subtree(SnShared &sh, const SmallNode root, uint32_t *A, u
             const int nrows = wave_rows_of(n, R);
             // ---- pivots: m-1 draws from the node input (A, not yet overwritten)
             if (tid < npiv) piv[tid] = A[off + pivot_draw(K, tid, n)];
-            // ---- columns (m <= 64 keys each): one wave per column, bitonic
-            for (uint32_t i = w; i < m; i += SN_NW) {
-                const uint32_t c0 = i * m, len = c0 < n ? min(m, n - c0) : 0u;
-                if (len == 0) break;                     // the later columns are empty too
-                uint32_t x = l < len ? A[off + c0 + l] : 0xFFFFFFFFu;
-                x = wave_bitonic64(x);
-                if (l < len) sm.s.buf[c0 + l] = x;
+            // ---- columns (m <= 64 keys each): 64 / S columns per wave at a
+            // time, each in a segment of S >= m lanes, bitonic
+            {
+                const uint32_t S = seg_of(m), per = WAVE / S;
+                for (uint32_t ib = w * per; ib < m; ib += SN_NW * per) {
+                    const uint32_t i = ib + l / S, e = l % S;
+                    const uint32_t c0 = i * m, len = (i < m && c0 < n) ? min(m, n - c0) : 0u;
+                    uint32_t x = e < len ? A[off + c0 + e] : 0xFFFFFFFFu;
+                    x = seg_bitonic_rt(x, S);
+                    if (e < len) sm.s.buf[c0 + e] = x;
+                }
             }
             __syncthreads();
             if (tid < npiv) {                           // rank sort of the draws
@@ -2236,15 +2261,51 @@ __device__ void small_subtree(SnShared &sh, const SmallNode root, uint32_t *A, u
                 }
                 sp_sh = top;
             }
-            for (uint32_t j = w; j < m; j += SN_NW) {   // one wave per bucket
-                const uint8_t c = cls[j];
-                const uint32_t b0 = bsl[j], nj = bsl[j + 1] - b0;
-                if (c == B_SORT) {
-                    uint32_t x = l < nj ? sm.s.buf[b0 + l] : 0xFFFFFFFFu;
-                    x = wave_bitonic64(x);
-                    if (l < nj) D[off + b0 + l] = x;
-                } else if (c == B_COPY) {
-                    for (uint32_t q = l; q < nj; q += WAVE) D[off + b0 + q] = sm.s.buf[b0 + q];
+            // base-case buckets (at most 64 keys here): four consecutive ones
+            // per wave at a time, in segments of 16 lanes when they all fit,
+            // else as two pairs in segments of 32, else one by one
+            for (uint32_t jb = 4 * w; jb < m; jb += 4 * SN_NW) {
+                uint32_t sz[4];
+                uint32_t mx4 = 0, mxa = 0, mxb = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t j = jb + q;
+                    sz[q] = j < m && cls[j] == B_SORT ? bsl[j + 1] - bsl[j] : 0u;
+                    mx4 = max(mx4, sz[q]);
+                }
+                mxa = max(sz[0], sz[1]);
+                mxb = max(sz[2], sz[3]);
+                // jobs: (first bucket offset, buckets, segment lanes), 8 bits each
+                uint32_t jobs = 0, njobs = 0;
+                auto add = [&](uint32_t dj, uint32_t g, uint32_t S) {
+                    jobs |= (dj | (g << 2) | ((uint32_t)__builtin_ctz(S) << 5)) << (8 * njobs);
+                    ++njobs;
+                };
+                if (mx4 == 0) {
+                } else if (mx4 <= 16) {
+                    add(0, 4, 16);
+                } else {
+                    if (mxa > 0) { if (mxa <= 32) add(0, 2, 32); else { add(0, 1, 64); add(1, 1, 64); } }
+                    if (mxb > 0) { if (mxb <= 32) add(2, 2, 32); else { add(2, 1, 64); add(3, 1, 64); } }
+                }
+#pragma unroll 1
+                for (uint32_t t = 0; t < njobs; ++t) {      // g consecutive buckets in segments of S lanes
+                    const uint32_t jd = (jobs >> (8 * t)) & 255u;
+                    const uint32_t j0 = jb + (jd & 3u), g = (jd >> 2) & 7u, S = 1u << (jd >> 5);
+                    const uint32_t q = l / S, e = l % S, j = j0 + q;
+                    const bool mine = q < g && j < m && cls[j] == B_SORT;
+                    const uint32_t b0 = mine ? bsl[j] : 0u, nj = mine ? bsl[j + 1] - b0 : 0u;
+                    uint32_t x = e < nj ? sm.s.buf[b0 + e] : 0xFFFFFFFFu;
+                    x = seg_bitonic_rt(x, S);
+                    if (e < nj) D[off + b0 + e] = x;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {                // single-value buckets: copied
+                    const uint32_t j = jb + q;
+                    if (j < m && cls[j] == B_COPY) {
+                        const uint32_t b0 = bsl[j], nj = bsl[j + 1] - b0;
+                        for (uint32_t e = l; e < nj; e += WAVE) D[off + b0 + e] = sm.s.buf[b0 + e];
+                    }
                 }
             }
             if (bigbase_sh) {                           // base cases above 64 keys (cut-offs above 64)
