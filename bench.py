@@ -219,21 +219,21 @@ def bench_batched(args, wl):
     seeds = np.arange(1, wl["count"] + 1, dtype=np.uint64)
     ws = binding.Workspace(dev)
     base = torch.from_numpy(keys.view(np.int32)).to(dev)
-    cutoff, tune = args.cutoff, None
-    if args.autotune:
-        print("# autotuning the cut-off", file=sys.stderr, flush=True)
-        cutoff, tune = autotune.tune_batched_cutoff(base, offs, seeds, ws=ws)
+    cutoff, tile, tune = args.cutoff, 0, None
+    if not args.no_autotune and not args.cutoff:
+        print("# autotuning the cut-off and tile shapes", file=sys.stderr, flush=True)
+        cutoff, tile, tune = autotune.tune_batched(base, offs, seeds, ws=ws)
     ins = [base.clone() for _ in range(args.warmup + args.steps)]
     out = torch.empty_like(base)
     for i in range(args.warmup):
-        used = binding.squaresort_batched_u32(ins[i], out, offs, seeds, cutoff=cutoff, ws=ws)
+        used = binding.squaresort_batched_u32(ins[i], out, offs, seeds, cutoff=cutoff, ws=ws, tile=tile)
     torch.cuda.synchronize()
     if not args.no_timing:
         binding.timing_enable(True)
     print(f"# timing {args.steps} batched steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     for i in range(args.warmup, args.warmup + args.steps):
-        used = binding.squaresort_batched_u32(ins[i], out, offs, seeds, cutoff=cutoff, ws=ws)
+        used = binding.squaresort_batched_u32(ins[i], out, offs, seeds, cutoff=cutoff, ws=ws, tile=tile)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timing = binding.timing_report() if not args.no_timing else {}
@@ -251,7 +251,8 @@ def bench_batched(args, wl):
         torch.cuda.synchronize()
         p0 = time.perf_counter()
         for i, (lo, hi) in enumerate(bounds):
-            binding.squaresort_u32(src[lo:hi], plain_out[lo:hi], seed=int(seeds[i]), cutoff=used, ws=ws)
+            binding.squaresort_u32(src[lo:hi], plain_out[lo:hi], seed=int(seeds[i]), cutoff=used, ws=ws,
+                                   tile=tile)
         torch.cuda.synchronize()
         if r:
             plain_ms.append((time.perf_counter() - p0) * 1e3)
@@ -261,7 +262,7 @@ def bench_batched(args, wl):
     # by an untimed copy before each replay; HIP events around the replay)
     print(f"# planned graph: {args.steps} replays", file=sys.stderr, flush=True)
     gin, gout = torch.empty_like(base), torch.empty_like(base)
-    plan = binding.BatchedGraph(gin, gout, offs, seeds, cutoff=used)
+    plan = binding.BatchedGraph(gin, gout, offs, seeds, cutoff=used, tile=tile)
     stream = torch.cuda.current_stream(dev)
     gms = []
     for r in range(args.warmup + args.steps):
@@ -294,7 +295,8 @@ def bench_batched(args, wl):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"batched_u32_{wl['count']}x_loguniform[2^10,2^20]", "instances": wl["count"],
                    "total_keys": total, "key_dist": wl["dist"], "data_seed": wl["data_seed"],
-                   "seeds": "1..count", "cutoff": int(used), "autotune": tune},
+                   "seeds": "1..count", "cutoff": int(used), "tile": binding.tile_fields(tile),
+                   "autotune": tune},
         "plain_per_instance": {"value": round(total / (pms / 1e3) / 1e9, 4), "unit": "GKeys/s",
                                "ms_per_step": round(pms, 3), "calls_per_step": wl["count"]},
         "graph_replay": {"value": round(total / (gmed / 1e3) / 1e9, 4), "unit": "GKeys/s",
@@ -520,7 +522,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=None, help="override the size (2^k keys)")
     ap.add_argument("--cutoff", type=int, default=0, help="base-case cut-off (0 = the library's automatic choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--autotune", action="store_true", help="batched workload: pick the cut-off by timing")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched workload: library defaults instead of the tuned cut-off and tile shapes")
     ap.add_argument("--plain-steps", type=int, default=2, help="batched workload: timed one-call-per-instance steps")
     ap.add_argument("--serve-count", type=int, default=256, help="served workload: requests in the stream")
     ap.add_argument("--serve-load", type=float, default=0.8,

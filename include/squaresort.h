@@ -100,6 +100,21 @@ enum {
 
 #define SQS_MAX_DEPTH 64
 
+/* Tile word of sqs_params (fields of two bits; value 3 is invalid in each):
+ *   SQS_TILE_COLW(v)  waves per work-group of the wave-level column kernel
+ *                     (nodes of at most 1024 columns, one column per wave):
+ *                     v = 0: 4, 1: 2, 2: 8 (template instances);
+ *   SQS_TILE_WCAP(v)  largest bucket (or base-case segment) sorted by one
+ *                     wave: 1024 >> v keys; larger ones go to the 4-wave
+ *                     work-group kernel;
+ *   SQS_TILE_M4CAP(v) largest bucket sorted by one 4-wave work-group:
+ *                     4096 >> v keys; larger ones
+ *                     go to the 16-wave kernel (up to 16384 keys). */
+#define SQS_TILE_COLW(v)  ((uint32_t)(v) & 3u)
+#define SQS_TILE_WCAP(v)  (((uint32_t)(v) & 3u) << 2)
+#define SQS_TILE_M4CAP(v) (((uint32_t)(v) & 3u) << 4)
+#define SQS_TILE_MASK     0x3Fu
+
 /* Parameters shared by every entry point.
  *   cutoff          in/out.  Base case iff a (sub)array has n <= cutoff keys
  *                   (Alg. 1 first step; the paper's cut-off experiment,
@@ -110,6 +125,11 @@ enum {
  *                   keeps every bucket that is not single-valued smaller than
  *                   its node, so the recursion ends.)
  *   flags           SQS_FLAG_* above.
+ *   tile            tile shapes (0 = the library's defaults), SQS_TILE_*
+ *                   below; any value gives the same output and recursion
+ *                   tree, only the time changes (an autotuner picks it with
+ *                   the cut-off, as the paper's cut-off experiment of
+ *                   Section 4.2 picks C).  Unknown bits or values: SQS_ERR_ARG.
  *   workspace       device scratch of workspace_bytes bytes, at least
  *                   squaresort_workspace_bytes(n, kind, cutoff) (or the
  *                   batched query): the per-level arrays the paper allocates
@@ -128,7 +148,7 @@ enum {
 typedef struct sqs_params {
     uint64_t cutoff;
     uint32_t flags;
-    uint32_t reserved;
+    uint32_t tile;
     void *workspace;
     uint64_t workspace_bytes;
     uint64_t *digest;

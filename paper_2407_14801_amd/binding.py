@@ -32,8 +32,24 @@ STATUS = {0: "SQS_OK", -1: "SQS_ERR_ARG", -2: "SQS_ERR_ALIAS", -3: "SQS_ERR_WORK
           -4: "SQS_ERR_DEVICE", -5: "SQS_ERR_PRECOND", -6: "SQS_ERR_DEPTH", -7: "SQS_ERR_UNSUPPORTED"}
 
 
+def tile_word(colw: int = 4, wcap: int = 1024, m4cap: int = 4096) -> int:
+    """The sqs_params tile word (SQS_TILE_* fields): waves per work-group of
+    the wave-level column kernel (4, 2 or 8), the largest bucket one wave
+    sorts (1024, 512 or 256) and the largest one 4-wave work-group sorts
+    (4096, 2048 or 1024)."""
+    cw = {4: 0, 2: 1, 8: 2}[colw]
+    wc = {1024: 0, 512: 1, 256: 2}[wcap]
+    m4 = {4096: 0, 2048: 1, 1024: 2}[m4cap]
+    return cw | (wc << 2) | (m4 << 4)
+
+
+def tile_fields(word: int) -> dict:
+    """Inverse of tile_word."""
+    return {"colw": (4, 2, 8)[word & 3], "wcap": 1024 >> ((word >> 2) & 3), "m4cap": 4096 >> ((word >> 4) & 3)}
+
+
 class Params(ctypes.Structure):
-    _fields_ = [("cutoff", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+    _fields_ = [("cutoff", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("tile", ctypes.c_uint32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
                 ("digest", ctypes.c_void_p)]
 
@@ -111,12 +127,13 @@ class Workspace:
         return self.buf
 
 
-def _params(n, kind, cutoff, ws, digest, pivot_rule="replacement", flags=0):
+def _params(n, kind, cutoff, ws, digest, pivot_rule="replacement", flags=0, tile=0):
     nbytes = workspace_bytes(n, kind, cutoff)
     buf = (ws or Workspace()).get(nbytes) if n > 0 else None
     p = Params()
     p.cutoff = cutoff
     p.flags = (FLAG_DIGEST if digest is not None else 0) | PIVOT_RULES[pivot_rule] | flags
+    p.tile = tile
     p.workspace = None if buf is None else buf.data_ptr()
     p.workspace_bytes = 0 if buf is None else buf.numel()
     p.digest = None if digest is None else digest.data_ptr()
@@ -138,7 +155,8 @@ def _stream_of(t):
 
 def squaresort_u32(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: int = 0,
                    ws: Workspace | None = None, digest: torch.Tensor | None = None,
-                   pivot_rule: str = "replacement", validate: bool = False, host_arrays: bool = False) -> int:
+                   pivot_rule: str = "replacement", validate: bool = False, host_arrays: bool = False,
+                   tile: int = 0) -> int:
     """Sort inp (uint32 bits in an int32 tensor; clobbered) into out.  Returns
     the cut-off used.  pivot_rule "alg1" selects the Alg. 1 pivot rule;
     validate sets SQS_FLAG_VALIDATE; host_arrays (SQS_FLAG_HOST_ARRAYS): inp
@@ -147,7 +165,7 @@ def squaresort_u32(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: 
     assert inp.dtype == torch.int32 and out.dtype == torch.int32 and inp.numel() == out.numel()
     n = inp.numel()
     fl = (FLAG_VALIDATE if validate else 0) | (FLAG_HOST_ARRAYS if host_arrays else 0)
-    p, _keep = _params(n, KIND_U32, cutoff, ws, digest, pivot_rule, fl)
+    p, _keep = _params(n, KIND_U32, cutoff, ws, digest, pivot_rule, fl, tile)
     _check(_lib.squaresort_u32(n, _ptr(inp), _ptr(out), seed, ctypes.byref(p), _stream_of(inp)),
            "squaresort_u32")
     return p.cutoff
@@ -183,12 +201,13 @@ def squaresort_u64(inp: torch.Tensor, out: torch.Tensor, seed: int = 1, cutoff: 
 
 def squaresort_kv(keys_in, vals_in, keys_out, vals_out, seed: int = 1, cutoff: int = 0,
                   ws: Workspace | None = None, digest: torch.Tensor | None = None,
-                  pivot_rule: str = "replacement", validate: bool = False, host_arrays: bool = False) -> int:
+                  pivot_rule: str = "replacement", validate: bool = False, host_arrays: bool = False,
+                  tile: int = 0) -> int:
     _check_dev(keys_in, vals_in, keys_out, vals_out, host=host_arrays)
     assert keys_in.dtype == torch.int64 and vals_in.dtype == torch.int32
     n = keys_in.numel()
     fl = (FLAG_VALIDATE if validate else 0) | (FLAG_HOST_ARRAYS if host_arrays else 0)
-    p, _keep = _params(n, KIND_KV, cutoff, ws, digest, pivot_rule, fl)
+    p, _keep = _params(n, KIND_KV, cutoff, ws, digest, pivot_rule, fl, tile)
     _check(_lib.squaresort_kv(n, _ptr(keys_in), _ptr(vals_in), _ptr(keys_out), _ptr(vals_out), seed,
                               ctypes.byref(p), _stream_of(keys_in)), "squaresort_kv")
     return p.cutoff
@@ -225,9 +244,11 @@ def batched_workspace_bytes(offsets, kind: int = KIND_U32, cutoff: int = 0) -> i
 
 
 def squaresort_batched_u32(inp: torch.Tensor, out: torch.Tensor, offsets, seeds, cutoff: int = 0,
-                           ws: Workspace | None = None, digest: torch.Tensor | None = None) -> int:
+                           ws: Workspace | None = None, digest: torch.Tensor | None = None,
+                           tile: int = 0) -> int:
     """Sort the instances [offsets[i], offsets[i+1]) of inp (clobbered) into
-    out, instance i with seeds[i] (host arrays).  Returns the cut-off used."""
+    out, instance i with seeds[i] (host arrays); tile is the tile word
+    (tile_word).  Returns the cut-off used."""
     import numpy as np
     _check_dev(inp, out)
     assert inp.dtype == torch.int32 and out.dtype == torch.int32 and inp.numel() == out.numel()
@@ -240,6 +261,7 @@ def squaresort_batched_u32(inp: torch.Tensor, out: torch.Tensor, offsets, seeds,
     p = Params()
     p.cutoff = cutoff
     p.flags = FLAG_DIGEST if digest is not None else 0
+    p.tile = tile
     p.workspace = buf.data_ptr()
     p.workspace_bytes = buf.numel()
     p.digest = None if digest is None else digest.data_ptr()
@@ -249,7 +271,8 @@ def squaresort_batched_u32(inp: torch.Tensor, out: torch.Tensor, offsets, seeds,
 
 
 def squaresort_batched_kv(keys_in, vals_in, keys_out, vals_out, offsets, seeds, cutoff: int = 0,
-                          ws: Workspace | None = None, digest: torch.Tensor | None = None) -> int:
+                          ws: Workspace | None = None, digest: torch.Tensor | None = None,
+                          tile: int = 0) -> int:
     """Key/value batched form (uint64 keys in int64 tensors, uint32 values in
     int32 tensors).  Returns the cut-off used."""
     import numpy as np
@@ -264,6 +287,7 @@ def squaresort_batched_kv(keys_in, vals_in, keys_out, vals_out, offsets, seeds, 
     p = Params()
     p.cutoff = cutoff
     p.flags = FLAG_DIGEST if digest is not None else 0
+    p.tile = tile
     p.workspace = buf.data_ptr()
     p.workspace_bytes = buf.numel()
     p.digest = None if digest is None else digest.data_ptr()
@@ -289,7 +313,7 @@ class BatchedGraph:
     and status tensors are bound to the plan and kept alive here."""
 
     def __init__(self, inp: torch.Tensor, out: torch.Tensor, offsets, seeds, cutoff: int = 0,
-                 digest: torch.Tensor | None = None):
+                 digest: torch.Tensor | None = None, tile: int = 0):
         import numpy as np
         _check_dev(inp, out)
         assert inp.dtype == torch.int32 and out.dtype == torch.int32 and inp.numel() == out.numel()
@@ -304,6 +328,7 @@ class BatchedGraph:
         p = Params()
         p.cutoff = cutoff
         p.flags = FLAG_DIGEST if digest is not None else 0
+        p.tile = tile
         p.workspace = self.ws.data_ptr()
         p.workspace_bytes = self.ws.numel()
         p.digest = None if digest is None else digest.data_ptr()

@@ -144,6 +144,7 @@ template <class K> struct Batch {
     unsigned long long *trRec;   // per heavy chunk: TB words (status << 62 | value), see k_transpose
     uint32_t trCap;
     unsigned long long *H;
+    uint32_t wcap, m4cap;   // largest bucket of the wave class and of the mid4 class (tile choice)
 };
 
 // largest k with prefix[k] <= item (prefix is non-decreasing, prefix[0] = 0)
@@ -667,12 +668,13 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
 // the whole group), searches its first and last over the column and the
 // others inside that bracket.  Summed over the group's columns the positions
 // give the group's bucket counts; every 64th gives a bucket-block offset.
-template <class K, bool HV>
-__global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, const K *src, const uint32_t *vsrc,
-                                                                 K *dst, uint32_t *vdst, uint32_t cutoff)
+template <class K, bool HV, int NWS>
+__global__ __launch_bounds__(NWS * WAVE) void k_colsort_small(Batch<K> b, const K *src, const uint32_t *vsrc,
+                                                               K *dst, uint32_t *vdst, uint32_t cutoff)
 {
     static_assert(PIV_ALIGN * WAVE >= WCAP, "one pivot slice per lane covers a node");
-    __shared__ WaveSmem<WR> wsm[SM_NW];
+    static_assert(NWS >= 1 && TG % NWS == 0, "whole columns per wave");
+    __shared__ WaveSmem<WR> wsm[NWS];
     __shared__ uint32_t Pl[WCAP];
     __shared__ uint32_t total_sh;
     const uint32_t si = find_node(b.smlGrp, b.NS, blockIdx.x);
@@ -690,7 +692,7 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
     static_assert(sizeof(RankTab<256>) + sizeof(uint32_t) * WR * WAVE >= sizeof(uint64_t) * WCAP, "column fits");
     K *ck = sizeof(K) == 4 ? reinterpret_cast<K *>(wsm[w].buf) : reinterpret_cast<K *>(&wsm[w]);
 
-    for (uint32_t t = threadIdx.x; t < WCAP; t += SM_NW * WAVE) Pl[t] = 0;
+    for (uint32_t t = threadIdx.x; t < WCAP; t += NWS * WAVE) Pl[t] = 0;
     if (threadIdx.x == 0) total_sh = 0;
     wave_table_clear(wsm[w].tab);
     // this lane's pivots and strict flags (16-byte loads of its aligned, padded slice)
@@ -712,7 +714,7 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
     uint32_t total = 0;
     __syncthreads();
 
-    for (uint32_t c = w; c < ncol; c += SM_NW) {
+    for (uint32_t c = w; c < ncol; c += NWS) {
         const uint32_t i = i0 + c;
         const uint32_t len = __builtin_amdgcn_readfirstlane(column_len(i, m, n));
         uint32_t *so = b.srcOff + nd.src + i;              // so[J*m]
@@ -865,7 +867,7 @@ __global__ __launch_bounds__(SM_NW * WAVE) void k_colsort_small(Batch<K> b, cons
     __syncthreads();
     const uint32_t tot = total_sh;
     uint32_t *blk = b.blk + nd.blk + (uint64_t)g * m;
-    for (uint32_t t = threadIdx.x; t < m; t += SM_NW * WAVE) {
+    for (uint32_t t = threadIdx.x; t < m; t += NWS * WAVE) {
         const uint32_t hi = t < npiv ? Pl[t] : tot;
         const uint32_t c = hi - (t > 0 ? Pl[t - 1] : 0u);
         if (S == 1) blk[t] = c;
@@ -1486,8 +1488,8 @@ __global__ __launch_bounds__(CL_NT) void k_classify(Batch<K> b, uint32_t cutoff)
             base = nd.off + lo;
             if (blo == bhi) cls = CLS_COPY;
             else if (s > cutoff) cls = CLS_INTERNAL;
-            else if (s <= (uint32_t)WCAP) cls = CLS_SMALL;
-            else if (s <= M4_CAP) cls = CLS_MID4;
+            else if (s <= b.wcap) cls = CLS_SMALL;
+            else if (s <= b.m4cap) cls = CLS_MID4;
             else if (s <= (uint32_t)SORT_CAP) cls = CLS_MID;
             else cls = CLS_BIG;
         }

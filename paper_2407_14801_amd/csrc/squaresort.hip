@@ -106,10 +106,30 @@ inline uint32_t sub_groups(uint32_t groups, uint32_t target, uint32_t cap)
 // splits each over the grid (k_base_*) instead of giving each one work-group.
 constexpr size_t SPLIT_SEGS = 256;
 
-// base-case class of a segment of n > 0 keys (n <= cut-off)
-inline int size_class(uint64_t n)
+// base-case class of a segment of n > 0 keys (n <= cut-off); wcap and m4cap
+// are the tile choice's largest wave and mid4 buckets
+inline int size_class(uint64_t n, uint32_t wcap, uint32_t m4cap)
 {
-    return n <= (uint64_t)WCAP ? CLS_SMALL : n <= M4_CAP ? CLS_MID4 : n <= (uint64_t)SORT_CAP ? CLS_MID : CLS_BIG;
+    return n <= wcap ? CLS_SMALL : n <= m4cap ? CLS_MID4 : n <= (uint64_t)SORT_CAP ? CLS_MID : CLS_BIG;
+}
+
+// Tile choices (the sqs_params tile word, 0 = defaults): waves per
+// work-group of the wave-level column kernel, and the largest bucket sorted
+// by one wave and by one 4-wave work-group.  Every choice gives the same
+// output and recursion tree.
+struct Tile {
+    int colw = SM_NW;
+    uint32_t wcap = WCAP, m4cap = M4_CAP;
+};
+inline bool decode_tile(uint32_t w, Tile &t)
+{
+    if (w & ~(uint32_t)SQS_TILE_MASK) return false;
+    const uint32_t cw = w & 3u, wc = (w >> 2) & 3u, m4 = (w >> 4) & 3u;
+    if (cw > 2u || wc > 2u || m4 > 2u) return false;
+    t.colw = cw == 0 ? SM_NW : cw == 1 ? 2 : 8;
+    t.wcap = (uint32_t)WCAP >> wc;
+    t.m4cap = M4_CAP >> m4;                 // never below wcap (1024 at most)
+    return true;
 }
 
 struct HostNode {
@@ -201,6 +221,7 @@ template <class K, bool HV> struct Engine {
     // check that they are, and the output's bucket bounds
     bool cols_sorted = false;
     bool validate = false;
+    Tile tile;
     // planned-graph mode: the launches are being captured into a graph that
     // is replayed later, so nothing may wait for the device: host data go up
     // synchronously at planning time (into workspace that is never reused),
@@ -376,7 +397,7 @@ template <class K, bool HV> struct Engine {
                     if (lo >= h.n) break;
                     const uint32_t len = (uint32_t)std::min<uint64_t>(d.m, h.n - lo);
                     if (len > cutoff) { col_kids.push_back({h.off + lo, len, node_child_key(h.key, 0, i)}); continue; }
-                    const int cls = size_class(len);
+                    const int cls = size_class(len, tile.wcap, tile.m4cap);
                     colLists[cls].push_back(BucketItem{cnode, 0u, (uint32_t)lo, len});
                 }
             } else if (skew_only && cols_sorted) {
@@ -408,7 +429,7 @@ template <class K, bool HV> struct Engine {
         // work-groups so that the column kernels fill the chip; they then add
         // their bucket counts into the group's (cleared below).
         const uint32_t subBig = sub_groups(bigGrp.back(), COL_WG_BIG, TG);
-        const uint32_t subSml = sub_groups(smlGrp.back(), COL_WG_SML, TG / SM_NW);
+        const uint32_t subSml = sub_groups(smlGrp.back(), COL_WG_SML * SM_NW / tile.colw, TG / tile.colw);
         if (subBig > 1)
             for (uint32_t q = 0; q < NB; ++q) {
                 desc[bigIdx[q]].sub = subBig;
@@ -434,13 +455,15 @@ template <class K, bool HV> struct Engine {
         // mid buckets hold > WCAP keys and internal ones > cutoff keys
         const uint32_t capSmall = bucS[N];
         const uint32_t capCopy = (uint32_t)std::min<uint64_t>(0xFFFFFFFFull, bucS[N] + keysTot / COPY_CH + 1);
-        const uint32_t capMid4 = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (WCAP + 1) + 1);
-        const uint32_t capMid = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (M4_CAP + 1) + 1);
+        const uint32_t capMid4 = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (tile.wcap + 1) + 1);
+        const uint32_t capMid = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (tile.m4cap + 1) + 1);
         const uint32_t capBig = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / (SORT_CAP + 1) + 1);
         const uint32_t capInt = (uint32_t)std::min<uint64_t>(bucS[N], keysTot / ((uint64_t)cutoff + 1) + 1);
 
         // ---- device metadata
         Batch<K> b;
+        b.wcap = tile.wcap;
+        b.m4cap = tile.m4cap;
         NodeDesc *dDesc = ws.take<NodeDesc>(N);
         uint32_t *dIdx = ws.take<uint32_t>(idx.size());
         b.piv = ws.take<K>(std::max<uint32_t>(pivS[N], 1));
@@ -536,7 +559,12 @@ template <class K, bool HV> struct Engine {
         if (NB) launch("k_colsort", keysTot, [&] {
             k_colsort_big<K, HV><<<bigGrp.back(), SORT_NT, 0, st>>>(b, A, VA, cdst, vcdst, colCut); });
         if (NS) launch("k_colsort_w", keysTot, [&] {
-            k_colsort_small<K, HV><<<smlGrp.back(), SM_NW * WAVE, 0, st>>>(b, A, VA, cdst, vcdst, colCut); });
+            if (tile.colw == 2)
+                k_colsort_small<K, HV, 2><<<smlGrp.back(), 2 * WAVE, 0, st>>>(b, A, VA, cdst, vcdst, colCut);
+            else if (tile.colw == 8)
+                k_colsort_small<K, HV, 8><<<smlGrp.back(), 8 * WAVE, 0, st>>>(b, A, VA, cdst, vcdst, colCut);
+            else
+                k_colsort_small<K, HV, SM_NW><<<smlGrp.back(), SM_NW * WAVE, 0, st>>>(b, A, VA, cdst, vcdst, colCut); });
         launch("k_colscan", bucS[N], [&] { k_colscan<K><<<cdiv(bucS[N], 256), 256, 0, st>>>(b); });
         launch("k_bucket_start", bucS[N], [&] { k_bucket_start<K><<<N, 1024, 0, st>>>(b, skew_only ? skew_bs : nullptr); });
         if (int rc = check()) return rc;
@@ -668,6 +696,8 @@ template <class K, bool HV> struct Engine {
         release(mark);                     // stream-ordered: later work on this stream may reuse it
         if (ws.overflow) return SQS_ERR_WORKSPACE;
         Batch<K> b{};
+        b.wcap = tile.wcap;
+        b.m4cap = tile.m4cap;
         b.span[CLS_BIG] = s.items; b.cap[CLS_BIG] = 256 * nseg;
         b.ctr = s.ctr;
         b.bigInD = 1;
@@ -738,6 +768,8 @@ template <class K, bool HV> struct Engine {
                       std::vector<BucketItem> (&lists)[NCLS])
     {
         Batch<K> b{};
+        b.wcap = tile.wcap;
+        b.m4cap = tile.m4cap;
         for (int c = CLS_MID4; c <= CLS_BIG; ++c)     // largest first, as k_order_lists orders device lists
             std::stable_sort(lists[c].begin(), lists[c].end(),
                              [](const BucketItem &x, const BucketItem &y) { return x.size > y.size; });
@@ -823,7 +855,7 @@ template <class K, bool HV> struct Engine {
             d.off = offs[i];
             d.n = (uint32_t)n;
             d.m = 1;
-            const int cls = size_class(n);
+            const int cls = size_class(n, tile.wcap, tile.m4cap);
             lists[cls].push_back(BucketItem{(uint32_t)leaf.size(), 0u, 0u, (uint32_t)n});
             leaf.push_back(d);
         }
@@ -917,6 +949,8 @@ int resolve_cutoff(int kind, sqs_params *p, uint32_t *out)
     uint64_t c = p ? p->cutoff : 0;
     if (c == 0) c = max_cutoff_of(kind);
     if (c < 4 || c > max_cutoff_of(kind)) return SQS_ERR_ARG;
+    Tile t;
+    if (p && !decode_tile(p->tile, t)) return SQS_ERR_ARG;
     if (p) p->cutoff = c;
     *out = (uint32_t)c;
     return SQS_OK;
@@ -1005,6 +1039,7 @@ int run_sort(uint64_t n, K *in, uint32_t *vin, K *out, uint32_t *vout, uint64_t 
     const bool validate = p && (p->flags & SQS_FLAG_VALIDATE);
     if (validate && (!p->workspace || p->workspace_bytes < 256)) return SQS_ERR_WORKSPACE;
     Engine<K, HV> e;
+    if (p) decode_tile(p->tile, e.tile);
     e.A = in; e.VA = vin; e.D = out; e.VD = vout;
     e.cutoff = C;
     e.st = (hipStream_t)stream;
@@ -1078,6 +1113,7 @@ int skew_transpose_u32(uint64_t n, uint32_t *in, uint32_t *out, uint64_t *bucket
     const uint64_t need = node_meta_bytes(n, 4) + (64 << 10);
     if (!params || !params->workspace || params->workspace_bytes < need) return SQS_ERR_WORKSPACE;
     Engine<uint32_t, false> e;
+    decode_tile(params->tile, e.tile);
     e.A = in; e.VA = nullptr; e.D = nullptr; e.VD = nullptr;
     e.cutoff = C;
     e.st = (hipStream_t)stream;
@@ -1155,6 +1191,7 @@ int run_batched(uint32_t count, const uint64_t *offsets, K *in, uint32_t *vin, K
     if (params->flags & (SQS_FLAG_COLS_SORTED | SQS_FLAG_VALIDATE | SQS_FLAG_HOST_ARRAYS))
         return SQS_ERR_ARG;                                  // single-instance flags
     Engine<K, HV> e;
+    decode_tile(params->tile, e.tile);
     e.A = in; e.VA = vin; e.D = out; e.VD = vout;
     e.cutoff = C;
     e.st = (hipStream_t)stream;
@@ -1245,6 +1282,7 @@ int squaresort_batched_graph_u32(uint32_t count, const uint64_t *offsets, uint32
     {
         Engine<uint32_t, false> e;
         e.A = in; e.VA = nullptr; e.D = out; e.VD = nullptr;
+        decode_tile(params->tile, e.tile);
         e.cutoff = C;
         e.st = pl->cs;
         e.ws.base = static_cast<char *>(params->workspace);

@@ -146,3 +146,25 @@ def test_noalloc_argument_errors_before_gpu_work(b):
     assert b.lib.squaresort_u32_noalloc(1 << 20, fake_in, fake_out, 1, ctypes.byref(_params(cutoff=64)), None) == -3
     # params may be null (automatic cut-off): still rejected by size
     assert b.lib.squaresort_u32_noalloc(1 << 26, fake_in, fake_out, 1, None, None) == -3
+
+
+def test_tile_word_errors_before_gpu_work(b):
+    """Tile words with unknown bits or a field value of 3 are rejected before
+    any GPU work; tile_word and tile_fields invert each other."""
+    import numpy as np
+    fake_in, fake_out = 0x10000000, 0x20000000
+    offs = np.array([0, 10, 20], dtype=np.uint64)
+    seeds = np.array([1, 2], dtype=np.uint64)
+    for word in (3, 3 << 2, 3 << 4, 1 << 6, 1 << 31):
+        p = _params()
+        p.tile = word
+        assert _call_u32(b, 100, fake_in, fake_out, p) == -1, word
+        p = _params(ws=0x50000000, nbytes=1 << 30)
+        p.tile = word
+        assert b.lib.squaresort_batched_u32(2, offs.ctypes.data, fake_in, fake_out, seeds.ctypes.data,
+                                            ctypes.byref(p), None) == -1, word
+    for cw in (4, 2, 8):
+        for wc in (1024, 512, 256):
+            for m4 in (4096, 2048, 1024):
+                assert b.tile_fields(b.tile_word(cw, wc, m4)) == {"colw": cw, "wcap": wc, "m4cap": m4}
+    assert b.tile_word() == 0

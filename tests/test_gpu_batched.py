@@ -33,12 +33,12 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _batched(b, ws, keys, sizes, seeds, cutoff, digest=False):
+def _batched(b, ws, keys, sizes, seeds, cutoff, digest=False, tile=0):
     offs = b.batched_offsets(sizes)
     inp = torch.from_numpy(keys.view(np.int32)).to(DEV)
     out = torch.empty_like(inp)
     dg = torch.zeros(1, dtype=torch.int64, device=DEV) if digest else None
-    used = b.squaresort_batched_u32(inp, out, offs, seeds, cutoff=cutoff, ws=ws, digest=dg)
+    used = b.squaresort_batched_u32(inp, out, offs, seeds, cutoff=cutoff, ws=ws, digest=dg, tile=tile)
     torch.cuda.synchronize()
     res = out.cpu().numpy().view(np.uint32)
     d = int(dg.cpu().numpy().view(np.uint64)[0]) if digest else None
@@ -108,6 +108,43 @@ def test_batched_digest_is_sum_of_instance_trees(b, ws):
     assert dg == want
 
 
+# tile words: each field off its default, and all three together
+TILES = [dict(colw=2), dict(colw=8), dict(wcap=256), dict(wcap=512, m4cap=1024), dict(m4cap=2048),
+         dict(colw=8, wcap=256, m4cap=1024)]
+
+
+@pytest.mark.parametrize("fields", TILES, ids=lambda f: "-".join(f"{k}{v}" for k, v in f.items()))
+def test_batched_tile_shapes_same_trees(b, ws, fields):
+    """Every tile choice leaves each instance as the oracle does and adds
+    the same digest (the tile word changes kernels and size classes, not the
+    recursion tree): cut-off 64 runs every level through the wave-level
+    column kernel, cut-off 0 puts buckets on every class boundary."""
+    tile = b.tile_word(**fields)
+    _say(f"batched tile {fields} word={tile}")
+    sizes = np.array([0, 1, 200, 256, 257, 512, 513, 1024, 1025, 2048, 2049, 4096, 4097, 9000, 30_000, 70_000],
+                     dtype=np.int64)
+    keys = datagen.uniform_u32(int(sizes.sum()), seed=21)
+    seeds = np.arange(1, len(sizes) + 1, dtype=np.uint64) * 7919
+    got, offs, used, dg = _batched(b, ws, keys, sizes, seeds, 64, digest=True, tile=tile)
+    want = 0
+    for i in range(len(sizes)):
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        if hi == lo:
+            continue
+        w, wd, _ = oracle.squaresort_u32(keys[lo:hi], int(seeds[i]), used, want_digest=True)
+        assert np.array_equal(got[lo:hi], w), f"instance {i}"
+        want = (want + wd) & 0xFFFFFFFFFFFFFFFF
+    assert dg == want
+    # automatic cut-off: base-case instances and buckets of every class
+    sizes = datagen.log_uniform_sizes(300, 1 << 8, 1 << 18, seed=22)
+    keys = datagen.uniform_u32(int(sizes.sum()), seed=23)
+    seeds = np.arange(len(sizes), dtype=np.uint64) + 5
+    got, offs, used, _ = _batched(b, ws, keys, sizes, seeds, 0, tile=tile)
+    for i in range(len(sizes)):
+        lo, hi = int(offs[i]), int(offs[i + 1])
+        assert np.array_equal(got[lo:hi], np.sort(keys[lo:hi])), f"instance {i}"
+
+
 def test_batched_log_uniform_workload(b, ws):
     """The batched workload's shape at reduced count: log-uniform sizes in
     [2^10, 2^20], uniform keys, automatic cut-off."""
@@ -121,13 +158,13 @@ def test_batched_log_uniform_workload(b, ws):
         assert np.array_equal(got[lo:hi], np.sort(keys[lo:hi])), f"instance {i}"
 
 
-def _batched_kv(b, ws, k, v, sizes, seeds, cutoff, digest=False):
+def _batched_kv(b, ws, k, v, sizes, seeds, cutoff, digest=False, tile=0):
     offs = b.batched_offsets(sizes)
     ki = torch.from_numpy(np.ascontiguousarray(k, np.uint64).view(np.int64)).to(DEV)
     vi = torch.from_numpy(np.ascontiguousarray(v, np.uint32).view(np.int32)).to(DEV)
     ko, vo = torch.empty_like(ki), torch.empty_like(vi)
     dg = torch.zeros(1, dtype=torch.int64, device=DEV) if digest else None
-    used = b.squaresort_batched_kv(ki, vi, ko, vo, offs, seeds, cutoff=cutoff, ws=ws, digest=dg)
+    used = b.squaresort_batched_kv(ki, vi, ko, vo, offs, seeds, cutoff=cutoff, ws=ws, digest=dg, tile=tile)
     torch.cuda.synchronize()
     d = int(dg.cpu().numpy().view(np.uint64)[0]) if digest else None
     return ko.cpu().numpy().view(np.uint64), vo.cpu().numpy().view(np.uint32), offs, used, d
@@ -150,13 +187,15 @@ def test_batched_kv_mixed_classes(b, ws, cutoff):
         assert np.array_equal(gv[lo:hi], v[lo:hi][order]), f"instance {i} (n={hi - lo})"
 
 
-def test_batched_kv_digest_is_sum_of_instance_trees(b, ws):
-    _say("batched kv digest cutoff=64")
+@pytest.mark.parametrize("fields", [{}, dict(colw=2, wcap=256, m4cap=1024), dict(colw=8, wcap=512)],
+                         ids=["default", "colw2-wcap256-m4cap1024", "colw8-wcap512"])
+def test_batched_kv_digest_is_sum_of_instance_trees(b, ws, fields):
+    _say(f"batched kv digest cutoff=64 tile {fields}")
     sizes = datagen.log_uniform_sizes(24, 10, 20_000, seed=9)
     k, _ = datagen.kv_mixture(int(sizes.sum()), seed=22)
     v = np.arange(k.size, dtype=np.uint32)
     seeds = np.arange(1, len(sizes) + 1, dtype=np.uint64) * 7777
-    gk, gv, offs, used, dg = _batched_kv(b, ws, k, v, sizes, seeds, 64, digest=True)
+    gk, gv, offs, used, dg = _batched_kv(b, ws, k, v, sizes, seeds, 64, digest=True, tile=b.tile_word(**fields))
     want = 0
     for i in range(len(sizes)):
         lo, hi = int(offs[i]), int(offs[i + 1])
