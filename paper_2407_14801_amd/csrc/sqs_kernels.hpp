@@ -360,6 +360,130 @@ __device__ inline uint32_t column_len(uint32_t i, uint32_t m, uint32_t n)
 }
 
 // key at position p of a sorted column held in LDS
+// ------------------------------------------------------- merge column sort
+// Columns of 64-bit keys of at most MergeCap::CAP keys are sorted by a stable
+// merge sort in LDS (keys, and values beside them), which leaves the
+// registers of the radix passes free: each thread first sorts IPT
+// consecutive keys in registers (odd-even transposition: adjacent exchanges
+// of strictly greater keys, so equal keys keep their order), then runs of L
+// merge into runs of 2L; each thread produces IPT consecutive outputs of its
+// run pair, finding where they start on the merge path (a binary search over
+// the pair's diagonal) and taking the smaller head IPT times, the left
+// run's head on ties (stable).  A thread's run is an odd number of keys, so
+// that the lanes' accesses to their own runs (IPT 8-byte words apart) fall
+// into different LDS banks.
+template <bool HV> struct MergeCap {
+    static constexpr int IPT = HV ? 13 : 17;             // keys per thread
+    static constexpr int SLOTS = SORT_NT * IPT;
+    static constexpr int CAP = SLOTS < SORT_CAP ? SLOTS : SORT_CAP;   // 13312 (with values) or 16384 keys
+};
+template <bool HV> struct MergeSm {
+    uint64_t k[MergeCap<HV>::SLOTS];
+    uint32_t v[HV ? MergeCap<HV>::SLOTS : 1];
+};
+// the column kernel's LDS: the sort layout, or the merge sort's arrays over it
+template <bool HV, bool MG> struct ColSm {
+    SortSm sort;
+};
+template <bool HV> struct ColSm<HV, true> {
+    union {
+        SortSm sort;
+        MergeSm<HV> mg;
+    };
+};
+static_assert(sizeof(ColSm<true, true>) <= 160 * 1024, "fits one CU's LDS");
+
+// Stable sort of K[0 .. len) (and V) in place; len <= MergeCap<HV>::CAP.
+// Entry: the keys are in LDS and a barrier has passed; exit: sorted, after
+// a barrier.  Positions len .. (a multiple of IPT) are padding, set here to
+// the largest key: being last, they stay behind equal real keys.
+template <bool HV>
+__device__ void lds_merge_sort(uint64_t *K, uint32_t *V, uint32_t len)
+{
+    constexpr int IPT = MergeCap<HV>::IPT;
+    const uint32_t t = threadIdx.x;
+    const uint32_t nact = (len + IPT - 1) / IPT;         // threads that hold keys
+    const uint32_t lenp = nact * IPT;
+    if (t < lenp - len) {                                // fewer than IPT pads
+        K[len + t] = ~0ull;
+        if (HV) V[len + t] = 0u;
+    }
+    __syncthreads();
+    uint64_t k[IPT];
+    uint32_t v[IPT];
+    const uint32_t pos = t * IPT;
+    if (t < nact) {
+#pragma unroll
+        for (int s = 0; s < IPT; ++s) {
+            k[s] = K[pos + s];
+            if (HV) v[s] = V[pos + s];
+        }
+#pragma unroll
+        for (int rd = 0; rd < IPT; ++rd) {
+#pragma unroll
+            for (int s = rd & 1; s + 1 < IPT; s += 2) {
+                const bool sw = k[s] > k[s + 1];
+                const uint64_t a = k[s], b = k[s + 1];
+                k[s] = sw ? b : a;
+                k[s + 1] = sw ? a : b;
+                if (HV) {
+                    const uint32_t x = v[s], y = v[s + 1];
+                    v[s] = sw ? y : x;
+                    v[s + 1] = sw ? x : y;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < IPT; ++s) {                  // own positions: no other thread reads them yet
+            K[pos + s] = k[s];
+            if (HV) V[pos + s] = v[s];
+        }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (uint32_t L = IPT; L < len; L *= 2) {            // uniform over the work-group
+        if (t < nact) {
+            const uint32_t a0 = pos / (2 * L) * (2 * L);
+            const uint32_t la = min(L, lenp - a0);
+            const uint32_t b0 = a0 + la;
+            const uint32_t lb = b0 < lenp ? min(L, lenp - b0) : 0u;
+            const uint32_t d = pos - a0;                 // outputs of the pair before this thread's
+            // merge path: i = keys of the left run among the first d outputs
+            uint32_t lo = d > lb ? d - lb : 0u, hi = min(d, la);
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (K[a0 + mid] <= K[b0 + d - mid - 1]) lo = mid + 1; else hi = mid;
+            }
+            // the outputs one by one: the smaller head, the left run's on ties
+            uint32_t i = lo, j = d - lo;
+            uint64_t ka = i < la ? K[a0 + i] : 0ull;
+            uint64_t kb = j < lb ? K[b0 + j] : 0ull;
+#pragma unroll
+            for (int s = 0; s < IPT; ++s) {
+                const bool ta = i < la && (j >= lb || ka <= kb);
+                k[s] = ta ? ka : kb;
+                if (HV) v[s] = V[ta ? a0 + i : b0 + j];
+                i += ta ? 1u : 0u;
+                j += ta ? 0u : 1u;
+                const bool more = ta ? i < la : j < lb;
+                const uint32_t nx = min(ta ? a0 + i : b0 + j, lenp - 1u);
+                const uint64_t kn = more ? K[nx] : 0ull;
+                ka = ta ? kn : ka;
+                kb = ta ? kb : kn;
+            }
+        }
+        __syncthreads();
+        if (t < nact) {
+#pragma unroll
+            for (int s = 0; s < IPT; ++s) {
+                K[pos + s] = k[s];
+                if (HV) V[pos + s] = v[s];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <class K> __device__ inline K col_key(const SortSm &sm, uint32_t p)
 {
     return sizeof(K) == 4 ? (K)sm.k32[p] : (K)sm.k64[p];
@@ -370,11 +494,13 @@ template <class K> __device__ inline K col_key(const SortSm &sm, uint32_t p)
 // then every pivot finds, by a galloping search in the sorted column, how
 // many keys are at-or-below it.  Summed over the group these positions give
 // the group's bucket counts.
-template <class K, bool HV>
+template <class K, bool HV, bool MG = false>
 __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *src, const uint32_t *vsrc,
                                                           K *dst, uint32_t *vdst, uint32_t cutoff)
 {
-    __shared__ SortSm sm;
+    static_assert(!MG || sizeof(K) == 8, "the merge column sort takes 64-bit keys");
+    __shared__ ColSm<HV, MG> csm;
+    SortSm &sm = csm.sort;
     const uint32_t bi = find_node(b.bigGrp, b.NB, blockIdx.x);
     const NodeDesc nd = b.nodes[b.bigIdx[bi]];
     const uint32_t wi = blockIdx.x - b.bigGrp[bi];
@@ -403,49 +529,13 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
         }
         const bool sorted = recursed && len > cutoff;   // sorted by its own recursion
         const uint64_t base = nd.off + (uint64_t)i * m;
-        K kk[SORT_IPT];
-        uint32_t vv[SORT_IPT];
-        tables_clear<SORT_NW, 256>(sm.s.tab);           // the previous search reused this LDS
-        const int R = block_rows<SORT_NW, SORT_IPT>(len);
-#pragma unroll
-        for (int r = 0; r < SORT_IPT; ++r) {
-            const uint32_t p = bpos(r, R);
-            const bool ok = r < R && p < len;
-            kk[r] = ok ? (sorted ? dst[base + p] : src[base + p]) : (K)0;
-            if (HV) vv[r] = ok && !sorted ? vsrc[base + p] : 0u;
-        }
-        wait_vmem();
-        __syncthreads();
         K clo = (K)0;
         int passes = 0;
-        // 32-bit keys without values sort by bins of the key range; a column
-        // with a crowded bin (and every other key type) by LSD radix passes
         int binned = 2;
         int rsh = 0;
         uint32_t rlast = 255u;
-        if constexpr (sizeof(K) == 4 && !HV) {
-            if (!sorted) {
-                uint32_t blo = 0u, nbin = 0u;
-                binned = bin_sort<SORT_NW, SORT_IPT>(kk, len, sm, blo, rsh, nbin);
-                if (binned == 1) { clo = (K)blo; rlast = nbin - 1u; }
-                if (binned == 2) {                     // loaded again: see lds_sort
-                    block_load<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, src + base, nullptr);
-                    tables_clear<SORT_NW, 256>(sm.s.tab);
-                    __syncthreads();
-                }
-            }
-        }
-        if (!sorted && binned == 2) {
-            block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm, false, (K)0, (K)0, &clo, &passes);
-            rsh = 8 * (passes - 1);
-        }
-        // 32-bit keys without values: the sorted column (minus clo) is still in
-        // the exchange buffer, and the start of every bin (or of every
-        // last-pass digit) in the tables' space, so the count searches there
-        // and narrows each whole-column search to the keys of the pivot's bin
-        // (digit)
-        const bool fast = sizeof(K) == 4 && !HV && !sorted && (passes > 0 || binned == 1);
-        const uint32_t *rtab = binned == 1 ? bin_starts(sm) : sm.s.tab[0].off;
+        bool fast = false;
+        const uint32_t *rtab = nullptr;
         // this thread's pivots and strict flags, as 16-byte loads of its
         // aligned, padded slice (entries past npiv are not used); for 32-bit
         // keys issued here, so that they arrive while the column is stored.
@@ -468,29 +558,114 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
                 }
             }
         };
-        if (sizeof(K) == 4) load_pivots(t0);
-        if (!sorted) {
+        if constexpr (MG) {
+            // 64-bit keys: stable merge sort in LDS; the sorted column stays
+            // there for the count
+            constexpr int MI = MergeCap<HV>::IPT;
+            uint64_t *Kc = csm.mg.k;
+            uint32_t *Vc = csm.mg.v;
+            uint64_t mk[MI];
+            uint32_t mv[MI];
+            // the row positions are recomputed for every column (not kept in
+            // registers across the column loop, which would spill)
+            uint32_t tid = threadIdx.x;
+            asm volatile("" : "+v"(tid));
 #pragma unroll
-            for (int r = 0; r < SORT_IPT; ++r) {
-                const uint32_t p = bpos(r, R);
-                if (r < R && p < len) {
-                    dst[base + p] = kk[r];
-                    if (HV) vdst[base + p] = vv[r];
+            for (int r = 0; r < MI; ++r) {
+                const uint32_t p = (uint32_t)r * SORT_NT + tid;
+                const bool ok = p < len;
+                mk[r] = ok ? (uint64_t)(sorted ? dst[base + p] : src[base + p]) : 0ull;
+                if (HV) mv[r] = ok && !sorted ? vsrc[base + p] : 0u;
+            }
+            wait_vmem();
+#pragma unroll
+            for (int r = 0; r < MI; ++r) {
+                const uint32_t p = (uint32_t)r * SORT_NT + tid;
+                if (p < len) {
+                    Kc[p] = mk[r];
+                    if (HV) Vc[p] = mv[r];
                 }
             }
-        }
-        if (!fast) {
             __syncthreads();
+            if (!sorted) {
+                lds_merge_sort<HV>(Kc, Vc, len);
+                uint32_t tid2 = threadIdx.x;
+                asm volatile("" : "+v"(tid2));
+#pragma unroll
+                for (int r = 0; r < MI; ++r) {
+                    const uint32_t p = (uint32_t)r * SORT_NT + tid2;
+                    if (p < len) {
+                        dst[base + p] = (K)Kc[p];
+                        if (HV) vdst[base + p] = Vc[p];
+                    }
+                }
+            }
+        } else {
+            K kk[SORT_IPT];
+            uint32_t vv[SORT_IPT];
+            tables_clear<SORT_NW, 256>(sm.s.tab);           // the previous search reused this LDS
+            const int R = block_rows<SORT_NW, SORT_IPT>(len);
 #pragma unroll
             for (int r = 0; r < SORT_IPT; ++r) {
                 const uint32_t p = bpos(r, R);
-                if (r < R && p < len) { if (sizeof(K) == 4) sm.k32[p] = (uint32_t)kk[r]; else sm.k64[p] = (uint64_t)kk[r]; }
+                const bool ok = r < R && p < len;
+                kk[r] = ok ? (sorted ? dst[base + p] : src[base + p]) : (K)0;
+                if (HV) vv[r] = ok && !sorted ? vsrc[base + p] : 0u;
             }
+            wait_vmem();
             __syncthreads();
+            // 32-bit keys without values sort by bins of the key range; a column
+            // with a crowded bin (and every other key type) by LSD radix passes
+            if constexpr (sizeof(K) == 4 && !HV) {
+                if (!sorted) {
+                    uint32_t blo = 0u, nbin = 0u;
+                    binned = bin_sort<SORT_NW, SORT_IPT>(kk, len, sm, blo, rsh, nbin);
+                    if (binned == 1) { clo = (K)blo; rlast = nbin - 1u; }
+                    if (binned == 2) {                     // loaded again: see lds_sort
+                        block_load<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, src + base, nullptr);
+                        tables_clear<SORT_NW, 256>(sm.s.tab);
+                        __syncthreads();
+                    }
+                }
+            }
+            if (!sorted && binned == 2) {
+                block_sort<K, HV, SORT_NW, SORT_IPT>(kk, vv, len, sm, false, (K)0, (K)0, &clo, &passes);
+                rsh = 8 * (passes - 1);
+            }
+            // 32-bit keys without values: the sorted column (minus clo) is still in
+            // the exchange buffer, and the start of every bin (or of every
+            // last-pass digit) in the tables' space, so the count searches there
+            // and narrows each whole-column search to the keys of the pivot's bin
+            // (digit)
+            fast = sizeof(K) == 4 && !HV && !sorted && (passes > 0 || binned == 1);
+            rtab = binned == 1 ? bin_starts(sm) : sm.s.tab[0].off;
+            if (sizeof(K) == 4) load_pivots(t0);
+            if (!sorted) {
+#pragma unroll
+                for (int r = 0; r < SORT_IPT; ++r) {
+                    const uint32_t p = bpos(r, R);
+                    if (r < R && p < len) {
+                        dst[base + p] = kk[r];
+                        if (HV) vdst[base + p] = vv[r];
+                    }
+                }
+            }
+            if (!fast) {
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < SORT_IPT; ++r) {
+                    const uint32_t p = bpos(r, R);
+                    if (r < R && p < len) { if (sizeof(K) == 4) sm.k32[p] = (uint32_t)kk[r]; else sm.k64[p] = (uint64_t)kk[r]; }
+                }
+                __syncthreads();
+            }
         }
         // key at position q of the sorted column, and a pivot in the same
         // space (below the column minimum: 0 taken as strict, below every key)
-        auto ck = [&](uint32_t q) -> K { return fast ? (K)sm.s.buf[q] : col_key<K>(sm, q); };
+        auto ck = [&](uint32_t q) -> K {
+            if constexpr (MG) return (K)csm.mg.k[q];
+            return fast ? (K)sm.s.buf[q] : col_key<K>(sm, q);
+        };
         auto tpiv = [&](K p, bool &st) -> K {
             if (!fast) return p;
             if (p < clo) { st = true; return (K)0; }
@@ -1927,14 +2102,14 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                     RankTab<256> &tab = sm.s.tab[wave_id()];
                     K kk[BK_IPT];
                     uint32_t vv[BK_IPT], pos[BK_IPT];
-    #pragma unroll
+#pragma unroll
                     for (int r = 0; r < BK_IPT; ++r) {                      // loads first, in flight together
                         const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
                         kk[r] = r < nrows && p < chN ? src[sb + c0 + p] : (K)0;
                         if (HV) vv[r] = r < nrows && p < chN ? vsrc[sb + c0 + p] : 0u;
                     }
                     wait_vmem();
-    #pragma unroll
+#pragma unroll
                     for (int r = 0; r < BK_IPT; ++r) {
                         if (r < nrows) {
                             const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
@@ -1944,7 +2119,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                     }
                     __syncthreads();
                     scan_tables<BK_NW, 256>(sm.s.tab, sm.wsum);
-    #pragma unroll
+#pragma unroll
                     for (int r = 0; r < BK_IPT; ++r) {
                         if (r < nrows) {
                             const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
@@ -1952,28 +2127,28 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                             pos[r] += tab.off[d];
                         }
                     }
-    #pragma unroll
+#pragma unroll
                     for (int wd = 0; wd < T::WORDS; ++wd) {
-    #pragma unroll
+#pragma unroll
                         for (int r = 0; r < BK_IPT; ++r)
                             if (r < nrows) sm.s.buf[pos[r]] = T::word(kk[r], wd);
                         __syncthreads();
-    #pragma unroll
+#pragma unroll
                         for (int r = 0; r < BK_IPT; ++r)
                             if (r < nrows) kk[r] = T::set_word(kk[r], wd, sm.s.buf[item_pos<BK_NW, BK_IPT>(r)]);
                         __syncthreads();
                     }
                     if (HV) {
-    #pragma unroll
+#pragma unroll
                         for (int r = 0; r < BK_IPT; ++r) if (r < nrows) sm.s.buf[pos[r]] = vv[r];
                         __syncthreads();
-    #pragma unroll
+#pragma unroll
                         for (int r = 0; r < BK_IPT; ++r) if (r < nrows) vv[r] = sm.s.buf[item_pos<BK_NW, BK_IPT>(r)];
                         __syncthreads();
                     }
                     // element at chunk position p has digit d (recomputed from its key);
                     // it goes to base[d] + run[d] + (p - start of d in this chunk)
-    #pragma unroll
+#pragma unroll
                     for (int r = 0; r < BK_IPT; ++r) {
                         if (r < nrows) {
                             const uint32_t p = item_pos<BK_NW, BK_IPT>(r);

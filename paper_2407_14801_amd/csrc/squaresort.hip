@@ -347,6 +347,7 @@ template <class K, bool HV> struct Engine {
         std::vector<NodeDesc> desc(N);
         // prefixes: piv, tile, buc, dig (N+1 each), then big/small index lists and group prefixes
         std::vector<uint32_t> bigIdx, smlIdx, bigGrp{0}, smlGrp{0};
+        uint32_t bigM = 0;                             // largest m of the work-group-column nodes
         std::vector<uint32_t> pfx(4 * (N + 1), 0);
         uint32_t *pivS = &pfx[0], *tileS = &pfx[(N + 1)], *bucS = &pfx[2 * (N + 1)], *digS = &pfx[3 * (N + 1)];
         uint64_t srcTot = 0, blkTot = 0, keysTot = 0;
@@ -413,7 +414,11 @@ template <class K, bool HV> struct Engine {
                 }
             }
             if (huge) {
-            } else if (d.m > (uint32_t)WCAP) { bigIdx.push_back(k); bigGrp.push_back(bigGrp.back() + d.groups); }
+            } else if (d.m > (uint32_t)WCAP) {
+                bigIdx.push_back(k);
+                bigGrp.push_back(bigGrp.back() + d.groups);
+                bigM = std::max(bigM, d.m);
+            }
             else { smlIdx.push_back(k); smlGrp.push_back(smlGrp.back() + d.groups); }
             pivS[k + 1] = pivS[k] + (uint32_t)align_up(d.m - 1, PIV_ALIGN);   // 16-key aligned slots
             tileS[k + 1] = tileS[k] + d.groups * d.nJ;
@@ -557,6 +562,12 @@ template <class K, bool HV> struct Engine {
             if (int rc = check()) return rc;
         }
         if (NB) launch("k_colsort", keysTot, [&] {
+            if constexpr (sizeof(K) == 8) {
+                if (bigM <= (uint32_t)MergeCap<HV>::CAP) {   // every column fits the merge sort
+                    k_colsort_big<K, HV, true><<<bigGrp.back(), SORT_NT, 0, st>>>(b, A, VA, cdst, vcdst, colCut);
+                    return;
+                }
+            }
             k_colsort_big<K, HV><<<bigGrp.back(), SORT_NT, 0, st>>>(b, A, VA, cdst, vcdst, colCut); });
         if (NS) launch("k_colsort_w", keysTot, [&] {
             if (tile.colw == 2)

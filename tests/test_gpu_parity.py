@@ -201,7 +201,7 @@ def test_u64_matches_oracle(b, ws, n, cutoff):
 
 
 @pytest.mark.parametrize("n,cutoff", [(9, 4), (5000, 16), (40_000, 64), (300_007, 0), (60_000, 0),
-                                      (125_000, 0), ((1 << 23) + 3, 0)])
+                                      (125_000, 0), ((1 << 23) + 3, 0), ((1 << 21) + 5, 1000)])
 def test_kv_matches_oracle(b, ws, n, cutoff):
     _say(f"kv n={n} cutoff={cutoff}")
     k, v = datagen.kv_mixture(n, seed=4)
@@ -363,6 +363,24 @@ def test_u32_presorted_digest(b, ws, name):
     assert np.array_equal(got, np.sort(x))
     want, wdg, _ = oracle.squaresort_u32(x, 2, used, want_digest=True)
     assert np.array_equal(got, want)
+    assert dg == wdg
+
+
+@pytest.mark.parametrize("n", [1_500_007, (1 << 22) + 1])
+def test_kv_largest_keys_stable(b, ws, n):
+    """Columns of the merge column sort whose lengths are not a multiple of
+    a thread's run, with many keys equal to the largest 64-bit value (the
+    value the sort pads with) among few others: equal keys keep their input
+    order and the tree digest is the oracle's."""
+    _say(f"kv largest keys n={n}")
+    g = np.random.default_rng(n)
+    top = np.uint64(2**64 - 1)
+    k = np.where(g.random(n) < 0.6, top, top - g.integers(0, 50, size=n).astype(np.uint64)).astype(np.uint64)
+    v = np.arange(n, dtype=np.uint32)
+    ko, vo, dg, used = gpu_kv(b, ws, k, v, seed=3, cutoff=0, digest=True)
+    order = np.argsort(k, kind="stable")
+    assert np.array_equal(ko, k[order]) and np.array_equal(vo, v[order])
+    _, _, wdg, _ = oracle.squaresort_kv(k, v, 3, used, want_digest=True)
     assert dg == wdg
 
 
