@@ -393,14 +393,14 @@ template <bool HV> struct ColSm<HV, true> {
 };
 static_assert(sizeof(ColSm<true, true>) <= 160 * 1024, "fits one CU's LDS");
 
-// Stable sort of K[0 .. len) (and V) in place; len <= MergeCap<HV>::CAP.
+// Stable sort of K[0 .. len) (and V) in place, runs of IPT keys (odd);
+// len <= IPT * (threads of the work-group).
 // Entry: the keys are in LDS and a barrier has passed; exit: sorted, after
 // a barrier.  Positions len .. (a multiple of IPT) are padding, set here to
 // the largest key: being last, they stay behind equal real keys.
-template <bool HV>
+template <bool HV, int IPT>
 __device__ void lds_merge_sort(uint64_t *K, uint32_t *V, uint32_t len)
 {
-    constexpr int IPT = MergeCap<HV>::IPT;
     const uint32_t t = threadIdx.x;
     const uint32_t nact = (len + IPT - 1) / IPT;         // threads that hold keys
     const uint32_t lenp = nact * IPT;
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(SORT_NT) void k_colsort_big(Batch<K> b, const K *sr
             }
             __syncthreads();
             if (!sorted) {
-                lds_merge_sort<HV>(Kc, Vc, len);
+                lds_merge_sort<HV, MI>(Kc, Vc, len);
                 uint32_t tid2 = threadIdx.x;
                 asm volatile("" : "+v"(tid2));
 #pragma unroll
@@ -1915,11 +1915,93 @@ __device__ __noinline__ void big_leaf_radix(const uint32_t *from, uint32_t *to, 
     }
 }
 
+// Leaves of 64-bit keys: the stable LDS merge sort (runs of IPT keys, BK_NT
+// threads) for parts of at most BK_NT * IPT keys (5632 with values, 7680
+// without), over the same LDS as the radix sort and small enough for two
+// work-groups per CU.
+template <bool HV> struct BigMergeSm {
+    static constexpr int IPT = HV ? 11 : 15;
+    static constexpr int CAP = BK_NT * IPT;
+    uint64_t k[CAP];
+    uint32_t v[HV ? CAP : 1];
+};
+template <class K, bool HV> struct BigSmem {
+    BigSm sort;
+};
+template <bool HV> struct BigSmem<uint64_t, HV> {
+    union {
+        BigSm sort;
+        BigMergeSm<HV> mg;
+    };
+};
+static_assert(sizeof(BigSmem<uint64_t, true>) <= 70 * 1024 && sizeof(BigSmem<uint64_t, false>) <= 70 * 1024,
+              "two work-groups per CU with the kernel's other shared arrays");
+
+// Leaves of 64-bit keys above the merge capacity: radix passes, in a
+// function that is not inlined (its registers apart from the kernel's).
+template <bool HV>
+__device__ __noinline__ void big_leaf_radix64(const uint64_t *from, const uint32_t *vfrom, uint64_t *to,
+                                              uint32_t *vto, uint32_t size, uint64_t lo, uint64_t hi, BigSm &sm)
+{
+    uint64_t kk[BK_IPT];
+    uint32_t vv[BK_IPT];
+    block_load<uint64_t, HV, BK_NW, BK_IPT>(kk, vv, size, from, vfrom);
+    tables_clear<BK_NW, 256>(sm.s.tab);
+    __syncthreads();
+    block_sort<uint64_t, HV, BK_NW, BK_IPT>(kk, vv, size, sm, true, lo, hi);
+    const int R = block_rows<BK_NW, BK_IPT>(size);
+#pragma unroll
+    for (int r = 0; r < BK_IPT; ++r) {
+        const uint32_t p = bpos(r, R);
+        if (r < R && p < size) {
+            to[p] = kk[r];
+            if (HV) vto[p] = vv[r];
+        }
+    }
+}
+
+template <bool HV>
+__device__ void big_leaf_merge(const uint64_t *from, const uint32_t *vfrom, uint64_t *to, uint32_t *vto,
+                               uint32_t size, BigMergeSm<HV> &mg)
+{
+    constexpr int IPT = BigMergeSm<HV>::IPT;
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));                      // positions recomputed here, not kept live
+    uint64_t mk[IPT];
+    uint32_t mv[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = (uint32_t)r * BK_NT + tid;
+        mk[r] = p < size ? from[p] : 0ull;
+        if (HV) mv[r] = p < size ? vfrom[p] : 0u;
+    }
+    wait_vmem();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = (uint32_t)r * BK_NT + tid;
+        if (p < size) {
+            mg.k[p] = mk[r];
+            if (HV) mg.v[p] = mv[r];
+        }
+    }
+    __syncthreads();
+    lds_merge_sort<HV, IPT>(mg.k, mg.v, size);
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = (uint32_t)r * BK_NT + tid;
+        if (p < size) {
+            to[p] = mg.k[p];
+            if (HV) vto[p] = mg.v[p];
+        }
+    }
+}
+
 template <class K, bool HV>
 __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint32_t *VA, K *D, uint32_t *VD)
 {
     using T = KeyT<K>;
-    __shared__ BigSm sm;
+    __shared__ BigSmem<K, HV> bsm;
+    BigSm &sm = bsm.sort;
     __shared__ BigSeg stack[BIG_STACK];
     __shared__ uint32_t hist[256], base[256], run[256];
     __shared__ uint32_t whist[BK_NW][1 << SPLIT_MAX];
@@ -1953,6 +2035,13 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                             D[sb + p] = A[sb + p];
                             if (HV) VD[sb + p] = VA[sb + p];
                         }
+                } else if constexpr (sizeof(K) == 8) {
+                    if (sg.size <= (uint32_t)BigMergeSm<HV>::CAP)
+                        big_leaf_merge<HV>(src + sb, HV ? vsrc + sb : nullptr, D + sb, HV ? VD + sb : nullptr,
+                                           sg.size, bsm.mg);
+                    else
+                        big_leaf_radix64<HV>(src + sb, HV ? vsrc + sb : nullptr, D + sb, HV ? VD + sb : nullptr,
+                                             sg.size, (uint64_t)sg.lo, (uint64_t)sg.hi, sm);
                 } else {
                     K kk[BK_IPT];
                     uint32_t vv[BK_IPT];
