@@ -2086,17 +2086,22 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
             // ---- split by the top sbits bits of (x - lo).  A range of at
             // most SPLIT_MAX bits is split into single values (copied, not
             // sorted); otherwise sbits is the fewest bits that give parts of
-            // about SPLIT_PART keys and the fewest 8-bit passes per part that
-            // any split of at most SPLIT_MAX bits gives
+            // about SPLIT_PART keys (for the merge leaves of 64-bit keys, two
+            // thirds of their capacity) and, for 32-bit keys, the fewest
+            // 8-bit passes per part that any split of at most SPLIT_MAX bits
+            // gives
             K *dstb = sg.in_d ? A : D;
             uint32_t *vdstb = sg.in_d ? VA : VD;
             const K klo = (K)sg.lo;
             const int bits = T::bitlen((K)((K)sg.hi - klo));
             int sbits = bits;
             if (bits > SPLIT_MAX) {
-                const int best = (bits - SPLIT_MAX + 7) / 8;
-                sbits = min(32 - __clz((sg.size - 1) / SPLIT_PART), SPLIT_MAX);
-                while (sbits < SPLIT_MAX && (bits - sbits + 7) / 8 > best) ++sbits;
+                constexpr uint32_t part = sizeof(K) == 8 ? 2u * BigMergeSm<HV>::CAP / 3u : SPLIT_PART;
+                sbits = min(32 - __clz((sg.size - 1) / part), SPLIT_MAX);
+                if (sizeof(K) == 4) {
+                    const int best = (bits - SPLIT_MAX + 7) / 8;
+                    while (sbits < SPLIT_MAX && (bits - sbits + 7) / 8 > best) ++sbits;
+                }
             }
             const int shift = bits - sbits;
             const uint32_t nparts = 1u << sbits;
