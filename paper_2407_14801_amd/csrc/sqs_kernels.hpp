@@ -399,7 +399,7 @@ static_assert(sizeof(ColSm<true, true>) <= 160 * 1024, "fits one CU's LDS");
 // a barrier.  Positions len .. (a multiple of IPT) are padding, set here to
 // the largest key: being last, they stay behind equal real keys.
 template <bool HV, int IPT>
-__device__ void lds_merge_sort(uint64_t *K, uint32_t *V, uint32_t len)
+__device__ __forceinline__ void lds_merge_sort(uint64_t *K, uint32_t *V, uint32_t len)
 {
     const uint32_t t = threadIdx.x;
     const uint32_t nact = (len + IPT - 1) / IPT;         // threads that hold keys
@@ -481,6 +481,43 @@ __device__ void lds_merge_sort(uint64_t *K, uint32_t *V, uint32_t len)
             }
         }
         __syncthreads();
+    }
+}
+
+// A segment of 64-bit keys (and values) sorted by the LDS merge sort: loaded
+// into LDS (k, v) from `from`, sorted, stored to `to`; size <= NT * IPT.
+template <bool HV, int IPT, int NT>
+__device__ __forceinline__ void merge_segment(const uint64_t *from, const uint32_t *vfrom, uint64_t *to, uint32_t *vto,
+                              uint32_t size, uint64_t *k, uint32_t *v)
+{
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));                      // positions recomputed here, not kept live
+    uint64_t mk[IPT];
+    uint32_t mv[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = (uint32_t)r * NT + tid;
+        mk[r] = p < size ? from[p] : 0ull;
+        if (HV) mv[r] = p < size ? vfrom[p] : 0u;
+    }
+    wait_vmem();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = (uint32_t)r * NT + tid;
+        if (p < size) {
+            k[p] = mk[r];
+            if (HV) v[p] = mv[r];
+        }
+    }
+    __syncthreads();
+    lds_merge_sort<HV, IPT>(k, v, size);
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = (uint32_t)r * NT + tid;
+        if (p < size) {
+            to[p] = k[p];
+            if (HV) vto[p] = v[p];
+        }
     }
 }
 
@@ -1715,8 +1752,9 @@ __global__ __launch_bounds__(CL_NT) void k_classify(Batch<K> b, uint32_t cutoff)
     }
 }
 
-// Single-value buckets: copy A -> D (one work-group per piece of at most
-// COPY_CH keys, persistent).
+// Single-value buckets: A -> D (one work-group per piece of at most COPY_CH
+// keys, persistent); the keys are written from the piece's first key, the
+// values copied.
 template <class K, bool HV>
 __global__ __launch_bounds__(CP_NT) void k_bucket_copy(Batch<K> b, const K *A, const uint32_t *VA, K *D, uint32_t *VD)
 {
@@ -1725,19 +1763,24 @@ __global__ __launch_bounds__(CP_NT) void k_bucket_copy(Batch<K> b, const K *A, c
     for (uint32_t it = blockIdx.x; it < cnt; it += gridDim.x) {
         const BucketItem e = b.list[CLS_COPY][it];
         const uint64_t base = b.nodes[e.node].off + e.lo;
+        if (e.size == 0) continue;
+        // every key of the piece is the bucket's one value: it is read once,
+        // only the values are copied
+        const K key = A[base];
         for (uint32_t p0 = 0; p0 < e.size; p0 += CP_NT * U) {
-            K x[U];
             uint32_t y[U];
+            if (HV) {
 #pragma unroll
-            for (uint32_t u = 0; u < U; ++u) {
-                const uint32_t p = p0 + u * CP_NT + threadIdx.x;
-                if (p < e.size) { x[u] = A[base + p]; if (HV) y[u] = VA[base + p]; }
+                for (uint32_t u = 0; u < U; ++u) {
+                    const uint32_t p = p0 + u * CP_NT + threadIdx.x;
+                    if (p < e.size) y[u] = VA[base + p];
+                }
+                wait_vmem();
             }
-            wait_vmem();
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 const uint32_t p = p0 + u * CP_NT + threadIdx.x;
-                if (p < e.size) { D[base + p] = x[u]; if (HV) VD[base + p] = y[u]; }
+                if (p < e.size) { D[base + p] = key; if (HV) VD[base + p] = y[u]; }
             }
         }
     }
@@ -1830,21 +1873,53 @@ __global__ __launch_bounds__(1024) void k_order_lists(Batch<K> b, uint32_t shift
 // Buckets of one LDS sort: one work-group of NW waves per bucket
 // (persistent), of class CLS (mid4: 4 waves, up to M4_CAP keys, several
 // work-groups per CU; mid: 16 waves, up to SORT_CAP keys).
+// 64-bit keys in the 16-wave class: buckets up to the merge capacity by the
+// LDS merge sort (its arrays over the radix sort's LDS), larger ones by radix
+// passes.
+template <class K, bool HV, int NW> struct MidSmem {
+    static constexpr bool MG = false;
+    SortSmem<NW, SORT_IPT> sort;
+};
+template <bool HV> struct MidSmem<uint64_t, HV, SORT_NW> {
+    static constexpr bool MG = true;
+    union {
+        SortSm sort;
+        MergeSm<HV> mg;
+    };
+};
+
 template <class K, bool HV, int NW, int CLS>
 __global__ __launch_bounds__(NW * WAVE, 4) void k_bucket_mid(Batch<K> b, const K *A, const uint32_t *VA,
                                                           K *D, uint32_t *VD)
 {
-    __shared__ SortSmem<NW, SORT_IPT> sm;
+    __shared__ MidSmem<K, HV, NW> msm;
+    SortSmem<NW, SORT_IPT> &sm = msm.sort;
     __shared__ uint32_t take_sh;
     const uint32_t cnt = min(b.ctr[CLS], b.cap[CLS]);
     uint32_t it = take_item(b.ctr, CLS, &take_sh);
     if (it >= cnt) return;                           // no item left: skip the table clear
     tables_clear<NW, 256>(sm.s.tab);
     __syncthreads();
+    bool dirty = false;                              // a merge sort has used the tables' LDS
     for (; it < cnt; it = take_item(b.ctr, CLS, &take_sh)) {
         const Span<K> e = b.ord[CLS] ? b.ord[CLS][it] : b.span[CLS][it];
         const uint64_t base = e.base;
         const K blo = e.lo, bhi = e.hi;
+        if constexpr (MidSmem<K, HV, NW>::MG) {
+            if (e.size <= (uint32_t)MergeCap<HV>::CAP) {
+                merge_segment<HV, MergeCap<HV>::IPT, NW * WAVE>(A + base, HV ? VA + base : nullptr, D + base,
+                                                               HV ? VD + base : nullptr, e.size, msm.mg.k,
+                                                               msm.mg.v);
+                dirty = true;
+                __syncthreads();
+                continue;
+            }
+            if (dirty) {
+                tables_clear<NW, 256>(sm.s.tab);
+                __syncthreads();
+                dirty = false;
+            }
+        }
         K kk[SORT_IPT];
         uint32_t vv[SORT_IPT];
         const int R = block_rows<NW, SORT_IPT>(e.size);
@@ -1960,40 +2035,12 @@ __device__ __noinline__ void big_leaf_radix64(const uint64_t *from, const uint32
     }
 }
 
+// (not inlined either: the split's registers stay apart from the sort's)
 template <bool HV>
-__device__ void big_leaf_merge(const uint64_t *from, const uint32_t *vfrom, uint64_t *to, uint32_t *vto,
-                               uint32_t size, BigMergeSm<HV> &mg)
+__device__ __noinline__ void big_leaf_merge(const uint64_t *from, const uint32_t *vfrom, uint64_t *to, uint32_t *vto,
+                                            uint32_t size, BigMergeSm<HV> &mg)
 {
-    constexpr int IPT = BigMergeSm<HV>::IPT;
-    uint32_t tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));                      // positions recomputed here, not kept live
-    uint64_t mk[IPT];
-    uint32_t mv[IPT];
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t p = (uint32_t)r * BK_NT + tid;
-        mk[r] = p < size ? from[p] : 0ull;
-        if (HV) mv[r] = p < size ? vfrom[p] : 0u;
-    }
-    wait_vmem();
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t p = (uint32_t)r * BK_NT + tid;
-        if (p < size) {
-            mg.k[p] = mk[r];
-            if (HV) mg.v[p] = mv[r];
-        }
-    }
-    __syncthreads();
-    lds_merge_sort<HV, IPT>(mg.k, mg.v, size);
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-        const uint32_t p = (uint32_t)r * BK_NT + tid;
-        if (p < size) {
-            to[p] = mg.k[p];
-            if (HV) vto[p] = mg.v[p];
-        }
-    }
+    merge_segment<HV, BigMergeSm<HV>::IPT, BK_NT>(from, vfrom, to, vto, size, mg.k, mg.v);
 }
 
 template <class K, bool HV>
