@@ -2035,6 +2035,24 @@ __device__ __noinline__ void big_leaf_radix64(const uint64_t *from, const uint32
     }
 }
 
+// Part statistics of one 64-key row for at most 2^SPLIT_MAX parts, from
+// SPLIT_MAX ballots of the part bits (valid lanes only): `mine` = the valid
+// lanes whose part equals this lane's part d, `lanes_j` = the valid lanes of
+// part j = this lane's index (meaningful for lanes below 2^SPLIT_MAX).
+__device__ inline void part_masks(bool ok, uint32_t d, unsigned long long &mine, unsigned long long &lanes_j)
+{
+    const uint32_t l = lane_id();
+    unsigned long long me = __ballot(ok), mj = me;
+#pragma unroll
+    for (int k = 0; k < SPLIT_MAX; ++k) {
+        const unsigned long long bk = __ballot(ok && ((d >> k) & 1u));
+        me &= ((d >> k) & 1u) ? bk : ~bk;
+        mj &= ((l >> k) & 1u) ? bk : ~bk;
+    }
+    mine = me;
+    lanes_j = mj;
+}
+
 // (not inlined either: the split's registers stay apart from the sort's)
 template <bool HV>
 __device__ __noinline__ void big_leaf_merge(const uint64_t *from, const uint32_t *vfrom, uint64_t *to, uint32_t *vto,
@@ -2156,7 +2174,11 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
             if (tid < BK_NW * (1 << SPLIT_MAX)) (&whist[0][0])[tid] = 0;
             __syncthreads();
             {                                                            // count, per-wave histograms
+                // 64-bit keys: lane j < 2^SPLIT_MAX counts the wave's keys of
+                // part j by row ballots (the LDS atomics of 32-bit keys
+                // collide on few parts for the duplicate-heavy key sets)
                 uint32_t *wh = whist[wave_id()];
+                uint32_t wc = 0u;
                 for (uint32_t p0 = 0; p0 < sg.size; p0 += BK_CAP) {    // a chunk's loads in flight together
                     K x[BK_IPT];
 #pragma unroll
@@ -2165,10 +2187,19 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                         x[r] = p < sg.size ? src[sb + p] : klo;
                     }
 #pragma unroll
-                    for (int r = 0; r < BK_IPT; ++r)
-                        if (p0 + r * BK_NT + tid < sg.size)
-                            atomicAdd(&wh[min((uint32_t)(((K)(x[r] - klo)) >> shift), nparts - 1)], 1u);
+                    for (int r = 0; r < BK_IPT; ++r) {
+                        const bool ok = p0 + r * BK_NT + tid < sg.size;
+                        const uint32_t d = min((uint32_t)(((K)(x[r] - klo)) >> shift), nparts - 1);
+                        if constexpr (sizeof(K) == 8) {
+                            unsigned long long mine, lj;
+                            part_masks(ok, d, mine, lj);
+                            wc += (uint32_t)__popcll(lj);
+                        } else if (ok) {
+                            atomicAdd(&wh[d], 1u);
+                        }
+                    }
                 }
+                if (sizeof(K) == 8 && lane_id() < (1u << SPLIT_MAX)) wh[lane_id()] = wc;
             }
             __syncthreads();
             if (tid < nparts) {
@@ -2235,12 +2266,13 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                     __syncthreads();
                 }
             } else {
-                tables_clear<BK_NW, 256>(sm.s.tab);
-                __syncthreads();
-                for (uint32_t c0 = 0; c0 < sg.size; c0 += BK_CAP) {       // stable scatter, chunk by chunk
+                // stable scatter, chunk by chunk: a key's place among the
+                // chunk's keys of its part comes from the wave's row ballots
+                // (rows and lanes in input order) and the waves' counts
+                for (uint32_t c0 = 0; c0 < sg.size; c0 += BK_CAP) {
                     const uint32_t chN = min((uint32_t)BK_CAP, sg.size - c0);
                     const int nrows = wave_rows<BK_IPT>(chN);
-                    RankTab<256> &tab = sm.s.tab[wave_id()];
+                    const uint32_t w = wave_id(), l = lane_id();
                     K kk[BK_IPT];
                     uint32_t vv[BK_IPT], pos[BK_IPT];
 #pragma unroll
@@ -2250,52 +2282,64 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                         if (HV) vv[r] = r < nrows && p < chN ? vsrc[sb + c0 + p] : 0u;
                     }
                     wait_vmem();
+                    auto part = [&](K x) { return min((uint32_t)(((K)(x - klo)) >> shift), nparts - 1); };
+                    uint32_t wc = 0u;                    // lane j: the wave's keys of part j in earlier rows
 #pragma unroll
                     for (int r = 0; r < BK_IPT; ++r) {
                         if (r < nrows) {
-                            const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
-                            const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
-                            pos[r] = rank_row(tab, d);
+                            const bool ok = item_pos<BK_NW, BK_IPT>(r) < chN;
+                            const uint32_t d = part(kk[r]);
+                            unsigned long long mine, lj;
+                            part_masks(ok, d, mine, lj);
+                            pos[r] = __shfl(wc, (int)d, WAVE) + rank_in_mask((uint32_t)mine, (uint32_t)(mine >> 32));
+                            wc += (uint32_t)__popcll(lj);
                         }
                     }
+                    if (l < (1u << SPLIT_MAX)) whist[w][l] = wc;
                     __syncthreads();
-                    scan_tables<BK_NW, 256>(sm.s.tab, sm.wsum);
+                    // lane j: part j's start in the chunk and this wave's first slot of it
+                    uint32_t tot = 0u, pre = 0u;
+                    if (l < (1u << SPLIT_MAX)) {
 #pragma unroll
-                    for (int r = 0; r < BK_IPT; ++r) {
-                        if (r < nrows) {
-                            const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
-                            const uint32_t d = p < chN ? min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1) : 255u;
-                            pos[r] += tab.off[d];
+                        for (int ww = 0; ww < BK_NW; ++ww) {
+                            const uint32_t c = whist[ww][l];
+                            tot += c;
+                            pre += (uint32_t)ww < w ? c : 0u;
                         }
                     }
+                    const uint32_t start = wave_incl_scan(tot) - tot;
+                    if (w == 0 && l < (1u << SPLIT_MAX)) { coff[l] = start; ccnt[l] = tot; }
+                    const uint32_t first = start + pre;
 #pragma unroll
-                    for (int wd = 0; wd < T::WORDS; ++wd) {
+                    for (int r = 0; r < BK_IPT; ++r)
+                        if (r < nrows) pos[r] += __shfl(first, (int)part(kk[r]), WAVE);
+                    // exchange into chunk order by part (valid keys only)
 #pragma unroll
-                        for (int r = 0; r < BK_IPT; ++r)
-                            if (r < nrows) sm.s.buf[pos[r]] = T::word(kk[r], wd);
-                        __syncthreads();
+                    for (int r = 0; r < BK_IPT; ++r)
+                        if (r < nrows && item_pos<BK_NW, BK_IPT>(r) < chN) sm.k64[pos[r]] = (uint64_t)kk[r];
+                    __syncthreads();
 #pragma unroll
-                        for (int r = 0; r < BK_IPT; ++r)
-                            if (r < nrows) kk[r] = T::set_word(kk[r], wd, sm.s.buf[item_pos<BK_NW, BK_IPT>(r)]);
-                        __syncthreads();
-                    }
+                    for (int r = 0; r < BK_IPT; ++r)
+                        if (r < nrows) kk[r] = (K)sm.k64[item_pos<BK_NW, BK_IPT>(r)];
+                    __syncthreads();
                     if (HV) {
 #pragma unroll
-                        for (int r = 0; r < BK_IPT; ++r) if (r < nrows) sm.s.buf[pos[r]] = vv[r];
+                        for (int r = 0; r < BK_IPT; ++r)
+                            if (r < nrows && item_pos<BK_NW, BK_IPT>(r) < chN) sm.s.buf[pos[r]] = vv[r];
                         __syncthreads();
 #pragma unroll
                         for (int r = 0; r < BK_IPT; ++r) if (r < nrows) vv[r] = sm.s.buf[item_pos<BK_NW, BK_IPT>(r)];
                         __syncthreads();
                     }
-                    // element at chunk position p has digit d (recomputed from its key);
+                    // element at chunk position p has part d (recomputed from its key);
                     // it goes to base[d] + run[d] + (p - start of d in this chunk)
 #pragma unroll
                     for (int r = 0; r < BK_IPT; ++r) {
                         if (r < nrows) {
                             const uint32_t p = item_pos<BK_NW, BK_IPT>(r);
                             if (p < chN) {
-                                const uint32_t d = min((uint32_t)(((K)(kk[r] - klo)) >> shift), nparts - 1);
-                                const uint32_t at = base[d] + run[d] + (p - sm.s.tab[0].off[d]);
+                                const uint32_t d = part(kk[r]);
+                                const uint32_t at = base[d] + run[d] + (p - coff[d]);
                                 if (at < sg.size) {                                  // guard: inside the segment
                                     dstb[sb + at] = kk[r];
                                     if (HV) vdstb[sb + at] = vv[r];
@@ -2304,11 +2348,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
                         }
                     }
                     __syncthreads();
-                    if (tid < nparts) {
-                        const uint32_t st0 = sm.s.tab[0].off[tid];
-                        const uint32_t en = tid + 1 < 256 ? sm.s.tab[0].off[tid + 1] : chN;
-                        run[tid] += min(en, chN) - min(st0, chN);
-                    }
+                    if (tid < nparts) run[tid] += ccnt[tid];
                     __syncthreads();
                 }
             }
