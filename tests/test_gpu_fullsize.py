@@ -113,3 +113,27 @@ def test_kv_mixture_full_size(b, ws):
     assert np.array_equal(gk, wk)
     assert np.array_equal(gv, wv)
     assert gdg == wdg
+
+
+@pytest.mark.parametrize("m", [13312, 13313])
+def test_kv_merge_column_capacity(b, ws, m):
+    """Key/value roots whose columns are exactly the merge column sort's
+    capacity (13312 pairs) and one more (taken by the radix column kernel):
+    the output is the stable sort (checked on the device against torch's
+    stable sort of the keys in unsigned order)."""
+    n = m * m
+    _say(f"kv merge column capacity m={m} n={n}")
+    g = torch.Generator(device=DEV)
+    g.manual_seed(m)
+    k = torch.randint(-(1 << 63), (1 << 63) - 1, (n,), dtype=torch.int64, device=DEV, generator=g)
+    k[: n // 3] = k[: n // 3] & 0xFFFF                 # a third of the keys in 2^16 values
+    v = torch.arange(n, dtype=torch.int32, device=DEV)
+    ki, vi = k.clone(), v.clone()
+    ko, vo = torch.empty_like(k), torch.empty_like(v)
+    b.squaresort_kv(ki, vi, ko, vo, seed=5, cutoff=0, ws=ws)
+    flip = torch.tensor(-(1 << 63), dtype=torch.int64, device=DEV)
+    ws_sorted, order = torch.sort(k ^ flip, stable=True)
+    assert torch.equal(ko, ws_sorted ^ flip)
+    assert torch.equal(vo, v[order])
+    del ki, vi, ko, vo, ws_sorted, order
+    torch.cuda.synchronize()

@@ -384,6 +384,43 @@ def test_kv_largest_keys_stable(b, ws, n):
     assert dg == wdg
 
 
+def _clusters(size, seed):
+    """16 clusters of `size` keys, cluster c in [c * 2^60, c * 2^60 + 2^20):
+    the first split of a base case (top bits of x - min) gives 16 parts of
+    `size` keys each, so the leaves have exactly that size."""
+    g = np.random.default_rng(seed)
+    k = (np.repeat(np.arange(16, dtype=np.uint64), size) << np.uint64(60)) + \
+        g.integers(0, 1 << 20, size=16 * size).astype(np.uint64)
+    return k[g.permutation(k.size)]
+
+
+@pytest.mark.parametrize("size", [5000, 5632, 5633, 7000, 8100])
+def test_kv_split_leaves_around_merge_capacity(b, ws, size):
+    """Key/value leaves of the MSD split on both sides of the merge
+    sort's capacity (5632 pairs; larger leaves take radix passes): stable
+    order and the oracle's digest."""
+    _say(f"kv split leaves size={size}")
+    k = _clusters(size, seed=size)
+    v = np.arange(k.size, dtype=np.uint32)
+    ko, vo, dg, used = gpu_kv(b, ws, k, v, seed=2, cutoff=0, digest=True)
+    order = np.argsort(k, kind="stable")
+    assert np.array_equal(ko, k[order]) and np.array_equal(vo, v[order])
+    _, _, wdg, _ = oracle.squaresort_kv(k, v, 2, used, want_digest=True)
+    assert dg == wdg
+
+
+@pytest.mark.parametrize("size", [7680, 7681, 8100])
+def test_u64_split_leaves_around_merge_capacity(b, ws, size):
+    """64-bit keys without values: leaves on both sides of the merge
+    capacity (7680 keys)."""
+    _say(f"u64 split leaves size={size}")
+    x = _clusters(size, seed=size + 1)
+    got, dg, used = gpu_u64(b, ws, x, seed=3, cutoff=0, digest=True)
+    assert np.array_equal(got, np.sort(x))
+    _, wdg, _ = oracle.squaresort_u64(x, 3, used, want_digest=True)
+    assert dg == wdg
+
+
 def test_kv_presorted_stable(b, ws):
     n = 3_000_017
     _say(f"kv presorted n={n}")
