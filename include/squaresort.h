@@ -108,8 +108,8 @@ enum {
  *                     wave: 1024 >> v keys; larger ones go to the 4-wave
  *                     work-group kernel;
  *   SQS_TILE_M4CAP(v) largest bucket sorted by one 4-wave work-group:
- *                     4096 >> v keys; larger ones
- *                     go to the 16-wave kernel (up to 16384 keys). */
+ *                     4096 >> v keys; larger ones go to the 16-wave kernel
+ *                     (up to 16384 keys). */
 #define SQS_TILE_COLW(v)  ((uint32_t)(v) & 3u)
 #define SQS_TILE_WCAP(v)  (((uint32_t)(v) & 3u) << 2)
 #define SQS_TILE_M4CAP(v) (((uint32_t)(v) & 3u) << 4)

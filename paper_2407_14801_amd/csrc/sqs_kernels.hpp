@@ -2175,8 +2175,9 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
             __syncthreads();
             {                                                            // count, per-wave histograms
                 // 64-bit keys: lane j < 2^SPLIT_MAX counts the wave's keys of
-                // part j by row ballots (the LDS atomics of 32-bit keys
-                // collide on few parts for the duplicate-heavy key sets)
+                // part j by row ballots (LDS atomics collide when few parts
+                // take most keys, as in duplicate-heavy key sets); 32-bit keys
+                // keep the atomics, cheaper when they do not collide
                 uint32_t *wh = whist[wave_id()];
                 uint32_t wc = 0u;
                 for (uint32_t p0 = 0; p0 < sg.size; p0 += BK_CAP) {    // a chunk's loads in flight together
