@@ -2495,6 +2495,160 @@ struct SnShared {
     uint32_t sp_sh, bigbase_sh;
 };
 
+// A node of at most WN_CAP keys (m <= 16) processed by one wave, for
+// cut-offs of at most 64 (every base-case bucket then fits the wave's bitonic
+// segments): the steps of small_subtree with wave-level synchronisation only.
+// wb: the wave's LDS scratch (WN_CAP + 16 words).  Buckets above the cut-off
+// are pushed on the work-group's stack (slots from an LDS atomic).
+constexpr uint32_t WN_CAP = 256;
+__device__ __noinline__ void wave_node(SnShared &sh, uint64_t root_off, SnFrame fr, uint32_t *A, uint32_t *D,
+                                 uint32_t cutoff, unsigned long long *digest, uint32_t *wb)
+{
+    constexpr int WR4 = WN_CAP / WAVE;
+    const uint32_t l = lane_id();
+    const uint64_t off = root_off + fr.off;
+    const uint32_t n = fr.n;
+    const uint64_t K = fr.key;
+    uint32_t m = 1;
+    while (m * m < n) ++m;                              // ceil(sqrt n) <= 16
+    const uint32_t npiv = m - 1;
+    uint32_t *wp = wb + WN_CAP;                         // the sorted pivots
+    // pivots: draw t by lane t, ranked among the draws by shuffles
+    const uint32_t x = l < npiv ? A[off + pivot_draw(K, l, n)] : 0xFFFFFFFFu;
+    uint32_t rk = 0;
+    for (uint32_t u = 0; u < npiv; ++u) {
+        const uint32_t y = __shfl(x, (int)u, WAVE);
+        rk += (y < x || (y == x && u < l)) ? 1u : 0u;
+    }
+    // columns: 64 / S at a time in segments of S >= m lanes, bitonic
+    const uint32_t S = seg_of(m), per = WAVE / S;
+    for (uint32_t ib = 0; ib < m; ib += per) {
+        const uint32_t i = ib + l / S, e = l % S;
+        const uint32_t c0 = i * m, len = (i < m && c0 < n) ? min(m, n - c0) : 0u;
+        uint32_t y = e < len ? A[off + c0 + e] : 0xFFFFFFFFu;
+        y = seg_bitonic_rt(y, S);
+        if (e < len) wb[c0 + e] = y;
+    }
+    if (l < npiv) wp[rk] = x;
+    wave_lds_sync();
+    // lane j: pivot j and its strict flag (a run of equal pivots: all but the last)
+    const uint32_t pj = l < npiv ? wp[l] : 0u;
+    const uint32_t sj = l + 1 < npiv && wp[l] == wp[l + 1] ? 1u : 0u;
+    uint32_t kk[WR4], dg[WR4], pos[WR4];
+#pragma unroll
+    for (int r = 0; r < WR4; ++r) {
+        const uint32_t p = (uint32_t)r * WAVE + l;
+        kk[r] = p < n ? wb[p] : 0u;                     // D, column-major
+        // bucket: the first pivot the key lies at or below (four fixed
+        // halving steps over at most 15 pivots, every lane in every step,
+        // so that the shuffles read active lanes only)
+        uint32_t lo = 0;
+#pragma unroll
+        for (uint32_t stp = 8; stp >= 1; stp >>= 1) {
+            const uint32_t t = lo + stp - 1;
+            const uint32_t pm = __shfl(pj, (int)min(t, 15u), WAVE), st = __shfl(sj, (int)min(t, 15u), WAVE);
+            if (t < npiv && !le_pivot(kk[r], pm, st != 0u)) lo += stp;
+        }
+        dg[r] = lo;
+    }
+    // SkewTranspose: a stable pass by bucket (at most 16), ranks from row ballots
+    uint32_t wc = 0u;                                   // lane j: keys of bucket j in earlier rows
+#pragma unroll
+    for (int r = 0; r < WR4; ++r) {
+        const bool ok = (uint32_t)r * WAVE + l < n;
+        unsigned long long me = __ballot(ok), mj = me;
+#pragma unroll
+        for (int bit = 0; bit < 4; ++bit) {
+            const unsigned long long bk = __ballot(ok && ((dg[r] >> bit) & 1u));
+            me &= ((dg[r] >> bit) & 1u) ? bk : ~bk;
+            mj &= ((l >> bit) & 1u) ? bk : ~bk;
+        }
+        pos[r] = __shfl(wc, (int)dg[r], WAVE) + rank_in_mask((uint32_t)me, (uint32_t)(me >> 32));
+        wc += (uint32_t)__popcll(mj);
+    }
+    const uint32_t bst = wave_incl_scan(l < m ? wc : 0u) - (l < m ? wc : 0u);   // lane j: bucket j's start
+    const uint32_t nj = l < m ? wc : 0u;
+    unsigned long long h = 0;
+    wave_lds_sync();                                    // the columns are read
+#pragma unroll
+    for (int r = 0; r < WR4; ++r) {
+        const uint32_t first = __shfl(bst, (int)dg[r], WAVE);      // every lane (a shuffle reads active lanes only)
+        if ((uint32_t)r * WAVE + l < n) {
+            const uint32_t q = pos[r] + first;
+            wb[q] = kk[r];
+            A[off + q] = kk[r];                         // A' for the child nodes
+            if (digest) h += splitmix((uint64_t)kk[r] ^ splitmix((uint64_t)q));
+        }
+    }
+    if (digest) {
+        h = wave_sum_u64(h);
+        if (l == 0) atomicAdd(digest, (unsigned long long)splitmix(K ^ h));
+    }
+    wave_lds_sync();
+    // buckets (lane j): single value, base case (at most the cut-off <= 64
+    // keys) or a child node
+    enum : uint32_t { W_SORT = 0, W_COPY = 1, W_NODE = 2, W_EMPTY = 3 };
+    uint32_t c = W_EMPTY;
+    const uint32_t pl = __shfl(pj, (int)(l > 0 ? l - 1 : 0), WAVE);   // every lane: the previous pivot
+    const uint32_t slo = __shfl(sj, (int)(l > 0 ? l - 1 : 0), WAVE);
+    if (l < m && nj > 0) {
+        const uint64_t L = l == 0 ? 0ull : (slo ? (uint64_t)pl : (uint64_t)pl + 1);
+        const int64_t U = l == npiv ? (int64_t)0xFFFFFFFFu : (sj ? (int64_t)pj - 1 : (int64_t)pj);
+        if ((int64_t)L == U) c = W_COPY;
+        else if (nj > cutoff) c = W_NODE;
+        else c = W_SORT;
+    }
+    if (c == W_NODE) {
+        const uint32_t slot = atomicAdd(&sh.sp_sh, 1u);
+        sh.stack[slot] = SnFrame{(uint16_t)(fr.off + bst), (uint16_t)nj, 0u, node_child_key(K, 1, l)};
+    }
+    // base-case buckets, four consecutive ones at a time (segments of 16
+    // lanes when they all fit, else pairs in segments of 32, else singly)
+    for (uint32_t jb = 0; jb < m; jb += 4) {
+        uint32_t sz[4], b0s[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t j = jb + q;
+            const uint32_t cq = __shfl(c, (int)min(j, 63u), WAVE);
+            const uint32_t nq = __shfl(nj, (int)min(j, 63u), WAVE);
+            sz[q] = j < m && cq == W_SORT ? nq : 0u;
+            b0s[q] = __shfl(bst, (int)min(j, 63u), WAVE);
+        }
+        const uint32_t mx4 = max(max(sz[0], sz[1]), max(sz[2], sz[3]));
+        const uint32_t mxa = max(sz[0], sz[1]), mxb = max(sz[2], sz[3]);
+        uint32_t jobs = 0, njobs = 0;
+        auto add = [&](uint32_t dj, uint32_t g, uint32_t Sg) {
+            jobs |= (dj | (g << 2) | ((uint32_t)__builtin_ctz(Sg) << 5)) << (8 * njobs);
+            ++njobs;
+        };
+        if (mx4 == 0) {
+        } else if (mx4 <= 16) {
+            add(0, 4, 16);
+        } else {
+            if (mxa > 0) { if (mxa <= 32) add(0, 2, 32); else { add(0, 1, 64); add(1, 1, 64); } }
+            if (mxb > 0) { if (mxb <= 32) add(2, 2, 32); else { add(2, 1, 64); add(3, 1, 64); } }
+        }
+        for (uint32_t t = 0; t < njobs; ++t) {
+            const uint32_t jd = (jobs >> (8 * t)) & 255u;
+            const uint32_t dj = jd & 3u, g = (jd >> 2) & 7u, Sg = 1u << (jd >> 5);
+            const uint32_t q = l / Sg, e = l % Sg;
+            uint32_t b0 = 0u, len = 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if ((uint32_t)u == dj + q && q < g) { b0 = b0s[u]; len = sz[u]; }
+            uint32_t y = e < len ? wb[b0 + e] : 0xFFFFFFFFu;
+            y = seg_bitonic_rt(y, Sg);
+            if (e < len) D[off + b0 + e] = y;
+        }
+    }
+    // single-value buckets: copied
+    for (uint32_t j = 0; j < m; ++j) {
+        if (__shfl(c, (int)j, WAVE) != W_COPY) continue;
+        const uint32_t b0 = __shfl(bst, (int)j, WAVE), len = __shfl(nj, (int)j, WAVE);
+        for (uint32_t e = l; e < len; e += WAVE) D[off + b0 + e] = wb[b0 + e];
+    }
+}
+
 // The whole subtree of one on-chip node (the caller has cleared sh.sm's
 // tables once; they are clear again on return).  Ends with a barrier.
 __device__ __forceinline__ void small_subtree(SnShared &sh, const SmallNode root, uint32_t *A, uint32_t *D, uint32_t cutoff,
@@ -2518,6 +2672,18 @@ __device__ __forceinline__ void small_subtree(SnShared &sh, const SmallNode root
             const uint32_t sp = sp_sh;
             if (sp == 0) break;
             const SnFrame fr = stack[sp - 1];
+            if (cutoff <= (uint32_t)WAVE && fr.n <= WN_CAP) {
+                // up to SN_NW small nodes from the top of the stack, one per wave
+                uint32_t nw = 1;
+                while (nw < (uint32_t)SN_NW && nw < sp && stack[sp - 1 - nw].n <= WN_CAP) ++nw;
+                const SnFrame mine = stack[sp - 1 - min(w, nw - 1)];
+                __syncthreads();                        // every frame read before any push
+                if (tid == 0) sp_sh = sp - nw;
+                __syncthreads();
+                if (w < nw) wave_node(sh, root.off, mine, A, D, cutoff, digest, sm.s.buf + w * (WN_CAP + 16));
+                __syncthreads();
+                continue;
+            }
             __syncthreads();
             if (tid == 0) { sp_sh = sp - 1; bigbase_sh = 0u; }
             const uint64_t off = root.off + fr.off;
@@ -2690,7 +2856,7 @@ __device__ __forceinline__ void small_subtree(SnShared &sh, const SmallNode root
     __syncthreads();                                    // every thread has seen the empty stack
 }
 
-__global__ __launch_bounds__(SN_NT) void k_small_nodes(const SmallNode *roots, uint32_t count, uint32_t *A,
+__global__ __launch_bounds__(SN_NT, 3) void k_small_nodes(const SmallNode *roots, uint32_t count, uint32_t *A,
                                                         uint32_t *D, uint32_t cutoff,
                                                         unsigned long long *digest)
 {
@@ -2707,7 +2873,7 @@ constexpr uint32_t ST_DEVICE = 2u;       // a device failure word (bounded wait,
 // The internal buckets of a batch (its CLS_INTERNAL list) sorted on chip,
 // each with its subtree, when they are on-chip nodes; any other one is
 // reported as ST_UNFINISHED.  Used where the host does not read the list.
-__global__ __launch_bounds__(SN_NT) void k_internal_nodes(Batch<uint32_t> b, uint32_t *A, uint32_t *D,
+__global__ __launch_bounds__(SN_NT, 3) void k_internal_nodes(Batch<uint32_t> b, uint32_t *A, uint32_t *D,
                                                            uint32_t cutoff, unsigned long long *digest,
                                                            uint32_t *status)
 {
