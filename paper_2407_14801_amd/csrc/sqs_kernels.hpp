@@ -2418,6 +2418,25 @@ struct SnFrame {
     unsigned long long key;
 };
 
+// the value of lane l ^ j (j a power of two, a constant once unrolled):
+// DPP lane moves inside rows of 16 lanes (j = 1, 2: quad permutations; 4: a
+// half-row mirror then a quad reversal; 8: a row rotation by 8), a swizzle
+// inside 32 lanes for 16, a lane permutation through LDS hardware for 32
+__device__ inline uint32_t lane_xor(uint32_t x, int j)
+{
+    switch (j) {
+    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);    // quad_perm 1,0,3,2
+    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);    // quad_perm 2,3,0,1
+    case 4: {
+        const int t = __builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false);          // row_half_mirror
+        return (uint32_t)__builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, false);             // quad_perm 3,2,1,0
+    }
+    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);   // row_ror 8
+    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);               // lane ^ 16 in 32
+    default: return __shfl_xor(x, j, WAVE);
+    }
+}
+
 // ascending bitonic sort of one key per lane within every aligned segment of
 // S lanes of a wave (S a power of two, 2 <= S <= 64): the partners of every
 // step lie in the same segment, and the last merge runs ascending in all
@@ -2428,7 +2447,7 @@ template <int S> __device__ inline uint32_t seg_bitonic(uint32_t x)
     for (int k = 2; k <= S; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint32_t y = __shfl_xor(x, j, WAVE);
+            const uint32_t y = lane_xor(x, j);
             const bool up = k == S || (l & (uint32_t)k) == 0;
             const bool keep_min = ((l & (uint32_t)j) == 0) == up;
             x = keep_min ? min(x, y) : max(x, y);
@@ -2502,8 +2521,10 @@ struct SnShared {
 // are pushed on the work-group's stack (slots from an LDS atomic).
 constexpr uint32_t WN_CAP = 256;
 __device__ __noinline__ void wave_node(SnShared &sh, uint64_t root_off, SnFrame fr, uint32_t *A, uint32_t *D,
-                                 uint32_t cutoff, unsigned long long *digest, uint32_t *wb)
+                                 uint32_t cutoff, unsigned long long *digest, uint32_t *wbg)
 {
+    // the scratch is LDS: addressed as such (a called function sees a generic pointer)
+    __attribute__((address_space(3))) uint32_t *wb = (__attribute__((address_space(3))) uint32_t *)wbg;
     constexpr int WR4 = WN_CAP / WAVE;
     const uint32_t l = lane_id();
     const uint64_t off = root_off + fr.off;
@@ -2512,20 +2533,34 @@ __device__ __noinline__ void wave_node(SnShared &sh, uint64_t root_off, SnFrame 
     uint32_t m = 1;
     while (m * m < n) ++m;                              // ceil(sqrt n) <= 16
     const uint32_t npiv = m - 1;
-    uint32_t *wp = wb + WN_CAP;                         // the sorted pivots
+    __attribute__((address_space(3))) uint32_t *wp = wb + WN_CAP;   // the sorted pivots
+    {                                                   // the node into LDS: one round trip
+        uint32_t v[WR4];
+#pragma unroll
+        for (int r = 0; r < WR4; ++r) {
+            const uint32_t p = (uint32_t)r * WAVE + l;
+            v[r] = p < n ? A[off + p] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < WR4; ++r) {
+            const uint32_t p = (uint32_t)r * WAVE + l;
+            if (p < n) wb[p] = v[r];
+        }
+        wave_lds_sync();
+    }
     // pivots: draw t by lane t, ranked among the draws by shuffles
-    const uint32_t x = l < npiv ? A[off + pivot_draw(K, l, n)] : 0xFFFFFFFFu;
+    const uint32_t x = l < npiv ? wb[pivot_draw(K, l, n)] : 0xFFFFFFFFu;
     uint32_t rk = 0;
     for (uint32_t u = 0; u < npiv; ++u) {
-        const uint32_t y = __shfl(x, (int)u, WAVE);
+        const uint32_t y = (uint32_t)__builtin_amdgcn_readlane((int)x, (int)u);   // u: the same in every lane
         rk += (y < x || (y == x && u < l)) ? 1u : 0u;
     }
-    // columns: 64 / S at a time in segments of S >= m lanes, bitonic
+    // columns, in place: 64 / S at a time in segments of S >= m lanes, bitonic
     const uint32_t S = seg_of(m), per = WAVE / S;
     for (uint32_t ib = 0; ib < m; ib += per) {
         const uint32_t i = ib + l / S, e = l % S;
         const uint32_t c0 = i * m, len = (i < m && c0 < n) ? min(m, n - c0) : 0u;
-        uint32_t y = e < len ? A[off + c0 + e] : 0xFFFFFFFFu;
+        uint32_t y = e < len ? wb[c0 + e] : 0xFFFFFFFFu;
         y = seg_bitonic_rt(y, S);
         if (e < len) wb[c0 + e] = y;
     }
@@ -2589,8 +2624,9 @@ __device__ __noinline__ void wave_node(SnShared &sh, uint64_t root_off, SnFrame 
     // keys) or a child node
     enum : uint32_t { W_SORT = 0, W_COPY = 1, W_NODE = 2, W_EMPTY = 3 };
     uint32_t c = W_EMPTY;
-    const uint32_t pl = __shfl(pj, (int)(l > 0 ? l - 1 : 0), WAVE);   // every lane: the previous pivot
-    const uint32_t slo = __shfl(sj, (int)(l > 0 ? l - 1 : 0), WAVE);
+    // every lane: the previous lane's pivot and flag (lane 0's are not used)
+    const uint32_t pl = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)pj, 0x138, 0xF, 0xF, false);   // wave_shr 1
+    const uint32_t slo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sj, 0x138, 0xF, 0xF, false);
     if (l < m && nj > 0) {
         const uint64_t L = l == 0 ? 0ull : (slo ? (uint64_t)pl : (uint64_t)pl + 1);
         const int64_t U = l == npiv ? (int64_t)0xFFFFFFFFu : (sj ? (int64_t)pj - 1 : (int64_t)pj);
@@ -2609,10 +2645,10 @@ __device__ __noinline__ void wave_node(SnShared &sh, uint64_t root_off, SnFrame 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t j = jb + q;
-            const uint32_t cq = __shfl(c, (int)min(j, 63u), WAVE);
-            const uint32_t nq = __shfl(nj, (int)min(j, 63u), WAVE);
+            const uint32_t cq = (uint32_t)__builtin_amdgcn_readlane((int)c, (int)min(j, 63u));
+            const uint32_t nq = (uint32_t)__builtin_amdgcn_readlane((int)nj, (int)min(j, 63u));
             sz[q] = j < m && cq == W_SORT ? nq : 0u;
-            b0s[q] = __shfl(bst, (int)min(j, 63u), WAVE);
+            b0s[q] = (uint32_t)__builtin_amdgcn_readlane((int)bst, (int)min(j, 63u));
         }
         const uint32_t mx4 = max(max(sz[0], sz[1]), max(sz[2], sz[3]));
         const uint32_t mxa = max(sz[0], sz[1]), mxb = max(sz[2], sz[3]);
@@ -2643,8 +2679,9 @@ __device__ __noinline__ void wave_node(SnShared &sh, uint64_t root_off, SnFrame 
     }
     // single-value buckets: copied
     for (uint32_t j = 0; j < m; ++j) {
-        if (__shfl(c, (int)j, WAVE) != W_COPY) continue;
-        const uint32_t b0 = __shfl(bst, (int)j, WAVE), len = __shfl(nj, (int)j, WAVE);
+        if ((uint32_t)__builtin_amdgcn_readlane((int)c, (int)j) != W_COPY) continue;
+        const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)bst, (int)j);
+        const uint32_t len = (uint32_t)__builtin_amdgcn_readlane((int)nj, (int)j);
         for (uint32_t e = l; e < len; e += WAVE) D[off + b0 + e] = wb[b0 + e];
     }
 }
@@ -2694,16 +2731,32 @@ __device__ __forceinline__ void small_subtree(SnShared &sh, const SmallNode root
             const uint32_t npiv = m - 1;
             const int R = block_rows<SN_NW, SN_IPT>(n);
             const int nrows = wave_rows_of(n, R);
-            // ---- pivots: m-1 draws from the node input (A, not yet overwritten)
-            if (tid < npiv) piv[tid] = A[off + pivot_draw(K, tid, n)];
-            // ---- columns (m <= 64 keys each): 64 / S columns per wave at a
-            // time, each in a segment of S >= m lanes, bitonic
+            // ---- the node into LDS in one round trip (every load in flight together)
+            {
+                uint32_t v[SN_IPT];
+#pragma unroll
+                for (int r = 0; r < SN_IPT; ++r) {
+                    const uint32_t p = (uint32_t)r * SN_NT + tid;
+                    v[r] = p < n ? A[off + p] : 0u;
+                }
+#pragma unroll
+                for (int r = 0; r < SN_IPT; ++r) {
+                    const uint32_t p = (uint32_t)r * SN_NT + tid;
+                    if (p < n) sm.s.buf[p] = v[r];
+                }
+            }
+            __syncthreads();
+            // ---- pivots: m-1 draws from the node input
+            if (tid < npiv) piv[tid] = sm.s.buf[pivot_draw(K, tid, n)];
+            __syncthreads();
+            // ---- columns (m <= 64 keys each), in place: 64 / S columns per
+            // wave at a time, each in a segment of S >= m lanes, bitonic
             {
                 const uint32_t S = seg_of(m), per = WAVE / S;
                 for (uint32_t ib = w * per; ib < m; ib += SN_NW * per) {
                     const uint32_t i = ib + l / S, e = l % S;
                     const uint32_t c0 = i * m, len = (i < m && c0 < n) ? min(m, n - c0) : 0u;
-                    uint32_t x = e < len ? A[off + c0 + e] : 0xFFFFFFFFu;
+                    uint32_t x = e < len ? sm.s.buf[c0 + e] : 0xFFFFFFFFu;
                     x = seg_bitonic_rt(x, S);
                     if (e < len) sm.s.buf[c0 + e] = x;
                 }
