@@ -2418,25 +2418,6 @@ struct SnFrame {
     unsigned long long key;
 };
 
-// the value of lane l ^ j (j a power of two, a constant once unrolled):
-// DPP lane moves inside rows of 16 lanes (j = 1, 2: quad permutations; 4: a
-// half-row mirror then a quad reversal; 8: a row rotation by 8), a swizzle
-// inside 32 lanes for 16, a lane permutation through LDS hardware for 32
-__device__ inline uint32_t lane_xor(uint32_t x, int j)
-{
-    switch (j) {
-    case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);    // quad_perm 1,0,3,2
-    case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, false);    // quad_perm 2,3,0,1
-    case 4: {
-        const int t = __builtin_amdgcn_mov_dpp((int)x, 0x141, 0xF, 0xF, false);          // row_half_mirror
-        return (uint32_t)__builtin_amdgcn_mov_dpp(t, 0x1B, 0xF, 0xF, false);             // quad_perm 3,2,1,0
-    }
-    case 8: return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, false);   // row_ror 8
-    case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F);               // lane ^ 16 in 32
-    default: return __shfl_xor(x, j, WAVE);
-    }
-}
-
 // ascending bitonic sort of one key per lane within every aligned segment of
 // S lanes of a wave (S a power of two, 2 <= S <= 64): the partners of every
 // step lie in the same segment, and the last merge runs ascending in all
