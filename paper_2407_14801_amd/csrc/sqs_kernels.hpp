@@ -97,12 +97,22 @@ constexpr int CTR_BIG_FAIL = 3 * NCLS + 4;
 // bucket of the SkewTranspose output holds a key outside its bounds
 constexpr int CTR_PRE_FAIL = 3 * NCLS + 5;
 constexpr int CTR_CHECK_FAIL = 3 * NCLS + 6;
-constexpr int CTR_WORDS = 3 * NCLS + 7;
+// the wide-bucket kernel (k_bucket_wide): its take counter over the MSD-split
+// list (from the end), the keys it sorted, and the buckets it may take
+constexpr int CTR_WIDE_TAKE = 3 * NCLS + 7;
+constexpr int CTR_WIDE_KEYS = 3 * NCLS + 8;
+constexpr int CTR_WIDE_ELIG = 3 * NCLS + 9;
+constexpr int CTR_WORDS = 3 * NCLS + 10;
 // sample attempts of the Alg. 1 pivot rule before a node gives up
 constexpr uint32_t ALG1_ATTEMPTS = 64;
 constexpr uint32_t COPY_CH = 32768;           // keys per piece of a single-value bucket copy
 constexpr uint32_t CP_NT = 1024;              // threads of a copy work-group
 constexpr uint32_t BIG_CAP = 16 * SORT_CAP;  // largest automatic cut-off: 262144 keys
+// buckets of 32-bit keys without values above SORT_CAP and up to WIDE_CAP
+// keys, with a key range of at least WIDE_RANGE values, are sorted whole in
+// LDS (k_bucket_wide)
+constexpr uint32_t WIDE_CAP = 28672;
+constexpr uint32_t WIDE_RANGE = 16;
 
 // A base-case sort item, resolved: its first slot in A and D, its size and
 // the inclusive key bounds of its bucket (one load gives a sort kernel all
@@ -1725,6 +1735,10 @@ __global__ __launch_bounds__(CL_NT) void k_classify(Batch<K> b, uint32_t cutoff)
         if (mask[c] && l == 0) o = atomicAdd(&wgCnt[c], (uint32_t)__popcll(mask[c]));
         woff[c] = __shfl(o, 0, WAVE);
     }
+    // buckets the wide-bucket kernel may take (counted for every key type)
+    const unsigned long long wide = __ballot(cls == CLS_BIG && it.size <= WIDE_CAP &&
+                                             (uint64_t)(K)(bhi - blo) >= (uint64_t)WIDE_RANGE);
+    if (wide && l == 0) atomicAdd(&b.ctr[CTR_WIDE_ELIG], (uint32_t)__popcll(wide));
     __syncthreads();
     if (threadIdx.x < NCLS) {
         const uint32_t c = threadIdx.x;
@@ -2061,6 +2075,167 @@ __device__ __noinline__ void big_leaf_merge(const uint64_t *from, const uint32_t
     merge_segment<HV, BigMergeSm<HV>::IPT, BK_NT>(from, vfrom, to, vto, size, mg.k, mg.v);
 }
 
+// Buckets of 32-bit keys without values from one LDS sort up to WIDE_CAP keys
+// (base cases, taken from the small end of the MSD-split list before the
+// MSD-split kernel runs): the whole bucket sits in LDS (the CU's 160 KB) and
+// one bin sort of WBINS bins orders it, so every key is read and written
+// once, where the split reads it three times and writes it twice.  The bins
+// cut the bucket's key range [lo, hi] into WBINS intervals by a fixed-point
+// multiply (bin = (x - lo) * mul / 2^32, non-decreasing in x; for a range of
+// fewer than WBINS values, one bin per value, which needs no sort): about 2
+// to 3.5 keys a bin for uniform keys.  Every key takes its slot in its bin
+// from an LDS atomic add, the bins are laid out by a scan, and every bin of
+// at most BIN_NET keys is sorted in place by a sorting network.  A bucket with
+// a bin of more keys (clustered keys), or with a key range of fewer than
+// WIDE_RANGE values, is left untouched to the MSD-split kernel; a sorted one
+// has the size of its list entry set to zero, which that kernel skips.  Items are claimed from the end of the list, which is
+// ordered largest first, until one exceeds WIDE_CAP.
+static_assert(WIDE_RANGE == 1u << SPLIT_MAX, "one MSD split pass separates a smaller range's values");
+constexpr int WIDE_IPT = (int)WIDE_CAP / SORT_NT;     // 28 keys per thread
+constexpr int WBINS = 8192;
+constexpr int WBPT = WBINS / SORT_NT;                 // 8 bins per thread
+static_assert(WIDE_IPT * SORT_NT == (int)WIDE_CAP && WBPT * SORT_NT == WBINS, "whole rows and bins per thread");
+struct WideSmem {
+    uint32_t buf[WIDE_CAP + BIN_NET];   // the keys, then all-ones words under the networks' last reads
+    uint32_t st[WBINS + 1];             // bin counts, then bin starts (st[WBINS] = size)
+    uint32_t wsum[SORT_NW];
+    uint32_t wflag[SORT_NW];
+    uint2 bl[SORT_NW][64];              // per wave: bins of 9 .. BIN_NET keys (start, size)
+};
+
+__global__ __launch_bounds__(SORT_NT, 1) void k_bucket_wide(Batch<uint32_t> b, const uint32_t *A, uint32_t *D)
+{
+    __shared__ WideSmem sm;
+    __shared__ uint32_t take_sh;
+    const uint32_t tid = threadIdx.x, w = wave_id(), l = lane_id();
+    const uint32_t cnt = min(b.ctr[CLS_BIG], b.cap[CLS_BIG]);
+    Span<uint32_t> *list = b.ord[CLS_BIG];
+    if (b.ctr[CTR_WIDE_ELIG] == 0) return;           // no bucket to take (say, few key values)
+    while (true) {
+        if (tid == 0) take_sh = atomicAdd(&b.ctr[CTR_WIDE_TAKE], 1u);
+        __syncthreads();
+        const uint32_t k = take_sh;
+        __syncthreads();
+        if (k >= cnt) break;
+        const uint32_t it = cnt - 1u - k;
+        const Span<uint32_t> e = list[it];
+        if (e.size > WIDE_CAP) break;                 // every later claim is at least as large
+        // a range of fewer values: one pass of the MSD split separates the
+        // values without sorting (the bins' atomic adds would collide on a
+        // few words)
+        if (e.size == 0 || e.hi - e.lo < WIDE_RANGE) continue;
+        const uint64_t base = e.base;
+        const uint32_t size = e.size, lo = e.lo, range = e.hi - e.lo;
+        const bool one = range < (uint32_t)WBINS;     // one key value per bin
+        const uint32_t mul = one ? 0u : (uint32_t)(((uint64_t)WBINS << 32) / ((uint64_t)range + 1u));
+        auto bin = [&](uint32_t x) { return one ? x - lo : __umulhi(x - lo, mul); };
+#pragma unroll
+        for (int q = 0; q < WBPT; ++q) sm.st[q * SORT_NT + tid] = 0u;
+        uint32_t x[WIDE_IPT], rk[WIDE_IPT];
+#pragma unroll
+        for (int r = 0; r < WIDE_IPT; ++r) {          // the loads first, in flight together
+            const uint32_t p = (uint32_t)r * SORT_NT + tid;
+            x[r] = p < size ? A[base + p] : 0u;
+        }
+        wait_vmem();
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < WIDE_IPT; ++r)
+            if ((uint32_t)r * SORT_NT + tid < size) rk[r] = atomicAdd(&sm.st[bin(x[r])], 1u);
+        __syncthreads();
+        // bins WBPT*t .. WBPT*t + WBPT - 1: counts, crowding, exclusive starts
+        uint32_t c[WBPT], tot = 0u;
+        bool crowded = false;
+#pragma unroll
+        for (int q = 0; q < WBPT; ++q) {
+            c[q] = sm.st[WBPT * tid + q];
+            tot += c[q];
+            crowded |= c[q] > (uint32_t)BIN_NET;
+        }
+        const uint32_t incl = wave_incl_scan(tot);
+        const bool over = !one && __ballot(crowded) != 0ull;
+        if (l == WAVE - 1) { sm.wsum[w] = incl; sm.wflag[w] = over ? 1u : 0u; }
+        __syncthreads();
+        uint32_t run = incl - tot;
+        bool any = false;
+#pragma unroll
+        for (int ww = 0; ww < SORT_NW; ++ww) {
+            if ((uint32_t)ww < w) run += sm.wsum[ww];
+            any |= sm.wflag[ww] != 0u;
+        }
+        if (any) {                                    // uniform: left to the MSD split
+            __syncthreads();
+            continue;
+        }
+#pragma unroll
+        for (int q = 0; q < WBPT; ++q) { sm.st[WBPT * tid + q] = run; run += c[q]; }
+        if (tid == 0) sm.st[WBINS] = size;
+        if (tid < (uint32_t)BIN_NET) sm.buf[size + tid] = 0xFFFFFFFFu;   // at least every key
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < WIDE_IPT; ++r)
+            if ((uint32_t)r * SORT_NT + tid < size) sm.buf[sm.st[bin(x[r])] + rk[r]] = x[r];
+        __syncthreads();
+        if (!one) {
+            // bins of at most 8 keys by 4- or 8-key networks (as large as the
+            // wave's largest such bin needs), then the wave's larger bins,
+            // listed, one per lane by 16-key networks
+            uint32_t bigit = 0u;
+#pragma unroll 1
+            for (int q = 0; q < WBPT; ++q) {
+                const uint32_t bb = tid + (uint32_t)q * SORT_NT;
+                const uint32_t s = sm.st[bb], cb = sm.st[bb + 1] - s;
+                const bool big = cb > 8u;
+                bigit |= (big ? 1u : 0u) << q;
+                const uint32_t cs = big ? 0u : cb;
+                const uint32_t cm = wave_max(cs);
+                if (cm <= 1u) continue;
+                if (cm <= 4u) bin_net<4>(sm.buf, s, cs);
+                else bin_net<8>(sm.buf, s, cs);
+            }
+            const uint32_t nbig = (uint32_t)__popc(bigit);
+            const uint32_t bincl = wave_incl_scan(nbig);
+            const uint32_t btot = __shfl(bincl, WAVE - 1, WAVE);
+            if (btot > 0u) {
+                if (btot <= 64u) {
+                    uint2 *bl = sm.bl[w];
+                    uint32_t o = bincl - nbig;
+#pragma unroll 1
+                    for (int q = 0; q < WBPT; ++q)
+                        if ((bigit >> q) & 1u) {
+                            const uint32_t bb = tid + (uint32_t)q * SORT_NT;
+                            bl[o++] = make_uint2(sm.st[bb], sm.st[bb + 1] - sm.st[bb]);
+                        }
+                    wave_lds_sync();
+                    if (l < btot) {
+                        const uint2 e2 = bl[l];
+                        bin_net<16>(sm.buf, e2.x, e2.y);
+                    }
+                } else {
+#pragma unroll 1
+                    for (int q = 0; q < WBPT; ++q) {
+                        if (__ballot((bigit >> q) & 1u) == 0ull) continue;
+                        const uint32_t bb = tid + (uint32_t)q * SORT_NT;
+                        const bool big = (bigit >> q) & 1u;
+                        bin_net<16>(sm.buf, big ? sm.st[bb] : 0u, big ? sm.st[bb + 1] - sm.st[bb] : 0u);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < WIDE_IPT; ++r) {
+            const uint32_t p = (uint32_t)r * SORT_NT + tid;
+            if (p < size) D[base + p] = sm.buf[p];
+        }
+        if (tid == 0) {
+            list[it].size = 0u;                       // done: the MSD-split kernel skips it
+            atomicAdd(&b.ctr[CTR_WIDE_KEYS], size);
+        }
+        __syncthreads();
+    }
+}
+
 template <class K, bool HV>
 __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint32_t *VA, K *D, uint32_t *VD)
 {
@@ -2077,6 +2252,7 @@ __global__ __launch_bounds__(BK_NT, 4) void k_bucket_big(Batch<K> b, K *A, uint3
     const uint32_t cnt = min(b.ctr[CLS_BIG], b.cap[CLS_BIG]);
     for (uint32_t it = take_item(b.ctr, CLS_BIG, &take_sh); it < cnt; it = take_item(b.ctr, CLS_BIG, &take_sh)) {
         const Span<K> e = b.ord[CLS_BIG] ? b.ord[CLS_BIG][it] : b.span[CLS_BIG][it];
+        if (e.size == 0) continue;                   // sorted by k_bucket_wide
         const uint64_t bbase = e.base;
         if (tid == 0) {
             stack[0] = BigSeg{0u, e.size, b.bigInD, 0u, (uint64_t)e.lo, (uint64_t)e.hi};

@@ -622,6 +622,12 @@ template <class K, bool HV> struct Engine {
             k_bucket_mid<K, HV, M4_NW, CLS_MID4><<<std::min<uint32_t>(capMid4, 2048), M4_NW * WAVE, 0, st>>>(b, A, VA, D, VD); });
         launch("k_bucket", keysTot, [&] {
             k_bucket_mid<K, HV, SORT_NW, CLS_MID><<<std::min<uint32_t>(capMid, 512), SORT_NT, 0, st>>>(b, A, VA, D, VD); });
+        if constexpr (sizeof(K) == 4 && !HV) {
+            if (cutoff > (uint32_t)SORT_CAP)             // the MSD-split list's smallest buckets, whole in LDS
+                launch("k_bucket_wide", keysTot, [&] {
+                    k_bucket_wide<<<std::min<uint32_t>(capBig, COL_WG_BIG), SORT_NT, 0, st>>>(
+                        b, reinterpret_cast<const uint32_t *>(A), reinterpret_cast<uint32_t *>(D)); });
+        }
         if (cutoff > (uint32_t)SORT_CAP)
             launch("k_bucket_big", keysTot, [&] {
                 k_bucket_big<K, HV><<<std::min<uint32_t>(capBig, 512), BK_NT, 0, st>>>(b, A, VA, D, VD); });
@@ -650,7 +656,8 @@ template <class K, bool HV> struct Engine {
         set_units("k_bucket_w", hctr[2 * NCLS + CLS_SMALL]);
         set_units("k_bucket4", hctr[2 * NCLS + CLS_MID4]);
         set_units("k_bucket", hctr[2 * NCLS + CLS_MID]);
-        set_units("k_bucket_big", hctr[2 * NCLS + CLS_BIG]);
+        set_units("k_bucket_wide", hctr[CTR_WIDE_KEYS]);
+        set_units("k_bucket_big", hctr[2 * NCLS + CLS_BIG] - hctr[CTR_WIDE_KEYS]);
         resolve_timing();
         if (alg1 && hctr[CTR_FAIL]) return SQS_ERR_PRECOND;  // no valid Alg. 1 sample for some node
         if (hctr[CTR_TR_FAIL]) return SQS_ERR_DEVICE;          // a transpose chunk's wait ran out

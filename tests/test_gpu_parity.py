@@ -287,6 +287,52 @@ def test_u32_crowded_bins_large(b, ws):
     assert dg == wdg
 
 
+# Root buckets of 16385 .. 28672 32-bit keys are sorted whole in LDS by one
+# bin sort; one with a crowded bin (more than 16 keys in one bin's width) is
+# left to the MSD split.  The keys the wide-bucket kernel sorted are read from
+# the library's per-kernel unit counts; the eligible buckets come from the
+# oracle's root bucket starts at the same seed.
+WIDE_MIN, WIDE_MAX = 16_384, 28_672
+
+
+@pytest.mark.parametrize("name", ["uniform", "few_spikes", "spiky", "dup16", "dup14"])
+def test_u32_wide_buckets(b, ws, name):
+    n, seed, cutoff = (1 << 25) + 3, 7, 262_144
+    _say(f"u32 wide buckets {name} n={n}")
+    g = np.random.default_rng(21)
+    if name == "spiky":                  # every large bucket crowds a bin: all go to the split
+        x = _crowded(n, "spiky", seed=21)
+    elif name.startswith("dup"):         # 2^16 values of 512 copies, 2^14 of 2048
+        x = g.integers(0, 1 << int(name[3:]), size=n, dtype=np.uint64).astype(np.uint32)
+    else:
+        x = g.integers(0, 2**32, size=n, dtype=np.uint64)
+        if name == "few_spikes":         # 200 values of 64 copies: a few buckets crowd a bin
+            spikes = g.integers(0, 2**32, size=200, dtype=np.uint64)
+            x[g.choice(n, 200 * 64, replace=False)] = np.repeat(spikes, 64)
+        x = x.astype(np.uint32)
+    _, bs = oracle.root_intermediate(x.astype(np.uint64), seed=seed)
+    sz = np.diff(bs.astype(np.int64))
+    eligible = int(sz[(sz > WIDE_MIN) & (sz <= WIDE_MAX)].sum())
+    assert eligible > 0
+    b.timing_enable(True)
+    try:
+        got, used = gpu_u32(b, ws, x, seed=seed, cutoff=cutoff)
+        rep = b.timing_report()
+    finally:
+        b.timing_enable(False)
+    assert used == cutoff
+    assert np.array_equal(got, np.sort(x))
+    wide = rep.get("k_bucket_wide", {}).get("units", 0)
+    if name == "uniform":
+        assert 0.95 * eligible <= wide <= eligible
+    elif name == "few_spikes":
+        assert 0 < wide < eligible
+    elif name == "dup16":                # per value: no bin can crowd
+        assert wide == eligible
+    else:                                # spiky: crowded bins; dup14: ranges of at most 16 values
+        assert wide == 0
+
+
 @pytest.mark.parametrize("name", ["window8", "window16", "spiky"])
 def test_skew_transpose_crowded(b, ws, name):
     n = (1 << 22) + 7
