@@ -161,7 +161,9 @@ def percentiles(values, ps=(50, 99)):
 class GpuExecutor:
     """Sorts a batch of same-kind requests with one batched call on this
     kind's stream: inputs are packed into one buffer, outputs are views of
-    the packed result."""
+    the packed result.  A batch of one request takes the single-instance
+    call instead (the same bytes: an instance of a batch ends exactly as it
+    would alone)."""
 
     def __init__(self, device, cutoff: int = 0):
         import torch
@@ -180,6 +182,19 @@ class GpuExecutor:
             if r.ready is not None:
                 st.wait_event(r.ready)
         with torch.cuda.stream(st):
+            if len(batch) == 1:               # alone: the single-instance call (same bytes, no packing)
+                r = batch[0]
+                if kind == "u32":
+                    src = r.keys.clone()      # the call clobbers its input
+                    r.out_keys = torch.empty_like(src)
+                    b.squaresort_u32(src, r.out_keys, seed=r.seed, cutoff=self.cutoff, ws=self.ws[kind])
+                else:
+                    ks, vs = r.keys.clone(), r.vals.clone()
+                    r.out_keys, r.out_vals = torch.empty_like(ks), torch.empty_like(vs)
+                    b.squaresort_kv(ks, vs, r.out_keys, r.out_vals, seed=r.seed, cutoff=self.cutoff,
+                                    ws=self.ws[kind])
+                st.synchronize()
+                return
             sizes = [r.n for r in batch]
             offs = b.batched_offsets(sizes)
             seeds = np.array([r.seed for r in batch], dtype=np.uint64)
