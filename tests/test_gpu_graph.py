@@ -28,8 +28,12 @@ def _instances(count, lo, hi, seed):
     return sizes, keys
 
 
+# the last case: roots of 2^24..2^25 keys, whose largest buckets (16K..60K
+# keys) go to the wide-bucket and MSD-split kernels, which mark the list
+# entries they sorted; every replay rebuilds the lists on the device
 @pytest.mark.parametrize("count,lo,hi,cutoff", [(300, 1 << 6, 1 << 18, 0), (200, 1 << 8, 1 << 16, 64),
-                                                (32, 1 << 16, 1 << 20, 0), (40, 3, 30, 4), (50, 100, 600, 16)])
+                                                (32, 1 << 16, 1 << 20, 0), (40, 3, 30, 4), (50, 100, 600, 16),
+                                                (2, 1 << 24, 1 << 25, 0)])
 def test_graph_replays_match_eager_and_oracle(b, count, lo, hi, cutoff):
     print(f"graph count={count} sizes=[{lo},{hi}] cutoff={cutoff}", flush=True)
     sizes, keys = _instances(count, lo, hi, seed=count + lo)
