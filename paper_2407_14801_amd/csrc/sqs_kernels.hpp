@@ -450,6 +450,13 @@ __device__ __forceinline__ void lds_merge_sort(uint64_t *K, uint32_t *V, uint32_
         }
     }
     __syncthreads();
+    // Runs of at most 32 * IPT keys pair up inside one wave's 64 * IPT keys
+    // (every wave's first key is a multiple of 2L), so those rounds need
+    // only the wave's own LDS ordering, not a work-group barrier.
+    auto sync = [&](bool local) {
+        if (local) wave_lds_sync();
+        else __syncthreads();
+    };
 #pragma unroll 1
     for (uint32_t L = IPT; L < len; L *= 2) {            // uniform over the work-group
         if (t < nact) {
@@ -482,7 +489,7 @@ __device__ __forceinline__ void lds_merge_sort(uint64_t *K, uint32_t *V, uint32_
                 kb = ta ? kb : kn;
             }
         }
-        __syncthreads();
+        sync(L <= 32u * IPT);
         if (t < nact) {
 #pragma unroll
             for (int s = 0; s < IPT; ++s) {
@@ -490,8 +497,9 @@ __device__ __forceinline__ void lds_merge_sort(uint64_t *K, uint32_t *V, uint32_
                 if (HV) V[pos + s] = v[s];
             }
         }
-        __syncthreads();
+        sync(2 * L <= 32u * IPT && 2 * L < len);        // the next round's pairs
     }
+    __syncthreads();                                     // callers read any position
 }
 
 // A segment of 64-bit keys (and values) sorted by the LDS merge sort: loaded
