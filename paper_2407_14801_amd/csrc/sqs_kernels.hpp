@@ -1263,7 +1263,7 @@ __device__ inline int tile_table(const Batch<K> &b, const NodeDesc &nd, uint32_t
 // publishes its aggregate before it waits: the walk always ends.  Record
 // words pack status and value, and are read and written as device-scope
 // atomics (coherent across the chip's L2 caches).
-constexpr uint32_t TR_HEAVY = 2 * TR_CH;
+constexpr uint32_t TR_HEAVY = 3 * TR_CH;
 constexpr uint32_t TR_EXTRA = 1024;
 constexpr unsigned long long TR_AGG = 1ull << 62, TR_INCL = 2ull << 62;
 constexpr uint32_t TR_SPIN = 1u << 16;       // bound of one wait (tens of ms: far above a chunk's time)

@@ -495,8 +495,8 @@ template <class K, bool HV> struct Engine {
             b.ord[CLS_BIG] = ws.take<Span<K>>(capBig);
         }
         b.ctr = ws.take<uint32_t>(CTR_WORDS);
-        // heavy-tile transpose chunks: a tile above TR_HEAVY = 2 chunks has fewer
-        // than 1.5 * keys / TR_CH chunks, so the sum over tiles is below that
+        // heavy-tile transpose chunks: a tile above TR_HEAVY (three chunks) has
+        // fewer than 1.5 * keys / TR_CH chunks, so the sum over tiles is below that
         b.trCap = (uint32_t)std::min<uint64_t>(0xFFFFFFFFull, 3 * keysTot / (2 * TR_CH) + 1);
         b.trItem = ws.take<uint32_t>(2 * (uint64_t)b.trCap);
         b.trRec = ws.take<unsigned long long>((uint64_t)b.trCap * TB);
