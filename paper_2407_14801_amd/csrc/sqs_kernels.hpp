@@ -45,8 +45,8 @@ constexpr uint32_t M4_CAP = M4_NW * WAVE * SORT_IPT;  // 4096 keys per mid4 sort
 constexpr int TG = 64;                       // columns per column group
 constexpr int TB = 64;                       // buckets per bucket block
 constexpr int TR_NW = 4;                     // waves of the transpose work-group
-constexpr int TR_IPT = 12;                   // keys per thread per chunk
-constexpr int TR_CH = TR_NW * WAVE * TR_IPT; // 3072 keys per transpose chunk
+constexpr int TR_IPT = 10;                   // keys per thread per chunk
+constexpr int TR_CH = TR_NW * WAVE * TR_IPT; // 2560 keys per transpose chunk
 constexpr int CL_NT = 1024;                  // threads of the classify work-group
 
 using SortSm = SortSmem<SORT_NW, SORT_IPT>;
@@ -1473,14 +1473,13 @@ __device__ void transpose_tile(const Batch<K> &b, const K *src, const uint32_t *
 }
 
 // Every tile that is not heavy, whole, by its own work-group.  Registers are
-// held to seven waves per SIMD for 32-bit keys (LDS admits seven work-groups
-// per CU) and six for 64-bit keys; key/value tiles would spill, so stay free.
-// (Chunks of 3072 keys: a tile of the 2^28 root holds 4096 +- 512 keys, so
-// most take two chunks; smaller chunks made half the tiles heavy, larger
-// ones cost occupancy: 2048 keys 2.25 ms, 4096 keys 1.04 ms, 5120 keys
-// 1.14 ms, against 1.02 ms.)
+// held to eight waves per SIMD for 32-bit keys (LDS admits eight work-groups
+// per CU) and seven for 64-bit keys; key/value tiles would spill, so stay free.
+// (Chunks of 2560 keys: a tile of the 2^28 root holds 4096 +- 512 keys, so
+// most take two chunks either way, and smaller chunks raise the occupancy:
+// 4096-key chunks 1.04 ms, 3072 1.02 ms, 2560 0.92 ms; 5120 keys 1.14 ms.)
 template <class K, bool HV>
-__global__ __launch_bounds__(TR_NW * WAVE, HV ? 1 : (sizeof(K) == 4 ? 7 : 6)) void k_transpose(Batch<K> b, const K *src, const uint32_t *vsrc,
+__global__ __launch_bounds__(TR_NW * WAVE, HV ? 1 : (sizeof(K) == 4 ? 8 : 7)) void k_transpose(Batch<K> b, const K *src, const uint32_t *vsrc,
                                                             K *dst, uint32_t *vdst)
 {
     __shared__ TileSmem<K> sm;
