@@ -1180,7 +1180,8 @@ __global__ __launch_bounds__(1024) void k_bucket_start(Batch<K> b, unsigned long
 // s_t + 1 otherwise; thresholds are non-decreasing).  Slot u starts at
 // lo + u*2^sh and holds the number of thresholds at or below its start, so a
 // key's bucket lies between the entries of its slot and the next, and a
-// binary search over the thresholds in between (usually none) finishes it.  The table is built by one atomic add per pivot at the first slot its
+// binary search over the thresholds in between (usually none) finishes it.
+// The table is built by one atomic add per pivot at the first slot its
 // threshold does not exceed, then a scan.  A non-strict pivot equal to the
 // largest key has no threshold: no key passes it and no slot counts it.
 constexpr int TR_LUT_BITS = 9;
@@ -1479,8 +1480,8 @@ __device__ void transpose_tile(const Batch<K> &b, const K *src, const uint32_t *
 // most take two chunks either way, and smaller chunks raise the occupancy:
 // 4096-key chunks 1.04 ms, 3072 1.02 ms, 2560 0.92 ms; 5120 keys 1.14 ms.)
 template <class K, bool HV>
-__global__ __launch_bounds__(TR_NW * WAVE, HV ? 1 : (sizeof(K) == 4 ? 8 : 7)) void k_transpose(Batch<K> b, const K *src, const uint32_t *vsrc,
-                                                            K *dst, uint32_t *vdst)
+__global__ __launch_bounds__(TR_NW * WAVE, HV ? 1 : (sizeof(K) == 4 ? 8 : 7))
+void k_transpose(Batch<K> b, const K *src, const uint32_t *vsrc, K *dst, uint32_t *vdst)
 {
     __shared__ TileSmem<K> sm;
     tables_clear<TR_NW, TB>(sm.tab);
@@ -2099,8 +2100,9 @@ __device__ __noinline__ void big_leaf_merge(const uint64_t *from, const uint32_t
 // at most BIN_NET keys is sorted in place by a sorting network.  A bucket with
 // a bin of more keys (clustered keys), or with a key range of fewer than
 // WIDE_RANGE values, is left untouched to the MSD-split kernel; a sorted one
-// has the size of its list entry set to zero, which that kernel skips.  Items are claimed from the end of the list, which is
-// ordered largest first, until one exceeds WIDE_CAP.
+// has the size of its list entry set to zero, which that kernel skips.  Items
+// are claimed from the end of the list, which is ordered largest first,
+// until one exceeds WIDE_CAP.
 static_assert(WIDE_RANGE == 1u << SPLIT_MAX, "one MSD split pass separates a smaller range's values");
 constexpr int WIDE_IPT = (int)WIDE_CAP / SORT_NT;     // 28 keys per thread
 constexpr int WBINS = 8192;
